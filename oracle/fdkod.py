@@ -1,0 +1,286 @@
+"""FDK-OD in FP64 (Sec. 2.1 and Sec. 2.2 of the paper), test infrastructure only.
+
+Steps, in the paper's order:
+
+1. Split every slice into 4^s squares of side N/2^s (Sec. 2.1).
+2. For every square and angle, evaluate eq. (1) at the four vertices; the
+   minimum and maximum bound the part of each detector row the square uses
+   (Sec. 2.1).  The square's centre trajectory a_c(beta) = a(x_c, y_c, beta) is
+   the column that the shift makes constant (Sec. 2.1, "centers ... on one
+   column").
+3. Crop and shift every row, with linear interpolation (Sec. 2.1).
+4. Angular decimation: low-pass filter plus downsampling, P -> P' (Sec. 2.1).
+5. Backproject the square from the P' decimated angles; the second shift back
+   to detector positions is folded into the sample coordinate (Sec. 2.1 and
+   Sec. 2.2, "only one interpolation").
+
+Readings where the paper is silent (each is listed in the design doc):
+
+* squares: near-equal contiguous blocks, larger first, when 2^s does not
+  divide N; vertices are the four corner voxel centres and (x_c, y_c) their
+  mean;
+* local grid: local column j of square q at angle beta sits at detector index
+  u_j(beta) = a_c(beta) + u0_q + j, an integer offset from the centre
+  trajectory, with u0_q = floor(e_min + c_u) and
+  W_q = floor(e_max + c_u) - u0_q + 2, where e_min / e_max are the extremes of
+  a_min - a_c and a_max - a_c over the decimated angles;
+* decimation filter: a triangle (Bartlett) window of half-width
+  Delta' = 2 pi / P' centred on each decimated angle beta'_m = 2 pi m / P',
+  circular in beta and normalised to unit sum, with D = 2^(s-k) and
+  P' = ceil(P / D) (k = skipped decimation stages, Sec. 2.2).  When D divides
+  P it equals s-k cascaded [1, 2, 1]/4 half-band stages with keep-even;
+* each detector row is decimated on its own (Sec. 2.1, the bounds do not
+  depend on the row).
+
+Pinned by (tests/test_oracle_fdkod.py): s = 0 reproduces direct FDK; D = 1 is
+the identity; triangle weights equal the [1,2,1]/4 cascade; brute-force vertex
+containment of every voxel of every square and every bilinear footprint;
+linearity; interior means and centroids of analytic spheres; the update and
+crop counters of eq. (6) and eq. (7).
+"""
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import fdk as fdk_mod
+from . import geometry as g
+
+
+@dataclass
+class Square:
+    """One of the 4^s squares: voxel index ranges, centre, local column grid."""
+    x0: int
+    x1: int
+    y0: int
+    y1: int
+    xc: float
+    yc: float
+    u0: int = 0
+    width: int = 0
+
+
+def decimation_factor(s, k):
+    """D = 2^(s-k): s decomposition stages with k decimation stages skipped."""
+    if not 0 <= k <= s:
+        raise ValueError("need 0 <= k <= s")
+    return 1 << (s - k)
+
+
+def decimated_count(p, d):
+    """P' = ceil(P / D)."""
+    return -(-p // d)
+
+
+def make_squares(n, s):
+    """The squares of step 1 with their vertex-mean centres (coordinates)."""
+    c = g.centre(n)
+    out = []
+    for (x0, x1, y0, y1) in g.squares(n, s):
+        xc = 0.5 * ((x0 - c) + (x1 - 1 - c))
+        yc = 0.5 * ((y0 - c) + (y1 - 1 - c))
+        out.append(Square(x0, x1, y0, y1, xc, yc))
+    return out
+
+
+def vertices(sq, n):
+    """The four corner voxel centres of a square, as coordinate arrays."""
+    c = g.centre(n)
+    xs = np.array([sq.x0 - c, sq.x1 - 1 - c, sq.x0 - c, sq.x1 - 1 - c])
+    ys = np.array([sq.y0 - c, sq.y0 - c, sq.y1 - 1 - c, sq.y1 - 1 - c])
+    return xs, ys
+
+
+def centre_track(sq, betas, r):
+    """a_c(beta) = eq. (1) at the square's centre."""
+    return g.pix_pos(sq.xc, sq.yc, np.asarray(betas), r)
+
+
+def vertex_bounds(sq, n, betas, r):
+    """a_min(beta), a_max(beta): extremes of eq. (1) over the four vertices."""
+    xs, ys = vertices(sq, n)
+    a = g.pix_pos(xs[:, None], ys[:, None], np.asarray(betas)[None, :], r)
+    return a.min(axis=0), a.max(axis=0)
+
+
+def local_grid(sq, n, betas_dec, r):
+    """Fill sq.u0 and sq.width from the bounds at the decimated angles."""
+    cu = g.centre(n)
+    ac = centre_track(sq, betas_dec, r)
+    amin, amax = vertex_bounds(sq, n, betas_dec, r)
+    e_min = float(np.min(amin - ac))
+    e_max = float(np.max(amax - ac))
+    sq.u0 = int(np.floor(e_min + cu))
+    sq.width = int(np.floor(e_max + cu)) - sq.u0 + 2
+    return sq
+
+
+def plan(n, p, r, s, k):
+    """Squares with their local grids, the original and decimated angles."""
+    d = decimation_factor(s, k)
+    pd = decimated_count(p, d)
+    betas = g.angles(p)
+    betas_dec = g.angles(pd)
+    sqs = [local_grid(sq, n, betas_dec, r) for sq in make_squares(n, s)]
+    return sqs, betas, betas_dec
+
+
+def triangle_weights(p, pd):
+    """w[m, p]: triangle of half-width 2 pi / P' around beta'_m, circular in
+    beta, normalised so every row sums to one (decimation, step 4).
+
+    The distance between beta_p = 2 pi p / P and beta'_m = 2 pi m / P',
+    measured in decimated steps, is |p P' - m P| / P (circularly modulo P'),
+    so the unnormalised weight max(0, 1 - distance) is computed exactly from
+    integers: max(0, P - e) / P with e = circular |p P' - m P|."""
+    pp = np.arange(p, dtype=np.int64)[None, :]
+    mm = np.arange(pd, dtype=np.int64)[:, None]
+    period = p * pd
+    e = np.abs(pp * pd - mm * p) % period
+    e = np.minimum(e, period - e)
+    w = np.maximum(0, p - e).astype(np.float64)
+    return w / w.sum(axis=1, keepdims=True)
+
+
+def cascade121_weights(p, stages):
+    """Decimation by 2^stages built as ``stages`` rounds of circular [1, 2, 1]/4
+    smoothing followed by keeping the even samples (a half-band decimator).
+    Returns the equivalent [P / 2^stages, P] matrix.  Requires 2^stages | P.
+    Used only to pin ``triangle_weights``."""
+    if p % (1 << stages):
+        raise ValueError("cascade needs 2^stages to divide P")
+    mat = np.eye(p)
+    cur = p
+    for _ in range(stages):
+        smooth = np.zeros((cur, cur))
+        for i in range(cur):
+            smooth[i, (i - 1) % cur] += 0.25
+            smooth[i, i] += 0.5
+            smooth[i, (i + 1) % cur] += 0.25
+        keep = smooth[0::2]
+        mat = keep @ mat
+        cur //= 2
+    return mat
+
+
+def crop_shift(frows, sq, betas, r, n):
+    """Step 3: S[p, k, j] = Lin_u(q[p, rows[k], :], a_c(beta_p) + u0 + j), zero
+    outside the detector, for every filtered row k."""
+    ac = centre_track(sq, betas, r)
+    j = np.arange(sq.width, dtype=np.float64)
+    nrow = len(frows.rows)
+    out = np.zeros((len(betas), nrow, sq.width))
+    for p in range(len(betas)):
+        u = ac[p] + sq.u0 + j                          # index coordinates
+        iu = np.floor(u).astype(np.int64)
+        fu = u - iu
+        row = frows.data[p]                            # [nrow, N]
+        for d, w in ((0, 1.0 - fu), (1, fu)):
+            ui = iu + d
+            ok = (ui >= 0) & (ui < n)
+            out[p] += np.where(ok[None, :], w[None, :] * row[:, np.clip(ui, 0, n - 1)], 0.0)
+    return out
+
+
+def decimate(s_sub, weights):
+    """Step 4: Y[m, k, j] = sum_p w[m, p] S[p, k, j]."""
+    return np.tensordot(weights, s_sub, axes=(1, 0))
+
+
+def backproject_square(y_sub, slot, nv, sq, betas_dec, r, n, x, y, z):
+    """Step 5: f = (pi / P') sum_m U^-2 Bil(Y[m], v*, tau), with
+    tau = a - a_c(beta'_m) + c_u - u0 (the folded second shift) and
+    v* = b + c_v.  Rows outside the detector read zero; tau must lie in
+    [0, W-1) by construction of the local grid, which is asserted."""
+    cu = cv = g.centre(n)
+    pd = len(betas_dec)
+    ac = centre_track(sq, betas_dec, r)
+    f = np.zeros(np.broadcast(x, y, z).shape)
+    for m, beta in enumerate(betas_dec):
+        u_mag = g.depth(x, y, beta, r) / r
+        a = g.pix_pos(x, y, beta, r)
+        b = g.row_pos(x, y, z, beta, r)
+        tau = a - ac[m] + cu - sq.u0
+        if tau.size and (tau.min() < 0.0 or tau.max() >= sq.width - 1):
+            raise AssertionError("local column outside the square's grid")
+        f += fdk_mod.bilinear(y_sub[m], slot, nv, b + cv, tau) / (u_mag * u_mag)
+    return (np.pi / pd) * f
+
+
+def _square_points(sq, n, nz, slices):
+    c, cz = g.centre(n), g.centre(nz)
+    zs = np.asarray(slices, dtype=np.float64) - cz
+    ys = np.arange(sq.y0, sq.y1, dtype=np.float64) - c
+    xs = np.arange(sq.x0, sq.x1, dtype=np.float64) - c
+    return np.meshgrid(zs, ys, xs, indexing="ij")
+
+
+def square_pipeline(proj, r, sq, betas, betas_dec, weights, x, y, z,
+                    store=None):
+    """Steps 2-5 for one square at the voxel coordinates (x, y, z) that lie
+    inside it.  ``store`` optionally rounds the filtered rows and the decimated
+    data to a storage type (see oracle.storage)."""
+    n = proj.shape[2]
+    nv = proj.shape[1]
+    rows = fdk_mod.rows_for_points(n, r, betas_dec, x, y, z)
+    frows = fdk_mod.filter_rows(proj, r, rows)
+    if store is not None:
+        frows.data = store(frows.data)
+    s_sub = crop_shift(frows, sq, betas, r, n)
+    y_sub = decimate(s_sub, weights)
+    if store is not None:
+        y_sub = store(y_sub)
+    return backproject_square(y_sub, frows.slot, nv, sq, betas_dec, r, n, x, y, z)
+
+
+def fdkod(proj, r, s, k=0, slices=None, nz=None, store=None):
+    """FDK-OD of the listed slices (all by default).  Returns [S, N, N]."""
+    p_count, nv, n = proj.shape
+    nz = n if nz is None else nz
+    slices = np.arange(nz) if slices is None else np.asarray(slices)
+    sqs, betas, betas_dec = plan(n, p_count, r, s, k)
+    weights = triangle_weights(p_count, len(betas_dec))
+    out = np.zeros((len(slices), n, n))
+    for sq in sqs:
+        z, y, x = _square_points(sq, n, nz, slices)
+        out[:, sq.y0:sq.y1, sq.x0:sq.x1] = square_pipeline(
+            proj, r, sq, betas, betas_dec, weights, x, y, z, store)
+    return out
+
+
+def square_of(n, s, i, j):
+    """Index q of the square that holds voxel column i, row j."""
+    b = g.blocks(n, 2 ** s)
+    bx = next(t for t, (a0, a1) in enumerate(b) if a0 <= i < a1)
+    by = next(t for t, (a0, a1) in enumerate(b) if a0 <= j < a1)
+    return by * (2 ** s) + bx
+
+
+def fdkod_points(proj, r, s, k, idx, nz=None, store=None):
+    """FDK-OD at voxel indices ``idx`` ([K, 3] array of (l, j, i))."""
+    p_count, nv, n = proj.shape
+    nz = n if nz is None else nz
+    idx = np.asarray(idx)
+    sqs, betas, betas_dec = plan(n, p_count, r, s, k)
+    weights = triangle_weights(p_count, len(betas_dec))
+    qid = np.array([square_of(n, s, i, j) for (_, j, i) in idx])
+    out = np.zeros(len(idx))
+    c, cz = g.centre(n), g.centre(nz)
+    for q in np.unique(qid):
+        sel = qid == q
+        x = idx[sel, 2] - c
+        y = idx[sel, 1] - c
+        z = idx[sel, 0] - cz
+        out[sel] = square_pipeline(proj, r, sqs[q], betas, betas_dec, weights,
+                                   x, y, z, store)
+    return out
+
+
+def cost_counts(n, nz, p, r, s, k):
+    """Counters of the two costs of Sec. 2.2: cropped samples of the
+    decomposition (eq. (7): 4^s squares x N rows x W_q columns x P angles) and
+    voxel-angle updates of the reconstruction (eq. (6): N^2 N_z P')."""
+    sqs, betas, betas_dec = plan(n, p, r, s, k)
+    cropped = sum(sq.width for sq in sqs) * p * n
+    updates = n * n * nz * len(betas_dec)
+    return cropped, updates

@@ -1,0 +1,119 @@
+"""Seeded synthetic inputs: random-ellipsoid phantoms and their exact cone-beam
+line integrals.
+
+This module only makes inputs.  It holds none of the reconstruction method's
+arithmetic and is imported by the tests and the benchmark, never by the
+oracle or the GPU library.  The paper measured on a Shepp-Logan-3D phantom
+and on scanner data (Sec. 3); seeded random ellipsoids with closed-form
+projections stand in for both.
+
+Geometry (the same conventions as the reconstruction): voxel units; source at
+-R (cos beta, sin beta, 0); detector point Q(a, b) = a (-sin beta, cos beta, 0)
++ b (0, 0, 1) on a virtual detector through the axis; pixel (u, v) of
+projection p sits at a = u - (N-1)/2, b = v - (N-1)/2, beta_p = 2 pi p / P.
+Ellipsoids are given in normalised units, 1.0 = N/2 voxels, axis aligned, and
+densities add where they overlap.
+"""
+
+from dataclasses import dataclass
+import math
+
+import numpy as np
+import torch
+
+
+@dataclass
+class Ellipsoids:
+    centres: np.ndarray     # [M, 3] normalised (x, y, z)
+    axes: np.ndarray        # [M, 3] normalised semi-axes
+    density: np.ndarray     # [M]
+
+
+def random_ellipsoids(count, seed, centre_range=0.6, axis_range=(0.05, 0.4),
+                      density_range=(-0.5, 1.0)):
+    """``count`` ellipsoids drawn with numpy.random.default_rng(seed); per
+    ellipsoid the draw order is centre (3), semi-axes (3), density (1)."""
+    rng = np.random.default_rng(seed)
+    c = np.zeros((count, 3))
+    a = np.zeros((count, 3))
+    d = np.zeros(count)
+    for e in range(count):
+        c[e] = rng.uniform(-centre_range, centre_range, 3)
+        a[e] = rng.uniform(axis_range[0], axis_range[1], 3)
+        d[e] = rng.uniform(density_range[0], density_range[1])
+    return Ellipsoids(c, a, d)
+
+
+def sphere(centre, radius, density=1.0):
+    """A single sphere (normalised units), for closed-form checks."""
+    return Ellipsoids(np.array([centre], dtype=np.float64),
+                      np.array([[radius] * 3], dtype=np.float64),
+                      np.array([density], dtype=np.float64))
+
+
+def _chords(src, dirn, ell, scale, device):
+    """Sum over ellipsoids of density x chord length (voxel units) of the
+    lines src + t dirn (dirn unit vectors), shapes [..., 3]."""
+    out = torch.zeros(dirn.shape[:-1], dtype=torch.float64, device=device)
+    for e in range(len(ell.density)):
+        c = torch.tensor(ell.centres[e] * scale, dtype=torch.float64, device=device)
+        ax = torch.tensor(ell.axes[e] * scale, dtype=torch.float64, device=device)
+        o = (src - c) / ax
+        dd = dirn / ax
+        a2 = (dd * dd).sum(-1)
+        b = (o * dd).sum(-1)
+        cc = (o * o).sum(-1) - 1.0
+        disc = b * b - a2 * cc
+        chord = 2.0 * torch.sqrt(torch.clamp(disc, min=0.0)) / a2
+        out += float(ell.density[e]) * chord
+    return out
+
+
+def project(ell, n, p, r, device="cpu", out_dtype=torch.float32, angles=None,
+            rows=None):
+    """Exact line integrals [P, N_v, N] of the phantom (voxel-length units).
+
+    ``angles`` / ``rows`` restrict the output to some projections / detector
+    rows (default: all).  Computed in float64, returned in ``out_dtype``."""
+    scale = n / 2.0
+    c = (n - 1) / 2.0
+    angles = np.arange(p) if angles is None else np.asarray(angles)
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    a = torch.arange(n, dtype=torch.float64, device=device) - c
+    b = torch.tensor(rows, dtype=torch.float64, device=device) - c
+    bb, aa = torch.meshgrid(b, a, indexing="ij")
+    out = torch.empty((len(angles), len(rows), n), dtype=out_dtype, device=device)
+    for t, pi in enumerate(angles):
+        beta = 2.0 * math.pi * float(pi) / p
+        cb, sb = math.cos(beta), math.sin(beta)
+        src = torch.tensor([-r * cb, -r * sb, 0.0], dtype=torch.float64, device=device)
+        q = torch.stack([-aa * sb, aa * cb, bb], dim=-1)
+        d = q - src
+        d = d / torch.linalg.norm(d, dim=-1, keepdim=True)
+        out[t] = _chords(src, d, ell, scale, device).to(out_dtype)
+    return out
+
+
+def poisson_noise(proj, n, i0, seed):
+    """Photon-counting noise: lambda = I0 exp(-p / (N/2)), counts ~ Poisson,
+    p_hat = -(N/2) ln(max(counts, 1) / I0).  Seeded torch generator on the
+    tensor's device; returns a tensor of the input's dtype."""
+    gen = torch.Generator(device=proj.device)
+    gen.manual_seed(seed)
+    scale = n / 2.0
+    lam = i0 * torch.exp(-proj.double() / scale)
+    counts = torch.poisson(lam, generator=gen)
+    return (-scale * torch.log(torch.clamp(counts, min=1.0) / i0)).to(proj.dtype)
+
+
+def density(ell, n, nz, x, y, z):
+    """True phantom density at voxel coordinates (x, y, z) (numpy arrays)."""
+    scale = n / 2.0
+    out = np.zeros(np.broadcast(x, y, z).shape)
+    for e in range(len(ell.density)):
+        c = ell.centres[e] * scale
+        ax = ell.axes[e] * scale
+        inside = (((x - c[0]) / ax[0]) ** 2 + ((y - c[1]) / ax[1]) ** 2
+                  + ((z - c[2]) / ax[2]) ** 2) <= 1.0
+        out += ell.density[e] * inside
+    return out
