@@ -1,0 +1,173 @@
+/*
+ * fdkod.h -- C ABI of the FDK-OD cone-beam backprojection library for AMD
+ * MI355X (gfx950).
+ *
+ * FDK-OD ("optimal decomposition", Andriiashen and Kozhevnikov, 2017) splits
+ * every N x N slice into 4^s squares (Sec. 2.1), bounds the part of every
+ * detector row each square uses with eq. (1) evaluated at the square's
+ * vertices (Sec. 2.1), crops and shifts that part so the square's centre
+ * trajectory becomes one column, decimates it in angle from P to P' angles
+ * (low-pass filter + downsampling, Sec. 2.1), and backprojects each square
+ * from the decimated data (Sec. 2.2, eq. (6)-(8)).  The ramp filtering of the
+ * FDK stage it starts from is the "initial convolution" of Sec. 3.
+ *
+ * Geometry and units
+ *   Circular orbit, flat detector.  Units are voxels; the detector is a
+ *   virtual detector through the rotation axis with the voxel pitch.  The
+ *   source sits at distance R from the axis (the R of eq. (1)).  Angle
+ *   beta_p = 2 pi p / P over 360 degrees; source at -R (cos b, sin b, 0).
+ *   Voxel (i, j, l) sits at x = i - (N-1)/2, y = j - (N-1)/2,
+ *   z = l - (N_z-1)/2.  Detector pixel (u, v) sits at a = u - (N-1)/2,
+ *   b = v - (N-1)/2.
+ *
+ * Layouts (all device buffers, contiguous, 256-byte aligned)
+ *   projections  float32 [P][N][N]       (p, v, u), u fastest
+ *   filtered     store type [P][N][N]    same layout (fdkod_filter output)
+ *   workspace    store type, decimated sub-sinograms of every square,
+ *                fdkod_plan_info().workspace_bytes bytes (unused when s = 0)
+ *   volume       float32 [N_z][N][N]     (l, j, i), x fastest
+ *
+ * Ownership and streams
+ *   The caller owns every data buffer.  A plan owns only its small device
+ *   tables.  Every enqueueing call (fdkod_bounds, fdkod_filter,
+ *   fdkod_decompose, fdkod_reconstruct, fdkod_backproject) is asynchronous
+ *   on the given stream, allocates nothing and never synchronises.  Only
+ *   fdkod_plan_create synchronises (once).  A plan is read-only after
+ *   creation; concurrent use on several streams needs separate workspaces.
+ *
+ * Errors
+ *   Every call returns a status; nothing throws across the ABI.  Kernel
+ *   faults are asynchronous and surface at the caller's next synchronisation.
+ *   fdkod_last_error() returns a thread-local text for the last failure.
+ */
+#ifndef FDKOD_H
+#define FDKOD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdkod_plan_s* fdkod_plan_t;  /* opaque */
+typedef void* fdkod_stream_t;               /* a hipStream_t; NULL = null stream */
+
+typedef enum {
+    FDKOD_OK = 0,
+    FDKOD_E_ARG = 1,          /* null pointer, bad size or enum value */
+    FDKOD_E_GEOMETRY = 2,     /* R <= (N-1)/sqrt(2), 2^s > N, skip > s */
+    FDKOD_E_UNSUPPORTED = 3,  /* not a gfx950 device, or sizes beyond the kernels' tiles */
+    FDKOD_E_NOMEM = 4,        /* plan table allocation failed */
+    FDKOD_E_HIP = 5,          /* a HIP runtime call failed (see fdkod_last_error) */
+    FDKOD_E_STATE = 6         /* call not valid for this plan */
+} fdkod_status;
+
+typedef enum { FDKOD_F32 = 0, FDKOD_F16 = 1, FDKOD_BF16 = 2 } fdkod_dtype;
+
+typedef enum { FDKOD_DECIM_TRIANGLE = 0 } fdkod_decim;
+
+/* Problem statement, after Sec. 2.1: N, P, R, s, and the skipped
+ * decimation stages k of Sec. 2.2 (D = 2^(s-k), P' = ceil(P / D)). */
+typedef struct {
+    int32_t n;      /* detector width = height = volume side in x, y; 1..4096 */
+    int32_t nz;     /* volume slices; 0 means n */
+    int32_t p;      /* projections over 360 degrees; 1..65536 */
+    double r;       /* R of eq. (1), voxel units; must exceed (N-1)/sqrt(2) */
+    int32_t s;      /* decomposition stages: 4^s squares; 2^s <= N; s = 0 is direct FDK */
+    int32_t skip;   /* skipped decimation stages k, 0 <= k <= s */
+    int32_t store;  /* fdkod_dtype of the filtered and decimated sinograms */
+    int32_t decim;  /* fdkod_decim */
+} fdkod_params;
+
+/* Sizes and derived quantities of a plan (filled by fdkod_plan_info). */
+typedef struct {
+    int32_t squares;         /* 4^s */
+    int32_t p_dec;           /* P' = ceil(P / D) */
+    int32_t d;               /* D = 2^(s-k) */
+    int32_t fft_len;         /* M, the ramp filter's FFT length (>= 2N-1) */
+    int32_t max_width;       /* max over squares of W_q (local columns) */
+    int32_t z_run;           /* voxels along z per backprojection thread */
+    int64_t filtered_bytes;  /* P*N*N * sizeof(store) */
+    int64_t workspace_bytes; /* sum_q W_q * P' * N * sizeof(store); 0 when s = 0 */
+    int64_t volume_bytes;    /* N_z*N*N*4 */
+    int64_t updates;         /* N*N*N_z*P', voxel-angle updates of one reconstruction */
+} fdkod_info;
+
+/* Validate parameters without touching a device.  Same checks and codes as
+ * fdkod_plan_create's first step. */
+fdkod_status fdkod_validate(const fdkod_params* prm);
+
+/* Create a plan on `device`: validates, builds the angle, decimation and
+ * ramp-filter tables on the host in FP64 (rounded to FP32), runs the bounds
+ * kernel (eq. (1) at the square vertices, Sec. 2.1) and synchronises once to
+ * size the workspace.  *out receives the plan; on failure *out is NULL. */
+fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t* out);
+
+/* Release a plan's device tables.  NULL is accepted. */
+fdkod_status fdkod_plan_destroy(fdkod_plan_t plan);
+
+/* Copy the plan's sizes into *info (host memory). */
+fdkod_status fdkod_plan_info(fdkod_plan_t plan, fdkod_info* info);
+
+/* Re-enqueue the bounds kernel (Sec. 2.1, eq. (1) at the vertices of every
+ * square, for every original and decimated angle).  It rewrites the plan's
+ * device tables with the values fdkod_plan_create computed.  Not thread-safe
+ * against concurrent use of the same plan. */
+fdkod_status fdkod_bounds(fdkod_plan_t plan, fdkod_stream_t stream);
+
+/* Ramp filtering, the initial convolution of Sec. 3 (textbook FDK): cosine
+ * pre-weight R / sqrt(R^2 + a^2 + b^2), then linear convolution of every
+ * detector row with the spatial Ram-Lak kernel (unit spacing, zero outside
+ * the detector), by FFT of length M in FP32.  proj: float32 [P][N][N];
+ * filt: store type [P][N][N].  The buffers must not overlap. */
+fdkod_status fdkod_filter(fdkod_plan_t plan, const float* proj, void* filt,
+                          fdkod_stream_t stream);
+
+/* Decomposition (Sec. 2.1, eq. (7)): for every square q, detector row v,
+ * decimated angle m and local column j,
+ *   Y_q[m][v][j] = sum_p w[m][p] * Lin(filt[p][v][.], a_c(beta_p) + u0_q + j)
+ * with linear interpolation, zero outside the detector, and the triangle
+ * decimation weights w.  Writes the workspace.  No-op when s = 0. */
+fdkod_status fdkod_decompose(fdkod_plan_t plan, const void* filt, void* ws,
+                             fdkod_stream_t stream);
+
+/* Reconstruction (Sec. 2.2, eq. (6)): cone-weighted bilinear backprojection
+ * of every square from its decimated data (s > 0, reads ws) or of the whole
+ * slice from the filtered projections (s = 0, direct FDK, reads filt):
+ *   f = (pi / P') sum_m U^-2 Bil(Y_q[m], v*, tau),  U = depth / R,
+ * tau the local column of eq. (1)'s position, v* = b + (N-1)/2 (eq. (9)).
+ * Overwrites every voxel of vol (float32 [N_z][N][N]). */
+fdkod_status fdkod_reconstruct(fdkod_plan_t plan, const void* filt, const void* ws,
+                               float* vol, fdkod_stream_t stream);
+
+/* fdkod_decompose followed by fdkod_reconstruct on the same stream. */
+fdkod_status fdkod_backproject(fdkod_plan_t plan, const void* filt, float* vol,
+                               void* ws, fdkod_stream_t stream);
+
+/* Copy the bounds tables to host memory (any pointer may be NULL to skip):
+ *   ac_p    float [4^s][P]   a_c(beta_p), centre trajectory at original angles
+ *   ac_m    float [4^s][P']  a_c(beta'_m) at decimated angles
+ *   amin_m  float [4^s][P']  min of eq. (1) over the square's vertices
+ *   amax_m  float [4^s][P']  max of eq. (1) over the square's vertices
+ *   u0      int32 [4^s]      local column origin (detector index offset)
+ *   width   int32 [4^s]      W_q, local columns
+ *   rect    int32 [4^s][4]   x0, x1, y0, y1 voxel index ranges (half-open)
+ * Synchronises with the plan's device. */
+fdkod_status fdkod_get_bounds(fdkod_plan_t plan, float* ac_p, float* ac_m, float* amin_m,
+                              float* amax_m, int32_t* u0, int32_t* width, int32_t* rect);
+
+/* Static text for a status code. */
+const char* fdkod_status_str(fdkod_status st);
+
+/* Thread-local text describing the last failure on this thread ("" if none). */
+const char* fdkod_last_error(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int32_t fdkod_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDKOD_H */

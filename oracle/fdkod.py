@@ -215,22 +215,37 @@ def _square_points(sq, n, nz, slices):
     return np.meshgrid(zs, ys, xs, indexing="ij")
 
 
-def square_pipeline(proj, r, sq, betas, betas_dec, weights, x, y, z,
-                    store=None):
-    """Steps 2-5 for one square at the voxel coordinates (x, y, z) that lie
-    inside it.  ``store`` optionally rounds the filtered rows and the decimated
-    data to a storage type (see oracle.storage)."""
-    n = proj.shape[2]
-    nv = proj.shape[1]
-    rows = fdk_mod.rows_for_points(n, r, betas_dec, x, y, z)
-    frows = fdk_mod.filter_rows(proj, r, rows)
-    if store is not None:
-        frows.data = store(frows.data)
+def square_pipeline(frows, r, sq, betas, betas_dec, weights, x, y, z, store=None):
+    """Steps 3-5 for one square at the voxel coordinates (x, y, z) that lie
+    inside it, from the filtered rows ``frows`` (which must hold every row the
+    points touch).  ``store`` optionally rounds the decimated data to a storage
+    type (see oracle.storage); the filtered rows are rounded by the caller."""
+    n = frows.data.shape[-1]
     s_sub = crop_shift(frows, sq, betas, r, n)
     y_sub = decimate(s_sub, weights)
     if store is not None:
         y_sub = store(y_sub)
-    return backproject_square(y_sub, frows.slot, nv, sq, betas_dec, r, n, x, y, z)
+    return backproject_square(y_sub, frows.slot, frows.nv, sq, betas_dec, r, n, x, y, z)
+
+
+def _filtered(proj, r, betas_dec, pts, store):
+    """Filter (once) every detector row that any of the point sets touches."""
+    n = proj.shape[2]
+    rows = np.unique(np.concatenate(
+        [fdk_mod.rows_for_points(n, r, betas_dec, x, y, z) for (x, y, z) in pts] + [np.zeros(0, np.int64)]))
+    frows = fdk_mod.filter_rows(proj, r, rows)
+    if store is not None:
+        frows.data = store(frows.data)
+    return frows
+
+
+def _rows_subset(frows, x, y, z, betas_dec, r):
+    """Restrict filtered rows to those a square's points touch (keeps the
+    crop of step 3 to the rows that square needs)."""
+    n = frows.data.shape[-1]
+    rows = fdk_mod.rows_for_points(n, r, betas_dec, x, y, z)
+    sub = fdk_mod.FilteredRows(rows, frows.data[:, frows.slot[rows], :], frows.nv)
+    return sub
 
 
 def fdkod(proj, r, s, k=0, slices=None, nz=None, store=None):
@@ -240,11 +255,13 @@ def fdkod(proj, r, s, k=0, slices=None, nz=None, store=None):
     slices = np.arange(nz) if slices is None else np.asarray(slices)
     sqs, betas, betas_dec = plan(n, p_count, r, s, k)
     weights = triangle_weights(p_count, len(betas_dec))
+    pts = [tuple(reversed(_square_points(sq, n, nz, slices))) for sq in sqs]
+    frows = _filtered(proj, r, betas_dec, pts, store)
     out = np.zeros((len(slices), n, n))
-    for sq in sqs:
-        z, y, x = _square_points(sq, n, nz, slices)
+    for sq, (x, y, z) in zip(sqs, pts):
+        sub = _rows_subset(frows, x, y, z, betas_dec, r)
         out[:, sq.y0:sq.y1, sq.x0:sq.x1] = square_pipeline(
-            proj, r, sq, betas, betas_dec, weights, x, y, z, store)
+            sub, r, sq, betas, betas_dec, weights, x, y, z, store)
     return out
 
 
@@ -264,15 +281,16 @@ def fdkod_points(proj, r, s, k, idx, nz=None, store=None):
     sqs, betas, betas_dec = plan(n, p_count, r, s, k)
     weights = triangle_weights(p_count, len(betas_dec))
     qid = np.array([square_of(n, s, i, j) for (_, j, i) in idx])
-    out = np.zeros(len(idx))
     c, cz = g.centre(n), g.centre(nz)
+    groups = []
     for q in np.unique(qid):
         sel = qid == q
-        x = idx[sel, 2] - c
-        y = idx[sel, 1] - c
-        z = idx[sel, 0] - cz
-        out[sel] = square_pipeline(proj, r, sqs[q], betas, betas_dec, weights,
-                                   x, y, z, store)
+        groups.append((q, sel, (idx[sel, 2] - c, idx[sel, 1] - c, idx[sel, 0] - cz)))
+    frows = _filtered(proj, r, betas_dec, [pt for (_, _, pt) in groups], store)
+    out = np.zeros(len(idx))
+    for q, sel, (x, y, z) in groups:
+        sub = _rows_subset(frows, x, y, z, betas_dec, r)
+        out[sel] = square_pipeline(sub, r, sqs[q], betas, betas_dec, weights, x, y, z, store)
     return out
 
 

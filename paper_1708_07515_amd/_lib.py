@@ -1,0 +1,260 @@
+"""ctypes binding of libfdkod.so.  Argument marshalling only.
+
+The library must have been built (``python -m paper_1708_07515_amd.build`` or
+``__graft_entry__.build()``); importing the binding without it raises, there
+is no fallback path.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+STORE_TYPES = {"f32": 0, "f16": 1, "bf16": 2}
+_STORE_BYTES = {0: 4, 1: 2, 2: 2}
+
+FDKOD_OK = 0
+STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_GEOMETRY", 3: "E_UNSUPPORTED", 4: "E_NOMEM",
+                5: "E_HIP", 6: "E_STATE"}
+
+
+class FdkodError(RuntimeError):
+    def __init__(self, status, text):
+        self.status = status
+        self.code = STATUS_NAMES.get(status, str(status))
+        super().__init__(f"fdkod {self.code}: {text}")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nz", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("r", ctypes.c_double), ("s", ctypes.c_int32), ("skip", ctypes.c_int32),
+                ("store", ctypes.c_int32), ("decim", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("squares", ctypes.c_int32), ("p_dec", ctypes.c_int32), ("d", ctypes.c_int32),
+                ("fft_len", ctypes.c_int32), ("max_width", ctypes.c_int32),
+                ("z_run", ctypes.c_int32), ("filtered_bytes", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64), ("volume_bytes", ctypes.c_int64),
+                ("updates", ctypes.c_int64)]
+
+
+EXPORTS = {
+    "fdkod_validate": (ctypes.c_int, [ctypes.POINTER(Params)]),
+    "fdkod_plan_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "fdkod_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "fdkod_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
+    "fdkod_bounds": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "fdkod_filter": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p]),
+    "fdkod_decompose": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
+    "fdkod_reconstruct": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
+    "fdkod_backproject": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
+    "fdkod_get_bounds": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 7),
+    "fdkod_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "fdkod_last_error": (ctypes.c_char_p, []),
+    "fdkod_version": (ctypes.c_int32, []),
+}
+
+
+def library_path():
+    return os.environ.get("FDKOD_LIB", os.path.join(HERE, "libfdkod.so"))
+
+
+def load_library():
+    """Load libfdkod.so and declare its signatures.  Raises if it is missing."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with python -m paper_1708_07515_amd.build")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def _check(status):
+    if status != FDKOD_OK:
+        lib = load_library()
+        raise FdkodError(status, lib.fdkod_last_error().decode())
+
+
+def _params(n, p, r, s=0, skip=0, nz=0, store="f32"):
+    if isinstance(store, str):
+        store = STORE_TYPES[store]
+    return Params(int(n), int(nz), int(p), float(r), int(s), int(skip), int(store), 0)
+
+
+def validate(n, p, r, s=0, skip=0, nz=0, store="f32"):
+    """Host-only parameter check (no device needed)."""
+    prm = _params(n, p, r, s, skip, nz, store)
+    _check(load_library().fdkod_validate(ctypes.byref(prm)))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """An FDK-OD plan: geometry tables on one device, sizes of the buffers."""
+
+    def __init__(self, n, p, r, s=0, skip=0, nz=0, store="f32", device=0):
+        self._lib = load_library()
+        self.params = _params(n, p, r, s, skip, nz, store)
+        self.n, self.p, self.r, self.s, self.skip = int(n), int(p), float(r), int(s), int(skip)
+        self.nz = int(nz) or int(n)
+        self.store = self.params.store
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        _check(self._lib.fdkod_plan_create(ctypes.byref(self.params), self.device, ctypes.byref(h)))
+        self._h = h
+        info = Info()
+        _check(self._lib.fdkod_plan_info(h, ctypes.byref(info)))
+        self.info = info
+
+    # sizes ---------------------------------------------------------------
+    @property
+    def p_dec(self):
+        return self.info.p_dec
+
+    @property
+    def squares(self):
+        return self.info.squares
+
+    @property
+    def workspace_bytes(self):
+        return self.info.workspace_bytes
+
+    @property
+    def filtered_bytes(self):
+        return self.info.filtered_bytes
+
+    @property
+    def updates(self):
+        return self.info.updates
+
+    def store_torch_dtype(self):
+        import torch
+        return {0: torch.float32, 1: torch.float16, 2: torch.bfloat16}[self.store]
+
+    # buffer helpers (allocation happens here, in torch, never in the library)
+    def empty_filtered(self):
+        import torch
+        return torch.empty((self.p, self.n, self.n), dtype=self.store_torch_dtype(),
+                           device=f"cuda:{self.device}")
+
+    def empty_workspace(self):
+        import torch
+        nbytes = max(int(self.workspace_bytes), 256)
+        return torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def empty_volume(self):
+        import torch
+        return torch.empty((self.nz, self.n, self.n), dtype=torch.float32,
+                           device=f"cuda:{self.device}")
+
+    # checks ----------------------------------------------------------------
+    def _chk(self, t, shape, dtype, name):
+        if t is None:
+            raise ValueError(f"{name} is None")
+        if not t.is_cuda or t.device.index != self.device:
+            raise ValueError(f"{name} must live on cuda:{self.device}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        if t.dtype != dtype:
+            raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+
+    def _chk_ws(self, ws):
+        if self.s == 0:
+            return
+        if ws is None or not ws.is_cuda or ws.numel() * ws.element_size() < self.workspace_bytes:
+            raise ValueError(f"workspace must hold {self.workspace_bytes} bytes on the device")
+        if not ws.is_contiguous():
+            raise ValueError("workspace must be contiguous")
+
+    # enqueueing calls ----------------------------------------------------
+    def bounds(self, stream=None):
+        _check(self._lib.fdkod_bounds(self._h, _stream_ptr(stream)))
+
+    def filter(self, proj, filt, stream=None):
+        import torch
+        self._chk(proj, (self.p, self.n, self.n), torch.float32, "proj")
+        self._chk(filt, (self.p, self.n, self.n), self.store_torch_dtype(), "filt")
+        _check(self._lib.fdkod_filter(self._h, ctypes.c_void_p(proj.data_ptr()),
+                                      ctypes.c_void_p(filt.data_ptr()), _stream_ptr(stream)))
+
+    def decompose(self, filt, ws, stream=None):
+        self._chk(filt, (self.p, self.n, self.n), self.store_torch_dtype(), "filt")
+        self._chk_ws(ws)
+        _check(self._lib.fdkod_decompose(self._h, ctypes.c_void_p(filt.data_ptr()),
+                                         ctypes.c_void_p(ws.data_ptr() if ws is not None else 0),
+                                         _stream_ptr(stream)))
+
+    def reconstruct(self, filt, ws, vol, stream=None):
+        import torch
+        self._chk(vol, (self.nz, self.n, self.n), torch.float32, "vol")
+        if self.s == 0:
+            self._chk(filt, (self.p, self.n, self.n), self.store_torch_dtype(), "filt")
+        else:
+            self._chk_ws(ws)
+        _check(self._lib.fdkod_reconstruct(
+            self._h, ctypes.c_void_p(filt.data_ptr() if filt is not None else 0),
+            ctypes.c_void_p(ws.data_ptr() if ws is not None else 0),
+            ctypes.c_void_p(vol.data_ptr()), _stream_ptr(stream)))
+
+    def backproject(self, filt, vol, ws=None, stream=None):
+        import torch
+        self._chk(filt, (self.p, self.n, self.n), self.store_torch_dtype(), "filt")
+        self._chk(vol, (self.nz, self.n, self.n), torch.float32, "vol")
+        self._chk_ws(ws)
+        _check(self._lib.fdkod_backproject(
+            self._h, ctypes.c_void_p(filt.data_ptr()), ctypes.c_void_p(vol.data_ptr()),
+            ctypes.c_void_p(ws.data_ptr() if ws is not None else 0), _stream_ptr(stream)))
+
+    def get_bounds(self):
+        """Bounds tables as numpy arrays (synchronises)."""
+        import numpy as np
+        nsq, p, pd = self.squares, self.p, self.p_dec
+        ac_p = np.zeros((nsq, p), np.float32)
+        ac_m = np.zeros((nsq, pd), np.float32)
+        amin = np.zeros((nsq, pd), np.float32)
+        amax = np.zeros((nsq, pd), np.float32)
+        u0 = np.zeros(nsq, np.int32)
+        width = np.zeros(nsq, np.int32)
+        rect = np.zeros((nsq, 4), np.int32)
+        ptr = lambda a: ctypes.c_void_p(a.ctypes.data)  # noqa: E731
+        _check(self._lib.fdkod_get_bounds(self._h, ptr(ac_p), ptr(ac_m), ptr(amin), ptr(amax),
+                                          ptr(u0), ptr(width), ptr(rect)))
+        return dict(ac_p=ac_p, ac_m=ac_m, amin=amin, amax=amax, u0=u0, width=width, rect=rect)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fdkod_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

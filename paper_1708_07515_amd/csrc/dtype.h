@@ -1,0 +1,43 @@
+// Storage types of the filtered and decimated sinograms: FP32, FP16 and
+// BF16.  Arithmetic is always FP32; these helpers convert on load and store
+// (round to nearest even on store).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdkod {
+
+template <int S> struct Store;
+
+template <> struct Store<0> {
+    using T = float;
+    static __device__ __forceinline__ float load(const T* p, size_t i) { return p[i]; }
+    static __device__ __forceinline__ void put(T* p, size_t i, float v) { p[i] = v; }
+};
+
+template <> struct Store<1> {
+    using T = _Float16;
+    static __device__ __forceinline__ float load(const T* p, size_t i) { return (float)p[i]; }
+    static __device__ __forceinline__ void put(T* p, size_t i, float v) { p[i] = (_Float16)v; }
+};
+
+template <> struct Store<2> {
+    using T = uint16_t;  // bfloat16 bit pattern
+    static __device__ __forceinline__ float load(const T* p, size_t i) {
+        return __uint_as_float(((uint32_t)p[i]) << 16);
+    }
+    static __device__ __forceinline__ void put(T* p, size_t i, float v) {
+        uint32_t b = __float_as_uint(v);
+        if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu)) {
+            p[i] = (uint16_t)((b >> 16) | 0x40u);    // quiet NaN
+            return;
+        }
+        b += 0x7FFFu + ((b >> 16) & 1u);              // round to nearest even
+        p[i] = (uint16_t)(b >> 16);
+    }
+};
+
+inline int store_bytes(int s) { return s == 0 ? 4 : 2; }
+
+}  // namespace fdkod

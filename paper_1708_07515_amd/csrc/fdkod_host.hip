@@ -1,0 +1,580 @@
+// Host side of the C ABI declared in include/fdkod.h: parameter validation,
+// plan tables (built in FP64, stored in FP32), workspace layout, kernel
+// variant choice and launch sequencing.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fdkod.h"
+#include "internal.h"
+#include "dtype.h"
+
+using namespace fdkod;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fdkod_status fail(fdkod_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+fdkod_status hip_fail(hipError_t e, const char* what) {
+    return fail(FDKOD_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                               \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, what);  \
+    } while (0)
+
+int64_t floordiv(int64_t a, int64_t b) {
+    int64_t q = a / b;
+    if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+    return q;
+}
+
+int64_t ceildiv(int64_t a, int64_t b) { return -floordiv(-a, b); }
+
+// Near-equal contiguous blocks of [0, n), larger blocks first.
+std::vector<std::pair<int, int>> blocks(int n, int parts) {
+    std::vector<std::pair<int, int>> out;
+    int base = n / parts, extra = n % parts, start = 0;
+    for (int k = 0; k < parts; ++k) {
+        int size = base + (k < extra ? 1 : 0);
+        out.emplace_back(start, start + size);
+        start += size;
+    }
+    return out;
+}
+
+// Decimation schedule: a single walk over the extended projection index
+// p_ext = lo(0) .. P - 1 that feeds the triangle windows of the decimated
+// angles in order.  Window m holds the p_ext with |p_ext P' - m P| < P and
+// weights (P - |p_ext P' - m P|) / sum; integers keep the support exact.
+std::vector<DecimStep> build_schedule(int P, int pd) {
+    auto lo = [&](int64_t m) { return floordiv(m * P - P, pd) + 1; };
+    auto hi = [&](int64_t m) { return ceildiv(m * P + P, pd) - 1; };
+    auto weight = [&](int64_t m, int64_t pe) { return (int64_t)P - std::llabs(pe * pd - m * P); };
+    std::vector<double> sum(pd, 0.0);
+    for (int m = 0; m < pd; ++m)
+        for (int64_t pe = lo(m); pe <= hi(m); ++pe) sum[m] += (double)weight(m, pe);
+    std::vector<DecimStep> out;
+    int cur = 0;
+    for (int64_t pe = lo(0); pe <= hi(pd - 1); ++pe) {
+        DecimStep st;
+        st.p = (int)(((pe % P) + P) % P);
+        st.w0 = (pe >= lo(cur) && pe <= hi(cur)) ? (float)(weight(cur, pe) / sum[cur]) : 0.0f;
+        st.w1 = (cur + 1 < pd && pe >= lo(cur + 1) && pe <= hi(cur + 1))
+                    ? (float)(weight(cur + 1, pe) / sum[cur + 1]) : 0.0f;
+        st.emit = (pe == hi(cur)) ? 1 : 0;
+        out.push_back(st);
+        if (st.emit) ++cur;
+    }
+    return out;
+}
+
+}  // namespace
+
+struct fdkod_plan_s {
+    fdkod_params prm{};
+    int device = 0;
+    int n = 0, nz = 0, p = 0, s = 0, k = 0, d = 1, pd = 0, nsq = 1, store = 0;
+    int logm = 0;
+    double r = 0;
+    std::vector<SquareDesc> sq;
+    std::vector<int2> grid;
+    // decomposition kernel shape
+    int dec_chunks = 1, dec_tasks_per_sq = 1;
+    // backprojection kernel shape
+    int zrun = 16, tile_w = 32, tile_h = 32, ntiles = 0, nzt = 0;
+    bool bp_ok = false;     // the block footprint fits the largest LDS tile
+    int64_t ws_elems = 0;
+    // device tables
+    SquareDesc* d_sq = nullptr;
+    float2* d_trig_p = nullptr;
+    float2* d_trig_m = nullptr;
+    float* d_ac_p = nullptr;
+    float4* d_geo_m = nullptr;
+    int2* d_grid = nullptr;
+    int2* d_grid_direct = nullptr;
+    DecimStep* d_sched = nullptr;
+    int nsched = 0;
+    float2* d_resp = nullptr;
+    float* d_gtail = nullptr;
+    float2* d_tw = nullptr;
+    BpTile* d_tiles = nullptr;
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+fdkod_status dev_alloc(fdkod_plan_t pl, void** ptr, size_t bytes) {
+    if (std::getenv("FDKOD_FAULT") && std::strcmp(std::getenv("FDKOD_FAULT"), "nomem") == 0)
+        return fail(FDKOD_E_NOMEM, "allocation refused (FDKOD_FAULT=nomem)");
+    hipError_t e = hipMalloc(ptr, bytes ? bytes : 1);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FDKOD_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    pl->allocs.push_back(*ptr);
+    return FDKOD_OK;
+}
+
+template <class T>
+fdkod_status upload(fdkod_plan_t pl, T** dptr, const std::vector<T>& h) {
+    fdkod_status st = dev_alloc(pl, (void**)dptr, h.size() * sizeof(T));
+    if (st != FDKOD_OK) return st;
+    if (!h.empty()) HIP_TRY(hipMemcpy(*dptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice),
+                            "hipMemcpy");
+    return FDKOD_OK;
+}
+
+void release(fdkod_plan_t pl) {
+    if (!pl) return;
+    int prev = 0;
+    if (hipGetDevice(&prev) == hipSuccess) {
+        (void)hipSetDevice(pl->device);
+        for (void* p : pl->allocs) (void)hipFree(p);
+        (void)hipSetDevice(prev);
+    }
+    delete pl;
+}
+
+std::vector<float2> trig_table(int count) {
+    std::vector<float2> t(count);
+    for (int i = 0; i < count; ++i) {
+        double b = 2.0 * M_PI * (double)i / (double)count;
+        t[i] = make_float2((float)std::cos(b), (float)std::sin(b));
+    }
+    return t;
+}
+
+// In-place radix-2 FFT in FP64 (host tables only), sign -1.
+void fft64(std::vector<double>& re, std::vector<double>& im) {
+    const size_t m = re.size();
+    for (size_t i = 1, j = 0; i < m; ++i) {
+        size_t bit = m >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) {
+            std::swap(re[i], re[j]);
+            std::swap(im[i], im[j]);
+        }
+    }
+    for (size_t len = 2; len <= m; len <<= 1) {
+        const double ang = -2.0 * M_PI / (double)len;
+        for (size_t i = 0; i < m; i += len)
+            for (size_t k = 0; k < len / 2; ++k) {
+                const double wr = std::cos(ang * k), wi = std::sin(ang * k);
+                const size_t a = i + k, b = i + k + len / 2;
+                const double xr = re[b] * wr - im[b] * wi, xi = re[b] * wi + im[b] * wr;
+                re[b] = re[a] - xr;
+                im[b] = im[a] - xi;
+                re[a] += xr;
+                im[a] += xi;
+            }
+    }
+}
+
+// Running sum of the Ram-Lak kernel, g[n] = sum_{k <= n} h[k], FP64, for
+// n in [-lim, lim].  With T(m) = sum_{k >= m, k odd} 1/k^2:
+// g[n] = T(n+1)/pi^2 for n >= 0 and g[n] = -T(-n)/pi^2 for n < 0
+// (the kernel sums to zero, h is even, h[0] = 1/4, h[odd k] = -1/(pi^2 k^2)).
+std::vector<double> ramlak_running_sum(int lim) {
+    const int64_t kmax = ((int64_t)1 << 22) + 1;     // odd
+    // tail sum_{j >= 0} 1/(K + 2j)^2 by Euler-Maclaurin, error O(K^-5)
+    const double kk = (double)kmax;
+    double tail = 1.0 / (2.0 * kk) + 1.0 / (2.0 * kk * kk) + 1.0 / (3.0 * kk * kk * kk);
+    std::vector<double> t(lim + 2, 0.0);             // t[m] = T(m), m in [1, lim + 1]
+    double acc = tail;
+    for (int64_t k = kmax - 2; k >= 1; k -= 2) {
+        acc += 1.0 / ((double)k * (double)k);
+        if (k <= lim + 1) t[k] = acc;
+        if (k + 1 <= lim + 1) t[k + 1] = acc - 1.0 / ((double)k * (double)k);
+    }
+    std::vector<double> g(2 * lim + 1);
+    for (int n = -lim; n <= lim; ++n)
+        g[n + lim] = n >= 0 ? t[n + 1] / (M_PI * M_PI) : -t[-n] / (M_PI * M_PI);
+    return g;
+}
+
+// Filter tables: the DFT of the circularly wrapped running-sum kernel g
+// divided by M, the tail g[u - N] for the last difference, and the FFT
+// twiddles exp(-2 pi i k / M).
+void ramp_tables(int n, int m, std::vector<float2>& resp, std::vector<float>& gtail,
+                 std::vector<float2>& tw) {
+    const std::vector<double> g = ramlak_running_sum(m);
+    auto gat = [&](int lag) { return g[lag + m]; };
+    std::vector<double> re(m), im(m, 0.0);
+    for (int t = 0; t < m; ++t) re[t] = gat(t <= m / 2 ? t : t - m);
+    fft64(re, im);
+    resp.resize(m);
+    tw.resize(m);
+    for (int k = 0; k < m; ++k) {
+        resp[k] = make_float2((float)(re[k] / m), (float)(im[k] / m));
+        tw[k] = make_float2((float)std::cos(2.0 * M_PI * k / m), (float)-std::sin(2.0 * M_PI * k / m));
+    }
+    gtail.resize(n);
+    for (int u = 0; u < n; ++u) gtail[u] = (float)gat(u - n);
+}
+
+// Choose the backprojection LDS footprint (TW x TH samples) that holds the
+// footprint of a 16 x 16 x zrun voxel block at any angle, from the slice's
+// smallest depth Dmin = R - (N-1)/sqrt(2).
+bool choose_bp_tiles(int n, int nz, double r, int zrun, int* tw, int* th) {
+    const double c = (n - 1) / 2.0;
+    const double dmin = r - c * std::sqrt(2.0);
+    const double mag = r / dmin;
+    const double lat = c * std::sqrt(2.0) / dmin;
+    const double diag = (kTileXY - 1) * std::sqrt(2.0);
+    const double span_c = diag * mag * std::sqrt(1.0 + lat * lat);
+    const double zmax = (nz - 1) / 2.0;
+    const double span_r = (zrun - 1) * mag + zmax * r * diag / (dmin * dmin);
+    const int need_c = (int)std::ceil(span_c + 1e-6) + 4;
+    const int need_r = (int)std::ceil(span_r + 1e-6) + 4;
+    *tw = need_c <= 32 ? 32 : (need_c <= 64 ? 64 : 0);
+    *th = need_r <= 32 ? 32 : (need_r <= 64 ? 64 : 0);
+    return *tw && *th;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fdkod_status_str(fdkod_status st) {
+    switch (st) {
+        case FDKOD_OK: return "ok";
+        case FDKOD_E_ARG: return "invalid argument";
+        case FDKOD_E_GEOMETRY: return "invalid geometry";
+        case FDKOD_E_UNSUPPORTED: return "unsupported";
+        case FDKOD_E_NOMEM: return "out of memory";
+        case FDKOD_E_HIP: return "HIP runtime error";
+        case FDKOD_E_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+const char* fdkod_last_error(void) { return g_last_error.c_str(); }
+
+int32_t fdkod_version(void) { return 100; }
+
+fdkod_status fdkod_validate(const fdkod_params* prm) {
+    if (!prm) return fail(FDKOD_E_ARG, "params is NULL");
+    const fdkod_params& q = *prm;
+    if (q.n < 2 || q.n > 4096) return fail(FDKOD_E_ARG, "n must be in [2, 4096]");
+    if (q.nz < 0 || q.nz > 65536) return fail(FDKOD_E_ARG, "nz must be in [0, 65536]");
+    if (q.p < 1 || q.p > 65536) return fail(FDKOD_E_ARG, "p must be in [1, 65536]");
+    if (q.store < FDKOD_F32 || q.store > FDKOD_BF16) return fail(FDKOD_E_ARG, "unknown store type");
+    if (q.decim != FDKOD_DECIM_TRIANGLE) return fail(FDKOD_E_ARG, "unknown decimation");
+    if (!std::isfinite(q.r)) return fail(FDKOD_E_GEOMETRY, "R is not finite");
+    if (q.s < 0 || q.s > 12) return fail(FDKOD_E_GEOMETRY, "s must be in [0, 12]");
+    if ((1 << q.s) > q.n) return fail(FDKOD_E_GEOMETRY, "2^s exceeds N");
+    if (q.skip < 0 || q.skip > q.s) return fail(FDKOD_E_GEOMETRY, "skip must be in [0, s]");
+    if (!(q.r > (q.n - 1) / std::sqrt(2.0)))
+        return fail(FDKOD_E_GEOMETRY, "R must exceed (N-1)/sqrt(2) (eq. (1) denominator)");
+    const int d = 1 << (q.s - q.skip);
+    if (d > 1 && q.p < 2 * d) return fail(FDKOD_E_GEOMETRY, "decimation needs P >= 2 D");
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t* out) {
+    if (!out) return fail(FDKOD_E_ARG, "out is NULL");
+    *out = nullptr;
+    fdkod_status st = fdkod_validate(prm);
+    if (st != FDKOD_OK) return st;
+
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+    if (device < 0 || device >= ndev) return fail(FDKOD_E_ARG, "device out of range");
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(FDKOD_E_UNSUPPORTED, std::string("device is ") + prop.gcnArchName + ", not gfx950");
+    int prev = 0;
+    HIP_TRY(hipGetDevice(&prev), "hipGetDevice");
+    HIP_TRY(hipSetDevice(device), "hipSetDevice");
+
+    fdkod_plan_t pl = new fdkod_plan_s();
+    pl->prm = *prm;
+    pl->device = device;
+    pl->n = prm->n;
+    pl->nz = prm->nz ? prm->nz : prm->n;
+    pl->p = prm->p;
+    pl->r = prm->r;
+    pl->s = prm->s;
+    pl->k = prm->skip;
+    pl->d = 1 << (prm->s - prm->skip);
+    pl->pd = (int)ceildiv(pl->p, pl->d);
+    pl->nsq = 1 << (2 * pl->s);
+    pl->store = prm->store;
+    {
+        int m = 8;
+        while (m < 2 * pl->n - 1) m <<= 1;
+        pl->logm = 0;
+        while ((1 << pl->logm) < m) ++pl->logm;
+    }
+
+    auto bail = [&](fdkod_status code) {
+        release(pl);
+        (void)hipSetDevice(prev);
+        return code;
+    };
+
+    // squares (Sec. 2.1): vertex-mean centres in voxel coordinates
+    const double c = (pl->n - 1) / 2.0;
+    const auto bl = blocks(pl->n, 1 << pl->s);
+    for (auto& by : bl)
+        for (auto& bx : bl) {
+            SquareDesc d{};
+            d.x0 = bx.first; d.x1 = bx.second; d.y0 = by.first; d.y1 = by.second;
+            d.xc = (float)(0.5 * ((bx.first - c) + (bx.second - 1 - c)));
+            d.yc = (float)(0.5 * ((by.first - c) + (by.second - 1 - c)));
+            d.y_off = 0;
+            pl->sq.push_back(d);
+        }
+
+    // tables
+    const std::vector<float2> trig_p = trig_table(pl->p);
+    const std::vector<float2> trig_m = trig_table(pl->pd);
+    std::vector<float2> resp, tw;
+    std::vector<float> gtail;
+    ramp_tables(pl->n, 1 << pl->logm, resp, gtail, tw);
+    const std::vector<DecimStep> sched = build_schedule(pl->p, pl->pd);
+    pl->nsched = (int)sched.size();
+    {
+        int emits = 0;
+        for (const DecimStep& st_ : sched) emits += st_.emit;
+        if (emits != pl->pd) return bail(fail(FDKOD_E_GEOMETRY, "decimation schedule does not close every window"));
+    }
+
+    if ((st = upload(pl, &pl->d_sq, pl->sq)) != FDKOD_OK) return bail(st);
+    if ((st = upload(pl, &pl->d_trig_p, trig_p)) != FDKOD_OK) return bail(st);
+    if ((st = upload(pl, &pl->d_trig_m, trig_m)) != FDKOD_OK) return bail(st);
+    if ((st = upload(pl, &pl->d_resp, resp)) != FDKOD_OK) return bail(st);
+    if ((st = upload(pl, &pl->d_gtail, gtail)) != FDKOD_OK) return bail(st);
+    if ((st = upload(pl, &pl->d_tw, tw)) != FDKOD_OK) return bail(st);
+    if ((st = upload(pl, &pl->d_sched, sched)) != FDKOD_OK) return bail(st);
+    if ((st = upload(pl, &pl->d_grid_direct, std::vector<int2>{make_int2(0, pl->n)})) != FDKOD_OK)
+        return bail(st);
+    if ((st = dev_alloc(pl, (void**)&pl->d_ac_p, sizeof(float) * (size_t)pl->nsq * pl->p)) != FDKOD_OK)
+        return bail(st);
+    if ((st = dev_alloc(pl, (void**)&pl->d_geo_m, sizeof(float4) * (size_t)pl->nsq * pl->pd)) != FDKOD_OK)
+        return bail(st);
+    if ((st = dev_alloc(pl, (void**)&pl->d_grid, sizeof(int2) * (size_t)pl->nsq)) != FDKOD_OK)
+        return bail(st);
+
+    // bounds kernel, then one synchronisation to lay out the workspace
+    if ((st = fdkod_bounds(pl, nullptr)) != FDKOD_OK) return bail(st);
+    {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return bail(hip_fail(e, "bounds kernel"));
+    }
+    pl->grid.resize(pl->nsq);
+    {
+        hipError_t e = hipMemcpy(pl->grid.data(), pl->d_grid, sizeof(int2) * pl->nsq, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return bail(hip_fail(e, "hipMemcpy grid"));
+    }
+    int wmax = 0;
+    int64_t off = 0;
+    for (int q = 0; q < pl->nsq; ++q) {
+        const int w = pl->grid[q].y;
+        if (w < 2 || w > 4 * pl->n + 8) return bail(fail(FDKOD_E_HIP, "bounds kernel produced an invalid width"));
+        wmax = std::max(wmax, w);
+        pl->sq[q].y_off = off;
+        off += (int64_t)w * pl->pd * pl->n;
+        off = (off + 63) & ~(int64_t)63;     // 256-byte aligned planes for FP32
+    }
+    pl->ws_elems = pl->s > 0 ? off : 0;
+    {
+        hipError_t e = hipMemcpy(pl->d_sq, pl->sq.data(), sizeof(SquareDesc) * pl->nsq, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return bail(hip_fail(e, "hipMemcpy squares"));
+    }
+
+    // decomposition kernel shape: 64 * chunks local columns per wavefront
+    int ch = 1;
+    while (ch < 8 && 64 * ch < wmax) ch <<= 1;
+    pl->dec_chunks = ch;
+    pl->dec_tasks_per_sq = (wmax + 64 * ch - 1) / (64 * ch);
+
+    // backprojection kernel shape and tiles
+    pl->bp_ok = choose_bp_tiles(pl->n, pl->nz, pl->r, pl->zrun, &pl->tile_w, &pl->tile_h);
+    std::vector<BpTile> tiles;
+    for (int q = 0; q < pl->nsq; ++q) {
+        const SquareDesc& d = pl->sq[q];
+        for (int y = d.y0; y < d.y1; y += kTileXY)
+            for (int x = d.x0; x < d.x1; x += kTileXY) tiles.push_back(BpTile{q, x, y, 0});
+    }
+    pl->ntiles = (int)tiles.size();
+    pl->nzt = (pl->nz + pl->zrun - 1) / pl->zrun;
+    if ((int64_t)pl->ntiles * pl->nzt > (int64_t)1 << 30)
+        return bail(fail(FDKOD_E_UNSUPPORTED, "volume too large for one launch"));
+    if ((st = upload(pl, &pl->d_tiles, tiles)) != FDKOD_OK) return bail(st);
+
+    (void)hipSetDevice(prev);
+    *out = pl;
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_plan_destroy(fdkod_plan_t plan) {
+    release(plan);
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_plan_info(fdkod_plan_t pl, fdkod_info* info) {
+    if (!pl || !info) return fail(FDKOD_E_ARG, "NULL argument");
+    info->squares = pl->nsq;
+    info->p_dec = pl->pd;
+    info->d = pl->d;
+    info->fft_len = 1 << pl->logm;
+    int wmax = 0;
+    for (auto& g : pl->grid) wmax = std::max(wmax, (int)g.y);
+    info->max_width = wmax;
+    info->z_run = pl->zrun;
+    info->filtered_bytes = (int64_t)pl->p * pl->n * pl->n * store_bytes(pl->store);
+    info->workspace_bytes = pl->ws_elems * store_bytes(pl->store);
+    info->volume_bytes = (int64_t)pl->nz * pl->n * pl->n * 4;
+    info->updates = (int64_t)pl->n * pl->n * pl->nz * pl->pd;
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_bounds(fdkod_plan_t pl, fdkod_stream_t stream) {
+    if (!pl) return fail(FDKOD_E_ARG, "plan is NULL");
+    BoundsArgs a;
+    a.squares = pl->d_sq;
+    a.trig_p = pl->d_trig_p;
+    a.trig_m = pl->d_trig_m;
+    a.ac_p = pl->d_ac_p;
+    a.geo_m = pl->d_geo_m;
+    a.grid = pl->d_grid;
+    a.n = pl->n;
+    a.p = pl->p;
+    a.pd = pl->pd;
+    a.nsq = pl->nsq;
+    a.r = (float)pl->r;
+    a.cu = (float)((pl->n - 1) / 2.0);
+    HIP_TRY(launch_bounds(a, (hipStream_t)stream), "bounds kernel launch");
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_filter(fdkod_plan_t pl, const float* proj, void* filt, fdkod_stream_t stream) {
+    if (!pl || !proj || !filt) return fail(FDKOD_E_ARG, "NULL argument");
+    FilterArgs a;
+    a.proj = proj;
+    a.out = filt;
+    a.resp = pl->d_resp;
+    a.gtail = pl->d_gtail;
+    a.twiddle = pl->d_tw;
+    a.n = pl->n;
+    a.rows = pl->p * pl->n;
+    a.r = (float)pl->r;
+    a.c = (float)((pl->n - 1) / 2.0);
+    HIP_TRY(launch_filter(a, pl->logm, pl->store, (hipStream_t)stream), "filter kernel launch");
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_decompose(fdkod_plan_t pl, const void* filt, void* ws, fdkod_stream_t stream) {
+    if (!pl || !filt) return fail(FDKOD_E_ARG, "NULL argument");
+    if (pl->s == 0) return FDKOD_OK;
+    if (!ws) return fail(FDKOD_E_ARG, "workspace is NULL");
+    DecimArgs a;
+    a.filt = filt;
+    a.ws = ws;
+    a.squares = pl->d_sq;
+    a.grid = pl->d_grid;
+    a.ac_p = pl->d_ac_p;
+    a.sched = pl->d_sched;
+    a.nsched = pl->nsched;
+    a.n = pl->n;
+    a.p = pl->p;
+    a.pd = pl->pd;
+    a.nsq = pl->nsq;
+    a.tasks_per_sq = pl->dec_tasks_per_sq;
+    a.ntasks = pl->nsq * pl->n * pl->dec_tasks_per_sq;
+    HIP_TRY(launch_decimate(a, pl->dec_chunks, pl->store, (hipStream_t)stream), "decimate kernel launch");
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_reconstruct(fdkod_plan_t pl, const void* filt, const void* ws, float* vol,
+                               fdkod_stream_t stream) {
+    if (!pl || !vol) return fail(FDKOD_E_ARG, "NULL argument");
+    const bool direct = pl->s == 0;
+    if (direct && !filt) return fail(FDKOD_E_ARG, "filtered projections are NULL");
+    if (!direct && !ws) return fail(FDKOD_E_ARG, "workspace is NULL");
+    if (!pl->bp_ok)
+        return fail(FDKOD_E_UNSUPPORTED, "R too small: a block's detector footprint exceeds 64 x 64");
+    BpArgs a;
+    a.data = direct ? filt : ws;
+    a.vol = vol;
+    a.squares = pl->d_sq;
+    a.grid = direct ? pl->d_grid_direct : pl->d_grid;
+    a.trig = pl->d_trig_m;
+    a.tiles = pl->d_tiles;
+    a.ntiles = pl->ntiles;
+    a.nzt = pl->nzt;
+    a.nlogical = pl->ntiles * pl->nzt;
+    a.chunk = (a.nlogical + 7) / 8;
+    a.n = pl->n;
+    a.nz = pl->nz;
+    a.pd = pl->pd;
+    a.row_stride_direct = direct ? pl->n : 0;
+    a.r = (float)pl->r;
+    a.cu = (float)((pl->n - 1) / 2.0);
+    a.cv = a.cu;
+    a.cz = (float)((pl->nz - 1) / 2.0);
+    a.scale = (float)(M_PI / pl->pd);
+    HIP_TRY(launch_backproject(a, pl->zrun, pl->tile_w, pl->tile_h, pl->store, (hipStream_t)stream),
+            "backprojection kernel launch");
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_backproject(fdkod_plan_t pl, const void* filt, float* vol, void* ws,
+                               fdkod_stream_t stream) {
+    fdkod_status st = fdkod_decompose(pl, filt, ws, stream);
+    if (st != FDKOD_OK) return st;
+    return fdkod_reconstruct(pl, filt, ws, vol, stream);
+}
+
+fdkod_status fdkod_get_bounds(fdkod_plan_t pl, float* ac_p, float* ac_m, float* amin_m, float* amax_m,
+                              int32_t* u0, int32_t* width, int32_t* rect) {
+    if (!pl) return fail(FDKOD_E_ARG, "plan is NULL");
+    int prev = 0;
+    HIP_TRY(hipGetDevice(&prev), "hipGetDevice");
+    HIP_TRY(hipSetDevice(pl->device), "hipSetDevice");
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (ac_p)
+        HIP_TRY(hipMemcpy(ac_p, pl->d_ac_p, sizeof(float) * (size_t)pl->nsq * pl->p, hipMemcpyDeviceToHost),
+                "hipMemcpy ac_p");
+    if (ac_m || amin_m || amax_m) {
+        std::vector<float4> geo((size_t)pl->nsq * pl->pd);
+        HIP_TRY(hipMemcpy(geo.data(), pl->d_geo_m, sizeof(float4) * geo.size(), hipMemcpyDeviceToHost),
+                "hipMemcpy geo");
+        for (size_t i = 0; i < geo.size(); ++i) {
+            if (ac_m) ac_m[i] = geo[i].x;
+            if (amin_m) amin_m[i] = geo[i].y;
+            if (amax_m) amax_m[i] = geo[i].z;
+        }
+    }
+    std::vector<int2> g(pl->nsq);
+    HIP_TRY(hipMemcpy(g.data(), pl->d_grid, sizeof(int2) * pl->nsq, hipMemcpyDeviceToHost), "hipMemcpy grid");
+    for (int q = 0; q < pl->nsq; ++q) {
+        if (u0) u0[q] = g[q].x;
+        if (width) width[q] = g[q].y;
+        if (rect) {
+            rect[4 * q + 0] = pl->sq[q].x0;
+            rect[4 * q + 1] = pl->sq[q].x1;
+            rect[4 * q + 2] = pl->sq[q].y0;
+            rect[4 * q + 3] = pl->sq[q].y1;
+        }
+    }
+    (void)hipSetDevice(prev);
+    return FDKOD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+// Internal declarations shared by the host plan code and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+namespace fdkod {
+
+// One square of the decomposition (Sec. 2.1): voxel index ranges, centre
+// (vertex mean, voxel coordinates), local grid and the offset of its
+// decimated data in the workspace (elements).
+struct SquareDesc {
+    int x0, x1, y0, y1;
+    float xc, yc;
+    int64_t y_off;
+};
+
+// One step of the decimation schedule: the extended angle index p_ext
+// (the projection read is p_ext mod P), the weights of the projection in the
+// two open decimation windows, and whether the older window closes after it.
+struct DecimStep {
+    int p;        // projection index in [0, P)
+    int emit;     // 1: the older window is complete after this step
+    float w0;     // weight into the older open window
+    float w1;     // weight into the newer open window
+};
+
+// Backprojection tile: 16 x 16 voxels in x, y of one square.
+struct BpTile {
+    int sq;       // square index
+    int x0, y0;   // first voxel of the tile (indices)
+    int pad;
+};
+
+// Arguments of the bounds kernel.
+struct BoundsArgs {
+    const SquareDesc* squares;
+    const float2* trig_p;   // cos, sin of beta_p, [P]
+    const float2* trig_m;   // cos, sin of beta'_m, [P']
+    float* ac_p;            // [nsq][P]
+    float4* geo_m;          // [nsq][P'] a_c, a_min, a_max, 0
+    int2* grid;             // [nsq] u0, W
+    int n, p, pd, nsq;
+    float r, cu;
+};
+
+// Arguments of the ramp filter kernel.
+struct FilterArgs {
+    const float* proj;      // [rows][n]
+    void* out;              // [rows][n] store type
+    const float2* resp;     // DFT of the running-sum kernel g, / M, [M]
+    const float* gtail;     // g[u - N], u in [0, N)
+    const float2* twiddle;  // exp(-2 pi i k / M), [M]
+    int n;                  // detector width
+    int rows;               // P * N
+    float r;                // R
+    float c;                // (N-1)/2
+};
+
+// Arguments of the crop + shift + decimate kernel.
+struct DecimArgs {
+    const void* filt;       // [P][N][N] store type
+    void* ws;               // decimated data, store type
+    const SquareDesc* squares;
+    const int2* grid;       // u0, W per square
+    const float* ac_p;      // [nsq][P]
+    const DecimStep* sched;
+    int nsched;
+    int n, p, pd, nsq;
+    int tasks_per_sq;       // column groups per square
+    int ntasks;             // nsq * n * tasks_per_sq
+};
+
+// Arguments of the backprojection kernel.
+struct BpArgs {
+    const void* data;       // decimated data (s > 0) or filtered projections (s = 0)
+    float* vol;             // [nz][n][n]
+    const SquareDesc* squares;
+    const int2* grid;       // u0, W per square (direct: 0, N)
+    const float2* trig;     // cos, sin of the reconstruction angles, [pd]
+    const BpTile* tiles;
+    int ntiles;             // xy tiles
+    int nzt;                // z tiles
+    int nlogical;           // ntiles * nzt
+    int chunk;              // logical WGs per XCD
+    int n, nz, pd;
+    int row_stride_direct;  // 0 for per-square layout [m][v][W_q]
+    float r, cu, cv, cz;
+    float scale;            // pi / P'
+};
+
+hipError_t launch_bounds(const BoundsArgs& a, hipStream_t st);
+hipError_t launch_filter(const FilterArgs& a, int logm, int store, hipStream_t st);
+hipError_t launch_decimate(const DecimArgs& a, int chunks, int store, hipStream_t st);
+hipError_t launch_backproject(const BpArgs& a, int zrun, int tile_w, int tile_h,
+                              int store, hipStream_t st);
+
+// Limits the host checks before choosing a backprojection variant.
+constexpr int kTileXY = 16;      // voxels per tile side in x and y
+constexpr int kAngBatch = 8;     // angles staged in LDS per barrier
+
+}  // namespace fdkod

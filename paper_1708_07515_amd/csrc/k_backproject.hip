@@ -1,0 +1,176 @@
+// Reconstruction (Sec. 2.2, eq. (6)): cone-weighted bilinear backprojection of
+// every square from its decimated sub-sinogram (s > 0), or of the whole slice
+// from the filtered projections (s = 0: direct FDK, the same inner loop).
+//
+//   f(x, y, z) = (pi / P') sum_m U^-2 Bil(Y_q[m], v*, tau)
+//   U = depth / R,  tau = a(x, y) - a_c + c_u - u0  (eq. (1), folded back-shift),
+//   v* = z R / depth + c_v                            (eq. (9))
+//
+// Workgroup = 16 x 16 voxels in (x, y) of one square times ZR consecutive
+// slices; every thread owns one (x, y) and ZR accumulators in registers.
+// Angles are processed in batches of G.  For each angle of a batch the
+// footprint of the workgroup's voxel block on the (local) detector is bounded
+// with eq. (1) at the block's corners (columns) and eq. (9) at its corner
+// depths and end slices (rows) -- the paper's vertex bound applied to the
+// block -- and that footprint (at most TH x TW samples, padded by one sample
+// on every side) is staged in LDS in FP32.  Per (x, y, angle) a thread
+// computes tau, U and the weight once; along z only the row coordinate moves,
+// linearly (b = z / U), so each voxel-angle update is one bilinear sample from
+// LDS and one multiply-add.
+#include "internal.h"
+#include "dtype.h"
+#include "geom.h"
+
+namespace fdkod {
+
+template <int ZR, int TW, int TH, int G, int STORE>
+__global__ __launch_bounds__(256) void k_backproject(BpArgs a) {
+    using S = Store<STORE>;
+    using T = typename S::T;
+    constexpr int TWP = TW + 1;   // LDS row pitch (odd: spreads banks)
+    __shared__ float tile[G][TH * TWP];
+    __shared__ int4 meta[G];      // c0, r0 (first column / row of the footprint), -, -
+    __shared__ float4 mgeo[G];    // cos, sin, Dc, Lc
+
+    // XCD-aware order: each XCD runs a contiguous range of logical blocks
+    const int b = blockIdx.x;
+    const int lblk = (b & 7) * a.chunk + (b >> 3);
+    if (lblk >= a.nlogical) return;               // before any barrier
+    const int zt = lblk / a.ntiles;
+    const BpTile tl = a.tiles[lblk - zt * a.ntiles];
+    const SquareDesc sq = a.squares[tl.sq];
+    const int2 gd = a.grid[tl.sq];
+    const int u0 = gd.x, width = gd.y;
+
+    const int n = a.n;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int ix1 = min(tl.x0 + 15, sq.x1 - 1);
+    const int iy1 = min(tl.y0 + 15, sq.y1 - 1);
+    const int i = tl.x0 + tx, j = tl.y0 + ty;
+    const bool own = (i <= ix1) && (j <= iy1);
+    // offsets from the square centre; threads outside the square use the
+    // block's last voxel so every address they form stays in bounds
+    const float dx = (float)min(i, ix1) - a.cu - sq.xc;
+    const float dy = (float)min(j, iy1) - a.cu - sq.yc;
+    const float bx0 = (float)tl.x0 - a.cu - sq.xc, bx1 = (float)ix1 - a.cu - sq.xc;
+    const float by0 = (float)tl.y0 - a.cu - sq.yc, by1 = (float)iy1 - a.cu - sq.yc;
+
+    const int l0 = zt * ZR;
+    const int l1 = min(l0 + ZR, a.nz) - 1;
+    const float z0 = (float)l0 - a.cz;
+    const float zlast = (float)l1 - a.cz;
+
+    const bool direct = a.row_stride_direct != 0;
+    const int row_stride = direct ? a.row_stride_direct : width;
+    const size_t plane = (size_t)n * row_stride;
+    const T* data = (const T*)a.data + (direct ? 0 : sq.y_off);
+    const float kq = a.cu - (float)u0;            // tau = rel + kq
+
+    float acc[ZR];
+#pragma unroll
+    for (int k = 0; k < ZR; ++k) acc[k] = 0.0f;
+
+    for (int m0 = 0; m0 < a.pd; m0 += G) {
+        const int gcount = min(G, a.pd - m0);
+        // footprint of the block at each angle of the batch
+        if (threadIdx.x < gcount) {
+            const int m = m0 + threadIdx.x;
+            const float2 t = a.trig[m];
+            const float dc = a.r + sq.xc * t.x + sq.yc * t.y;
+            const float lc = sq.yc * t.x - sq.xc * t.y;
+            const float rdc = 1.0f / dc;
+            float tlo = INFINITY, thi = -INFINITY, vlo = INFINITY, vhi = -INFINITY;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float cx = (k & 1) ? bx1 : bx0;
+                const float cy = (k & 2) ? by1 : by0;
+                const float tau = rel_column(cx, cy, t.x, t.y, a.r, dc, lc, rdc) + kq;
+                tlo = fminf(tlo, tau);
+                thi = fmaxf(thi, tau);
+                const float iu = a.r / (dc + cx * t.x + cy * t.y);
+                const float va = z0 * iu + a.cv, vb = zlast * iu + a.cv;
+                vlo = fminf(vlo, fminf(va, vb));
+                vhi = fmaxf(vhi, fmaxf(va, vb));
+            }
+            meta[threadIdx.x] = make_int4((int)floorf(tlo) - 1, (int)floorf(vlo) - 1, 0, 0);
+            mgeo[threadIdx.x] = make_float4(t.x, t.y, dc, lc);
+        }
+        __syncthreads();
+        // stage the footprints: columns outside [0, width) and rows outside
+        // the detector are zero (zero extension)
+        for (int g = 0; g < gcount; ++g) {
+            const int4 mt = meta[g];
+            const T* pl = data + (size_t)(m0 + g) * plane;
+            for (int e = threadIdx.x; e < TH * TW; e += 256) {
+                const int rr = e / TW, cc = e % TW;
+                const int row = mt.y + rr, col = mt.x + cc;
+                float val = 0.0f;
+                if ((unsigned)row < (unsigned)n && (unsigned)col < (unsigned)width)
+                    val = S::load(pl, (size_t)row * row_stride + col);
+                tile[g][rr * TWP + cc] = val;
+            }
+        }
+        __syncthreads();
+        for (int g = 0; g < gcount; ++g) {
+            const float4 mg = mgeo[g];
+            const int4 mt = meta[g];
+            const float dl = dy * mg.x - dx * mg.y;
+            const float dd = dx * mg.x + dy * mg.y;
+            const float d = mg.z + dd;
+            const float rd = 1.0f / d;
+            const float tau = a.r * (dl * mg.z - mg.w * dd) * (1.0f / mg.z) * rd + kq
+                              - (float)mt.x;
+            const float invu = a.r * rd;
+            const float w = a.scale * invu * invu;
+            const float tf = floorf(tau);
+            const float fu = tau - tf;
+            const int ci = min(max((int)tf, 0), TW - 2);
+            const float v0 = z0 * invu + (a.cv - (float)mt.y);
+            const float* tg = tile[g] + ci;
+#pragma unroll
+            for (int k = 0; k < ZR; ++k) {
+                const float v = fmaf((float)k, invu, v0);
+                const float vf = floorf(v);
+                const float fv = v - vf;
+                const int ri = min(max((int)vf, 0), TH - 2);
+                const float* p = tg + ri * TWP;
+                const float a00 = p[0], a01 = p[1], a10 = p[TWP], a11 = p[TWP + 1];
+                const float top = fmaf(fu, a01 - a00, a00);
+                const float bot = fmaf(fu, a11 - a10, a10);
+                acc[k] = fmaf(w, fmaf(fv, bot - top, top), acc[k]);
+            }
+        }
+        __syncthreads();
+    }
+    if (own) {
+#pragma unroll
+        for (int k = 0; k < ZR; ++k) {
+            const int l = l0 + k;
+            if (l < a.nz) a.vol[((size_t)l * n + j) * n + i] = acc[k];
+        }
+    }
+}
+
+template <int ZR, int TW, int TH>
+static void launch_bp_t(const BpArgs& a, int store, dim3 grid, hipStream_t st) {
+    constexpr int G = (TW * TH <= 1024) ? 8 : (TW * TH <= 2048 ? 4 : 2);
+    switch (store) {
+        case 0: hipLaunchKernelGGL((k_backproject<ZR, TW, TH, G, 0>), grid, dim3(256), 0, st, a); break;
+        case 1: hipLaunchKernelGGL((k_backproject<ZR, TW, TH, G, 1>), grid, dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_backproject<ZR, TW, TH, G, 2>), grid, dim3(256), 0, st, a); break;
+    }
+}
+
+hipError_t launch_backproject(const BpArgs& a, int zrun, int tile_w, int tile_h, int store,
+                              hipStream_t st) {
+    const dim3 grid(8 * a.chunk);
+    if (zrun != 16) return hipErrorInvalidValue;
+    if (tile_w == 32 && tile_h == 32) launch_bp_t<16, 32, 32>(a, store, grid, st);
+    else if (tile_w == 32 && tile_h == 64) launch_bp_t<16, 32, 64>(a, store, grid, st);
+    else if (tile_w == 64 && tile_h == 32) launch_bp_t<16, 64, 32>(a, store, grid, st);
+    else if (tile_w == 64 && tile_h == 64) launch_bp_t<16, 64, 64>(a, store, grid, st);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace fdkod

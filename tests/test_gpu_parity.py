@@ -1,0 +1,164 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.  Tolerances: rel-RMSE <= 1e-4 for FP32 storage and
+<= 2e-3 for FP16 / BF16 storage (against the plain FP64 oracle)."""
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1708_07515_amd as pkg
+from oracle import fdk as ofdk, fdkod as ofdkod, geometry as g, metrics
+from gpu_common import (DEV, gpu_reconstruct, log, oracle_reconstruct, report, require_gpu,
+                        scan)
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-4
+TOL_HALF = 2e-3
+
+# cone64_p90: detector 64x64, P=90, R=512, volume 64^3, 10 ellipsoids, seed 1
+C1 = dict(n=64, p=90, r=512.0, ellipsoids=10, seed=1)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def c1_scan():
+    return scan(C1["n"], C1["p"], C1["r"], C1["ellipsoids"], C1["seed"])
+
+
+# --------------------------------------------------------------------- bounds
+
+@pytest.mark.parametrize("n,p,r,s,k", [(64, 90, 512.0, 1, 0), (64, 90, 512.0, 2, 0),
+                                       (72, 97, 300.0, 3, 1), (512, 360, 2048.0, 3, 0),
+                                       (2000, 720, 8000.0, 4, 0), (33, 20, 60.0, 2, 0)])
+def test_bounds_match_oracle_and_cover(n, p, r, s, k):
+    log(f"bounds n={n} p={p} r={r} s={s} k={k}")
+    with pkg.Plan(n, p, r, s=s, skip=k) as plan:
+        gb = plan.get_bounds()
+    sqs, betas, bd = ofdkod.plan(n, p, r, s, k)
+    c = g.centre(n)
+    for q, sq in enumerate(sqs):
+        assert tuple(gb["rect"][q]) == (sq.x0, sq.x1, sq.y0, sq.y1)
+        ac_p = ofdkod.centre_track(sq, betas, r)
+        ac_m = ofdkod.centre_track(sq, bd, r)
+        amin, amax = ofdkod.vertex_bounds(sq, n, bd, r)
+        tol = 2e-6 * (np.abs(ac_p).max() + n) + 1e-5
+        assert np.max(np.abs(gb["ac_p"][q] - ac_p)) <= tol
+        assert np.max(np.abs(gb["ac_m"][q] - ac_m)) <= tol
+        assert np.max(np.abs(gb["amin"][q] - amin)) <= tol
+        assert np.max(np.abs(gb["amax"][q] - amax)) <= tol
+        # integers decided in FP32 may differ by one at ties; the local grid
+        # must still cover every voxel of the square at every decimated angle
+        assert abs(int(gb["u0"][q]) - sq.u0) <= 1
+        assert abs(int(gb["width"][q]) - sq.width) <= 1
+        i, j = np.meshgrid(np.arange(sq.x0, sq.x1), np.arange(sq.y0, sq.y1))
+        for m, beta in enumerate(bd[:: max(1, len(bd) // 45)]):
+            tau = g.pix_pos(i - c, j - c, beta, r) - ofdkod.centre_track(sq, [beta], r)[0] + c \
+                - gb["u0"][q]
+            assert tau.min() >= -1e-3 and tau.max() < gb["width"][q] - 1 + 1e-3
+
+
+# --------------------------------------------------------------------- filter
+
+@pytest.mark.parametrize("n,p,r", [(64, 90, 512.0), (50, 7, 80.0), (33, 5, 40.0), (512, 4, 2048.0),
+                                   (2000, 2, 8000.0)])
+def test_filter_matches_oracle(n, p, r):
+    log(f"filter n={n} p={p}")
+    proj = scan(n, p, r, 8, 21)
+    with pkg.Plan(n, p, r, s=0) as plan:
+        filt = plan.empty_filtered()
+        plan.filter(proj.to(DEV), filt)
+        torch.cuda.synchronize()
+        got = filt.cpu().double().numpy()
+    ref = ofdk.filter_rows(proj.numpy(), r, np.arange(n)).data
+    err, mxr = report(f"filter n={n}", got, ref)
+    # Bound from the FP32 arithmetic: the pre-weighted row p~ is rounded
+    # (product and weight, ~2 u relative, u = 2^-24) before filtering, and the
+    # Ram-Lak gain sqrt(sum h^2) = 0.29 < 1 carries that noise to q, so
+    # |dq| <= 2 u |p~|; the FFT of the first difference adds ~4 log2(M) u |q|.
+    u = 2.0 ** -24
+    pw = proj.numpy().astype(np.float64) * ofdk.cosine_weight(n, r)[None]
+    m = 1 << int(np.ceil(np.log2(2 * n - 1)))
+    bound = u * (2.0 * np.linalg.norm(pw) / np.linalg.norm(ref) + 4 * np.log2(m))
+    log(f"  bound {bound:.2e}")
+    assert err <= bound and mxr <= 4 * bound
+
+
+# ------------------------------------------------------------ reconstruction
+
+def test_direct_fdk_c1_full_volume():
+    proj = c1_scan()
+    got, _ = gpu_reconstruct(proj, C1["n"], C1["p"], C1["r"], s=0)
+    ref = ofdk.fdk(proj.numpy(), C1["r"])
+    err, _ = report("direct FDK c1", got, ref)
+    assert err <= TOL_F32
+
+
+@pytest.mark.parametrize("s,k", [(1, 0), (2, 0), (2, 1), (2, 2)])
+def test_fdkod_c1_full_volume(s, k):
+    proj = c1_scan()
+    got, _ = gpu_reconstruct(proj, C1["n"], C1["p"], C1["r"], s=s, skip=k)
+    ref = ofdkod.fdkod(proj.numpy(), C1["r"], s, k)
+    err, _ = report(f"FDK-OD c1 s={s} k={k}", got, ref)
+    assert err <= TOL_F32
+
+
+@pytest.mark.parametrize("n,nz,p,r,s,k", [(72, 41, 97, 300.0, 2, 0), (72, 41, 97, 300.0, 3, 0),
+                                          (45, 17, 30, 90.0, 2, 1), (40, 9, 64, 60.0, 1, 0),
+                                          (45, 17, 30, 90.0, 0, 0)])
+def test_ragged_sizes(n, nz, p, r, s, k):
+    # squares of unequal size, P not divisible by D, partial z and xy tiles,
+    # a small R (large cone angle, wide footprints)
+    proj = scan(n, p, r, 7, 31)
+    got, _ = gpu_reconstruct(proj, n, p, r, s=s, skip=k, nz=nz)
+    ref = oracle_reconstruct(proj, r, s, k, nz=nz)
+    err, _ = report(f"ragged n={n} nz={nz} p={p} s={s} k={k}", got, ref)
+    assert err <= TOL_F32
+
+
+@pytest.mark.parametrize("store", ["f16", "bf16"])
+@pytest.mark.parametrize("s", [0, 2])
+def test_half_storage_c1(store, s):
+    proj = c1_scan()
+    got, _ = gpu_reconstruct(proj, C1["n"], C1["p"], C1["r"], s=s, store=store)
+    ref = oracle_reconstruct(proj, C1["r"], s)
+    err, _ = report(f"{store} s={s} vs FP64 oracle", got, ref)
+    assert err <= TOL_HALF
+    emu = oracle_reconstruct(proj, C1["r"], s, store=store)
+    err2, _ = report(f"{store} s={s} vs storage-rounded oracle", got, emu)
+    assert err2 <= 5e-4
+
+
+def test_bitwise_repeatable_and_stream_independent():
+    proj = c1_scan()
+    a, _ = gpu_reconstruct(proj, C1["n"], C1["p"], C1["r"], s=2)
+    b, _ = gpu_reconstruct(proj, C1["n"], C1["p"], C1["r"], s=2)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        c, _ = gpu_reconstruct(proj, C1["n"], C1["p"], C1["r"], s=2, stream=st)
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+# ------------------------------------------------- full-size workload (sampled)
+
+# cone512_p360: detector 512x512, P=360, R=2048, volume 512^3, 20 ellipsoids,
+# Poisson noise at 1e5 photons per ray
+C2 = dict(n=512, p=360, r=2048.0, ellipsoids=20, seed=2, photons=1e5)
+
+
+@pytest.fixture(scope="module")
+def c2_scan():
+    return scan(C2["n"], C2["p"], C2["r"], C2["ellipsoids"], C2["seed"], C2["photons"], on_gpu=True)
+
+
+@pytest.mark.parametrize("s", [0, 1, 2, 3])
+def test_c2_sampled_slices(c2_scan, s):
+    n, p, r = C2["n"], C2["p"], C2["r"]
+    slices = [0, 255, 511] if s in (0, 3) else [300]
+    got, _ = gpu_reconstruct(c2_scan, n, p, r, s=s)
+    ref = oracle_reconstruct(c2_scan, r, s, slices=slices)
+    err, _ = report(f"c2 s={s} slices {slices}", got[slices], ref)
+    assert err <= TOL_F32
