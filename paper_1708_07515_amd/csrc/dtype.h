@@ -14,12 +14,20 @@ template <> struct Store<0> {
     using T = float;
     static __device__ __forceinline__ float load(const T* p, size_t i) { return p[i]; }
     static __device__ __forceinline__ void put(T* p, size_t i, float v) { p[i] = v; }
+    // load through a raw buffer resource at a byte offset (zero when out of range)
+    static __device__ __forceinline__ float raw(__amdgpu_buffer_rsrc_t r, int off) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    }
 };
 
 template <> struct Store<1> {
     using T = _Float16;
     static __device__ __forceinline__ float load(const T* p, size_t i) { return (float)p[i]; }
     static __device__ __forceinline__ void put(T* p, size_t i, float v) { p[i] = (_Float16)v; }
+    static __device__ __forceinline__ float raw(__amdgpu_buffer_rsrc_t r, int off) {
+        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+        return (float)__builtin_bit_cast(_Float16, h);
+    }
 };
 
 template <> struct Store<2> {
@@ -35,6 +43,10 @@ template <> struct Store<2> {
         }
         b += 0x7FFFu + ((b >> 16) & 1u);              // round to nearest even
         p[i] = (uint16_t)(b >> 16);
+    }
+    static __device__ __forceinline__ float raw(__amdgpu_buffer_rsrc_t r, int off) {
+        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+        return __uint_as_float(((uint32_t)h) << 16);
     }
 };
 

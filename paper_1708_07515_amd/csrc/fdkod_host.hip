@@ -93,7 +93,7 @@ struct fdkod_plan_s {
     // decomposition kernel shape
     int dec_chunks = 1, dec_tasks_per_sq = 1;
     // backprojection kernel shape
-    int zrun = 16, tile_w = 32, tile_h = 32, ntiles = 0, nzt = 0;
+    int zrun = 32, tile_w = 32, tile_h = 48, ntiles = 0, nzt = 0;
     bool bp_ok = false;     // the block footprint fits the largest LDS tile
     int64_t ws_elems = 0;
     // device tables
@@ -101,6 +101,7 @@ struct fdkod_plan_s {
     float2* d_trig_p = nullptr;
     float2* d_trig_m = nullptr;
     float* d_ac_p = nullptr;
+    int2* d_crop = nullptr;
     float4* d_geo_m = nullptr;
     int2* d_grid = nullptr;
     int2* d_grid_direct = nullptr;
@@ -235,12 +236,12 @@ bool choose_bp_tiles(int n, int nz, double r, int zrun, int* tw, int* th) {
     const double lat = c * std::sqrt(2.0) / dmin;
     const double diag = (kTileXY - 1) * std::sqrt(2.0);
     const double span_c = diag * mag * std::sqrt(1.0 + lat * lat);
-    const double zmax = (nz - 1) / 2.0;
+    const double zmax = (nz - 1) / 2.0 + zrun;     // runs may extend past the last slice
     const double span_r = (zrun - 1) * mag + zmax * r * diag / (dmin * dmin);
     const int need_c = (int)std::ceil(span_c + 1e-6) + 4;
     const int need_r = (int)std::ceil(span_r + 1e-6) + 4;
     *tw = need_c <= 32 ? 32 : (need_c <= 64 ? 64 : 0);
-    *th = need_r <= 32 ? 32 : (need_r <= 64 ? 64 : 0);
+    *th = need_r <= 48 ? 48 : (need_r <= 64 ? 64 : 0);
     return *tw && *th;
 }
 
@@ -346,7 +347,8 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
     std::vector<float2> resp, tw;
     std::vector<float> gtail;
     ramp_tables(pl->n, 1 << pl->logm, resp, gtail, tw);
-    const std::vector<DecimStep> sched = build_schedule(pl->p, pl->pd);
+    std::vector<DecimStep> sched = build_schedule(pl->p, pl->pd);
+    while (sched.size() % kDecimUnroll) sched.push_back(DecimStep{0, 0, 0.0f, 0.0f});
     pl->nsched = (int)sched.size();
     {
         int emits = 0;
@@ -366,6 +368,8 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
     if ((st = dev_alloc(pl, (void**)&pl->d_ac_p, sizeof(float) * (size_t)pl->nsq * pl->p)) != FDKOD_OK)
         return bail(st);
     if ((st = dev_alloc(pl, (void**)&pl->d_geo_m, sizeof(float4) * (size_t)pl->nsq * pl->pd)) != FDKOD_OK)
+        return bail(st);
+    if ((st = dev_alloc(pl, (void**)&pl->d_crop, sizeof(int2) * (size_t)pl->nsq * pl->nsched)) != FDKOD_OK)
         return bail(st);
     if ((st = dev_alloc(pl, (void**)&pl->d_grid, sizeof(int2) * (size_t)pl->nsq)) != FDKOD_OK)
         return bail(st);
@@ -404,7 +408,15 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
     pl->dec_tasks_per_sq = (wmax + 64 * ch - 1) / (64 * ch);
 
     // backprojection kernel shape and tiles
-    pl->bp_ok = choose_bp_tiles(pl->n, pl->nz, pl->r, pl->zrun, &pl->tile_w, &pl->tile_h);
+    // the longest z run whose footprint fits the largest LDS tile
+    pl->bp_ok = false;
+    for (int zr : {32, 16}) {
+        if (choose_bp_tiles(pl->n, pl->nz, pl->r, zr, &pl->tile_w, &pl->tile_h)) {
+            pl->zrun = zr;
+            pl->bp_ok = true;
+            break;
+        }
+    }
     std::vector<BpTile> tiles;
     for (int q = 0; q < pl->nsq; ++q) {
         const SquareDesc& d = pl->sq[q];
@@ -453,10 +465,13 @@ fdkod_status fdkod_bounds(fdkod_plan_t pl, fdkod_stream_t stream) {
     a.ac_p = pl->d_ac_p;
     a.geo_m = pl->d_geo_m;
     a.grid = pl->d_grid;
+    a.sched = pl->d_sched;
+    a.crop = pl->d_crop;
     a.n = pl->n;
     a.p = pl->p;
     a.pd = pl->pd;
     a.nsq = pl->nsq;
+    a.nsched = pl->nsched;
     a.r = (float)pl->r;
     a.cu = (float)((pl->n - 1) / 2.0);
     HIP_TRY(launch_bounds(a, (hipStream_t)stream), "bounds kernel launch");
@@ -488,7 +503,7 @@ fdkod_status fdkod_decompose(fdkod_plan_t pl, const void* filt, void* ws, fdkod_
     a.ws = ws;
     a.squares = pl->d_sq;
     a.grid = pl->d_grid;
-    a.ac_p = pl->d_ac_p;
+    a.crop = pl->d_crop;
     a.sched = pl->d_sched;
     a.nsched = pl->nsched;
     a.n = pl->n;

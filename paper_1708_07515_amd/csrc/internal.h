@@ -42,7 +42,9 @@ struct BoundsArgs {
     float* ac_p;            // [nsq][P]
     float4* geo_m;          // [nsq][P'] a_c, a_min, a_max, 0
     int2* grid;             // [nsq] u0, W
-    int n, p, pd, nsq;
+    const DecimStep* sched; // decimation schedule (projection of each step)
+    int2* crop;             // [nsq][nsched] floor(a_c + u0), bits of the fraction
+    int n, p, pd, nsq, nsched;
     float r, cu;
 };
 
@@ -65,7 +67,7 @@ struct DecimArgs {
     void* ws;               // decimated data, store type
     const SquareDesc* squares;
     const int2* grid;       // u0, W per square
-    const float* ac_p;      // [nsq][P]
+    const int2* crop;       // [nsq][nsched] integer shift and fraction per step
     const DecimStep* sched;
     int nsched;
     int n, p, pd, nsq;
@@ -99,6 +101,6 @@ hipError_t launch_backproject(const BpArgs& a, int zrun, int tile_w, int tile_h,
 
 // Limits the host checks before choosing a backprojection variant.
 constexpr int kTileXY = 16;      // voxels per tile side in x and y
-constexpr int kAngBatch = 8;     // angles staged in LDS per barrier
+constexpr int kDecimUnroll = 4;  // schedule steps the decimation kernel loads at once
 
 }  // namespace fdkod

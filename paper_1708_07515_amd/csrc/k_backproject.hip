@@ -13,24 +13,31 @@
 // with eq. (1) at the block's corners (columns) and eq. (9) at its corner
 // depths and end slices (rows) -- the paper's vertex bound applied to the
 // block -- and that footprint (at most TH x TW samples, padded by one sample
-// on every side) is staged in LDS in FP32.  Per (x, y, angle) a thread
-// computes tau, U and the weight once; along z only the row coordinate moves,
-// linearly (b = z / U), so each voxel-angle update is one bilinear sample from
-// LDS and one multiply-add.
+// on every side) is staged in LDS as pairs (Y[c], Y[c+1] - Y[c]), so one
+// 64-bit LDS read pair fetches the two rows of a bilinear sample and each
+// horizontal interpolation is one FMA.  Per (x, y, angle) a thread computes
+// tau, U and the weight once; along z only the row coordinate moves, linearly
+// (b = z / U), so an update costs a row index, one LDS read and five FMAs.
 #include "internal.h"
 #include "dtype.h"
 #include "geom.h"
 
 namespace fdkod {
 
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) const char* lds_cptr;
+typedef __attribute__((address_space(3))) const f2v* lds_f2ptr;
+
 template <int ZR, int TW, int TH, int G, int STORE>
 __global__ __launch_bounds__(256) void k_backproject(BpArgs a) {
     using S = Store<STORE>;
     using T = typename S::T;
-    constexpr int TWP = TW + 1;   // LDS row pitch (odd: spreads banks)
-    __shared__ float tile[G][TH * TWP];
-    __shared__ int4 meta[G];      // c0, r0 (first column / row of the footprint), -, -
+    constexpr int TWP = TW + 1;   // LDS row pitch in pairs (odd: spreads banks)
+    static_assert(TWP <= 255, "ds_read2_b64 offset range");
+    __shared__ float2 tile[G][TH * TWP];
+    __shared__ int4 meta[G];      // c0, r0 (first column / row of the footprint), rows, -
     __shared__ float4 mgeo[G];    // cos, sin, Dc, Lc
+    __shared__ float2 mgeo2[G];   // R / Dc, c_u - u0 - c0
 
     // XCD-aware order: each XCD runs a contiguous range of logical blocks
     const int b = blockIdx.x;
@@ -55,16 +62,23 @@ __global__ __launch_bounds__(256) void k_backproject(BpArgs a) {
     const float bx0 = (float)tl.x0 - a.cu - sq.xc, bx1 = (float)ix1 - a.cu - sq.xc;
     const float by0 = (float)tl.y0 - a.cu - sq.yc, by1 = (float)iy1 - a.cu - sq.yc;
 
+    // the run covers ZR slices even past the volume's end (those voxels are
+    // computed and discarded), so the staged rows always hold the whole run
     const int l0 = zt * ZR;
-    const int l1 = min(l0 + ZR, a.nz) - 1;
     const float z0 = (float)l0 - a.cz;
-    const float zlast = (float)l1 - a.cz;
+    const float zlast = (float)(l0 + ZR - 1) - a.cz;
 
     const bool direct = a.row_stride_direct != 0;
     const int row_stride = direct ? a.row_stride_direct : width;
     const size_t plane = (size_t)n * row_stride;
     const T* data = (const T*)a.data + (direct ? 0 : sq.y_off);
     const float kq = a.cu - (float)u0;            // tau = rel + kq
+
+    // staging map: a lane keeps one footprint column, rows strided by 256 / TW
+    constexpr int RSTEP = 256 / TW;
+    static_assert(TH % RSTEP == 0, "uniform staging trip count");
+    const int scol = threadIdx.x % TW;
+    const int srow = threadIdx.x / TW;
 
     float acc[ZR];
 #pragma unroll
@@ -92,51 +106,67 @@ __global__ __launch_bounds__(256) void k_backproject(BpArgs a) {
                 vlo = fminf(vlo, fminf(va, vb));
                 vhi = fmaxf(vhi, fmaxf(va, vb));
             }
-            meta[threadIdx.x] = make_int4((int)floorf(tlo) - 1, (int)floorf(vlo) - 1, 0, 0);
+            const int c0 = (int)floorf(tlo) - 1;
+            const int r0 = (int)floorf(vlo) - 1;
+            const int rows = min((int)floorf(vhi) + 3 - r0, TH);
+            meta[threadIdx.x] = make_int4(c0, r0, rows, 0);
             mgeo[threadIdx.x] = make_float4(t.x, t.y, dc, lc);
+            mgeo2[threadIdx.x] = make_float2(a.r * rdc, kq - (float)c0);
         }
         __syncthreads();
-        // stage the footprints: columns outside [0, width) and rows outside
-        // the detector are zero (zero extension)
+        // stage the footprints as (Y[c], Y[c+1] - Y[c]); columns outside
+        // [0, width) and rows outside the detector are zero (zero extension)
         for (int g = 0; g < gcount; ++g) {
             const int4 mt = meta[g];
             const T* pl = data + (size_t)(m0 + g) * plane;
-            for (int e = threadIdx.x; e < TH * TW; e += 256) {
-                const int rr = e / TW, cc = e % TW;
-                const int row = mt.y + rr, col = mt.x + cc;
-                float val = 0.0f;
-                if ((unsigned)row < (unsigned)n && (unsigned)col < (unsigned)width)
-                    val = S::load(pl, (size_t)row * row_stride + col);
-                tile[g][rr * TWP + cc] = val;
+            const int col = mt.x + scol;
+            const bool cok = (unsigned)col < (unsigned)width;
+            for (int rr = srow; rr < TH; rr += RSTEP) {
+                const int row = mt.y + rr;
+                float y0 = 0.0f;
+                if (rr < mt.z && cok && (unsigned)row < (unsigned)n)
+                    y0 = S::load(pl, (size_t)row * row_stride + col);
+                // the last column's pair is never read (column index <= TW - 2)
+                const float y1 = __shfl_down(y0, 1, TW);
+                if (rr < mt.z) tile[g][rr * TWP + scol] = make_float2(y0, y1 - y0);
             }
         }
         __syncthreads();
         for (int g = 0; g < gcount; ++g) {
             const float4 mg = mgeo[g];
+            const float2 mg2 = mgeo2[g];
             const int4 mt = meta[g];
             const float dl = dy * mg.x - dx * mg.y;
             const float dd = dx * mg.x + dy * mg.y;
             const float d = mg.z + dd;
-            const float rd = 1.0f / d;
-            const float tau = a.r * (dl * mg.z - mg.w * dd) * (1.0f / mg.z) * rd + kq
-                              - (float)mt.x;
-            const float invu = a.r * rd;
-            const float w = a.scale * invu * invu;
+            const float rd = __builtin_amdgcn_rcpf(d);
+            const float tau = (dl * mg.z - mg.w * dd) * mg2.x * rd + mg2.y;
+            float invu = a.r * rd;
+            float w = a.scale * invu * invu;
             const float tf = floorf(tau);
             const float fu = tau - tf;
             const int ci = min(max((int)tf, 0), TW - 2);
-            const float v0 = z0 * invu + (a.cv - (float)mt.y);
-            const float* tg = tile[g] + ci;
+            float v0 = fmaf(z0, invu, a.cv - (float)mt.y);
+            // the row index is monotone in z: check the run's ends once; a
+            // run outside the staged rows (never expected) contributes zero
+            const float vend = fmaf((float)(ZR - 1), invu, v0);
+            if (!(v0 >= 0.0f && vend < (float)(mt.z - 1))) {
+                w = 0.0f;
+                v0 = 0.5f;
+                invu = 0.0f;
+            }
+            // 32-bit LDS byte address of the thread's column in this footprint
+            uint32_t tga = (uint32_t)(uintptr_t)(lds_cptr)(tile[g] + ci);
+            asm volatile("" : "+v"(tga));   // keep it one register: address = mad24(row, pitch, tga)
 #pragma unroll
             for (int k = 0; k < ZR; ++k) {
                 const float v = fmaf((float)k, invu, v0);
-                const float vf = floorf(v);
-                const float fv = v - vf;
-                const int ri = min(max((int)vf, 0), TH - 2);
-                const float* p = tg + ri * TWP;
-                const float a00 = p[0], a01 = p[1], a10 = p[TWP], a11 = p[TWP + 1];
-                const float top = fmaf(fu, a01 - a00, a00);
-                const float bot = fmaf(fu, a11 - a10, a10);
+                const float fv = __builtin_amdgcn_fractf(v);
+                const uint32_t ri = (uint32_t)(int)v;
+                const lds_f2ptr p = (lds_f2ptr)(uintptr_t)(tga + __umul24(ri, (uint32_t)(TWP * sizeof(float2))));
+                const f2v A = p[0], B = p[TWP];
+                const float top = fmaf(fu, A.y, A.x);
+                const float bot = fmaf(fu, B.y, B.x);
                 acc[k] = fmaf(w, fmaf(fv, bot - top, top), acc[k]);
             }
         }
@@ -153,7 +183,7 @@ __global__ __launch_bounds__(256) void k_backproject(BpArgs a) {
 
 template <int ZR, int TW, int TH>
 static void launch_bp_t(const BpArgs& a, int store, dim3 grid, hipStream_t st) {
-    constexpr int G = (TW * TH <= 1024) ? 8 : (TW * TH <= 2048 ? 4 : 2);
+    constexpr int G = (TW * TH <= 1600) ? 2 : 1;
     switch (store) {
         case 0: hipLaunchKernelGGL((k_backproject<ZR, TW, TH, G, 0>), grid, dim3(256), 0, st, a); break;
         case 1: hipLaunchKernelGGL((k_backproject<ZR, TW, TH, G, 1>), grid, dim3(256), 0, st, a); break;
@@ -164,13 +194,18 @@ static void launch_bp_t(const BpArgs& a, int store, dim3 grid, hipStream_t st) {
 hipError_t launch_backproject(const BpArgs& a, int zrun, int tile_w, int tile_h, int store,
                               hipStream_t st) {
     const dim3 grid(8 * a.chunk);
-    if (zrun != 16) return hipErrorInvalidValue;
-    if (tile_w == 32 && tile_h == 32) launch_bp_t<16, 32, 32>(a, store, grid, st);
-    else if (tile_w == 32 && tile_h == 64) launch_bp_t<16, 32, 64>(a, store, grid, st);
-    else if (tile_w == 64 && tile_h == 32) launch_bp_t<16, 64, 32>(a, store, grid, st);
-    else if (tile_w == 64 && tile_h == 64) launch_bp_t<16, 64, 64>(a, store, grid, st);
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
+#define FDKOD_BP_CASE(Z, W, H) \
+    if (zrun == Z && tile_w == W && tile_h == H) { launch_bp_t<Z, W, H>(a, store, grid, st); return hipGetLastError(); }
+    FDKOD_BP_CASE(32, 32, 48)
+    FDKOD_BP_CASE(32, 32, 64)
+    FDKOD_BP_CASE(32, 64, 48)
+    FDKOD_BP_CASE(32, 64, 64)
+    FDKOD_BP_CASE(16, 32, 48)
+    FDKOD_BP_CASE(16, 32, 64)
+    FDKOD_BP_CASE(16, 64, 48)
+    FDKOD_BP_CASE(16, 64, 64)
+#undef FDKOD_BP_CASE
+    return hipErrorInvalidValue;
 }
 
 }  // namespace fdkod

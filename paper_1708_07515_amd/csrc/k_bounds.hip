@@ -60,6 +60,7 @@ __global__ __launch_bounds__(256) void k_bounds(BoundsArgs a) {
         red[1][wave] = emax;
     }
     __syncthreads();
+    __shared__ int u0s;
     if (threadIdx.x == 0) {
         const int nw = (blockDim.x + 63) >> 6;
         float lo = red[0][0], hi = red[1][0];
@@ -70,10 +71,21 @@ __global__ __launch_bounds__(256) void k_bounds(BoundsArgs a) {
         const int u0 = (int)floorf(lo + c);
         const int w = (int)floorf(hi + c) - u0 + 2;
         a.grid[q] = make_int2(u0, w);
+        u0s = u0;
     }
     for (int p = threadIdx.x; p < a.p; p += blockDim.x) {
         const float2 t = a.trig_p[p];
         a.ac_p[(size_t)q * a.p + p] = pix_pos(sq.xc, sq.yc, t.x, t.y, a.r);
+    }
+    __syncthreads();
+    // crop table in schedule order: detector index of local column 0 at the
+    // step's projection, split into its integer part and fraction
+    const float u0f = (float)u0s;
+    for (int t = threadIdx.x; t < a.nsched; t += blockDim.x) {
+        const float2 tr = a.trig_p[a.sched[t].p];
+        const float o = pix_pos(sq.xc, sq.yc, tr.x, tr.y, a.r) + u0f;
+        const float of = floorf(o);
+        a.crop[(size_t)q * a.nsched + t] = make_int2((int)of, __float_as_int(o - of));
     }
 }
 

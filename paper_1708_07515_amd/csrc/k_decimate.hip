@@ -19,6 +19,15 @@
 
 namespace fdkod {
 
+// A pointer that is the same in every lane, held in scalar registers.
+template <class T>
+__device__ __forceinline__ void* uniform_ptr(const T* p) {
+    const uint64_t v = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (void*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+
 template <int CH, int STORE>
 __global__ __launch_bounds__(256) void k_decimate(DecimArgs a) {
     using S = Store<STORE>;
@@ -28,7 +37,10 @@ __global__ __launch_bounds__(256) void k_decimate(DecimArgs a) {
     const int chunk = nblk / 8;
     const int b = blockIdx.x;
     const int lblk = (b & 7) * chunk + (b >> 3);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index is uniform across the wave; say so, so that the task's
+    // square, row and buffer resources live in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     const int task = lblk * 4 + wave;
     if (task >= a.ntasks) return;         // no barriers in this kernel
 
@@ -45,9 +57,14 @@ __global__ __launch_bounds__(256) void k_decimate(DecimArgs a) {
 
     const T* filt = (const T*)a.filt;
     T* ws = (T*)a.ws;
-    const float* acp = a.ac_p + (size_t)q * a.p;
+    const int2* crop = a.crop + (size_t)q * a.nsched;
     const int64_t yoff = a.squares[q].y_off;
     const size_t plane = (size_t)n * width;   // elements per decimated angle
+    constexpr int ES = (int)sizeof(T);
+    // per-lane byte offset of each chunk's column within the cropped run
+    int lane_off[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) lane_off[c] = (jbase + 64 * c) * ES;
 
     float acc0[CH], acc1[CH];
 #pragma unroll
@@ -56,32 +73,60 @@ __global__ __launch_bounds__(256) void k_decimate(DecimArgs a) {
         acc1[c] = 0.0f;
     }
     int m = 0;
-    for (int t = 0; t < a.nsched; ++t) {
-        const DecimStep st = a.sched[t];
-        const float o = acp[st.p] + (float)u0;      // index of local column 0
-        const float of = floorf(o);
-        const float phi = o - of;
-        const int k = (int)of;
-        const T* row = filt + ((size_t)st.p * n + v) * n;
+    // The schedule is padded to a multiple of U with zero-weight steps, so the
+    // loads of U steps are issued together before their arithmetic.  Each
+    // detector row is read through a buffer resource spanning exactly that
+    // row: the hardware range check returns zero outside [0, N), which is the
+    // zero extension of the crop (offsets below the row wrap to huge unsigned
+    // values and are out of range too).
+    constexpr int U = kDecimUnroll;
+    for (int t = 0; t < a.nsched; t += U) {
+        DecimStep st[U];
+        int2 cr[U];
+        __amdgpu_buffer_rsrc_t rs[U];
 #pragma unroll
-        for (int c = 0; c < CH; ++c) {
-            const int i0 = k + jbase + 64 * c;
-            const float x0 = ((unsigned)i0 < (unsigned)n) ? S::load(row, i0) : 0.0f;
-            const float x1 = ((unsigned)(i0 + 1) < (unsigned)n) ? S::load(row, i0 + 1) : 0.0f;
-            const float val = fmaf(phi, x1 - x0, x0);
-            acc0[c] = fmaf(st.w0, val, acc0[c]);
-            acc1[c] = fmaf(st.w1, val, acc1[c]);
+        for (int u = 0; u < U; ++u) {
+            st[u] = a.sched[t + u];
+            cr[u] = crop[t + u];
+            rs[u] = __builtin_amdgcn_make_buffer_rsrc(
+                uniform_ptr(filt + ((size_t)st[u].p * n + v) * n), (short)0, n * ES, 0x00020000);
         }
-        if (st.emit) {
-            const size_t base = (size_t)yoff + (size_t)m * plane + (size_t)v * width;
+        float x0[U][CH], x1[U][CH];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
-                const int j = jbase + 64 * c;
-                if (j < width) S::put(ws, base + j, acc0[c]);
-                acc0[c] = acc1[c];
-                acc1[c] = 0.0f;
+                // two separately range-checked loads: a negative offset is out of
+                // range as a huge unsigned value, and no in-range access relies on
+                // a wrap.  The empty asm hides that off1 = off0 + ES, so the two
+                // loads are not merged into one wider load (whose range check
+                // would zero both elements at the detector's left edge).
+                const int off0 = cr[u].x * ES + lane_off[c];
+                int off1 = off0 + ES;
+                asm volatile("" : "+v"(off1));
+                x0[u][c] = S::raw(rs[u], off0);
+                x1[u][c] = S::raw(rs[u], off1);
             }
-            ++m;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const float phi = __int_as_float(cr[u].y);
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const float val = fmaf(phi, x1[u][c] - x0[u][c], x0[u][c]);
+                acc0[c] = fmaf(st[u].w0, val, acc0[c]);
+                acc1[c] = fmaf(st[u].w1, val, acc1[c]);
+            }
+            if (st[u].emit) {
+                const size_t base = (size_t)yoff + (size_t)m * plane + (size_t)v * width;
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const int j = jbase + 64 * c;
+                    if (j < width) S::put(ws, base + j, acc0[c]);
+                    acc0[c] = acc1[c];
+                    acc1[c] = 0.0f;
+                }
+                ++m;
+            }
         }
     }
 }

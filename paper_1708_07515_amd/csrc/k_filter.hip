@@ -116,25 +116,42 @@ __global__ __launch_bounds__(256) void k_filter(FilterArgs a) {
     const int n = a.n;
     const float rr = a.r * a.r;
 
-    // load, pre-weight, first difference, zero-pad
+    // load and pre-weight (zero-padded), then take the first difference in LDS
     const float b0 = has0 ? (float)(r0 % n) - a.c : 0.0f;
     const float b1 = has1 ? (float)(r1 % n) - a.c : 0.0f;
+    const float rb0 = rr + b0 * b0, rb1 = rr + b1 * b1;
     const float* p0 = a.proj + (size_t)r0 * n;
     const float* p1 = a.proj + (size_t)r1 * n;
-    auto wgt = [&](int u, float bb) {
-        const float au = (float)u - a.c;
-        return a.r / sqrtf(rr + au * au + bb * bb);
-    };
     for (int u = t; u < M; u += TP) {
-        float d0 = 0.0f, d1 = 0.0f;
+        float x0 = 0.0f, x1 = 0.0f;
         if (u < n) {
-            if (has0) d0 = p0[u] * wgt(u, b0) - (u > 0 ? p0[u - 1] * wgt(u - 1, b0) : 0.0f);
-            if (has1) d1 = p1[u] * wgt(u, b1) - (u > 0 ? p1[u - 1] * wgt(u - 1, b1) : 0.0f);
+            const float au = (float)u - a.c;
+            if (has0) x0 = p0[u] * (a.r * rsqrtf(rb0 + au * au));
+            if (has1) x1 = p1[u] * (a.r * rsqrtf(rb1 + au * au));
         }
-        z[u] = make_float2(d0, d1);
+        z[u] = make_float2(x0, x1);
     }
-    const float last0 = has0 ? p0[n - 1] * wgt(n - 1, b0) : 0.0f;
-    const float last1 = has1 ? p1[n - 1] * wgt(n - 1, b1) : 0.0f;
+    __syncthreads();
+    constexpr int EPT = (M + TP - 1) / TP;
+    float2 dv[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int u = t + e * TP;
+        dv[e] = make_float2(0.0f, 0.0f);     // the difference at u = N is applied after the FFT
+        if (u < n) {
+            const float2 cur = z[u];
+            const float2 prev = u > 0 ? z[u - 1] : make_float2(0.0f, 0.0f);
+            dv[e] = make_float2(cur.x - prev.x, cur.y - prev.y);
+        }
+    }
+    const float2 last = z[n - 1];
+    const float last0 = last.x, last1 = last.y;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int u = t + e * TP;
+        if (u < M) z[u] = dv[e];
+    }
     __syncthreads();
     fft_lds<LOGM, TP>(z, t, a.twiddle);
     for (int k = t; k < M; k += TP) {
