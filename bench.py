@@ -6,12 +6,13 @@ A step is one pass of the whole hot path over one scan already resident in
 HBM: bounds kernel (eq. (1) at the square vertices), ramp filter, crop + shift
 + angular decimation, backprojection of every square.  GVUPS (voxel-angle
 updates per second) counts the direct-equivalent work N*N*N_z*P per step, so
-FDK-OD and direct FDK are on the same scale.  Prints one JSON line.
+FDK-OD and direct FDK are on the same scale.  The main line is the 512^3,
+P = 360 workload; the N = 2000, P = 720 workload is reported beside it
+(``large_workload``).  Prints one JSON line.
 """
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -20,10 +21,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "GVUPS FDK-OD vs direct FDK on 1 MI355X at stated rel-RMSE vs FP64 oracle"
-HBM_PEAK_GBS = 8000.0
 # FP32 VALU peak without packed FP32: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2
 VALU_PEAK_TFLOPS = 78.6
-FLOPS_PER_UPDATE = 14     # row coordinate FMA, fraction, 3 lerps (sub + FMA), weighted FMA
+# algorithmic FP32 work of one voxel-angle update: row coordinate (FMA = 2),
+# its fraction (1), three linear interpolations (sub + FMA = 3 each), weighted
+# accumulation (FMA = 2)
+FLOPS_PER_UPDATE = 14
 
 
 def parse():
@@ -37,6 +40,10 @@ def parse():
     ap.add_argument("--store", default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-direct", action="store_true", help="skip timing direct FDK")
+    ap.add_argument("--no-large", action="store_true", help="skip the N=2000 workload")
+    ap.add_argument("--cpu-slices", type=int, default=12)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device copy (for HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -51,7 +58,8 @@ def timed_steps(torch, stages, steps, warmup):
         for _, fn in stages:
             fn()
     torch.cuda.synchronize()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)] for _ in range(steps)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
+          for _ in range(steps)]
     t0 = time.perf_counter()
     for k in range(steps):
         ev[k][0].record()
@@ -66,14 +74,102 @@ def timed_steps(torch, stages, steps, warmup):
     return per, total, wall
 
 
-def cpu_baseline(proj_cpu, wl, s, k, gpu_vol):
-    """Time the FP64 oracle (single thread) on one slice of the same workload,
-    and compare that slice with the GPU result."""
-    import numpy as np
+def make_scan(torch, wl, dev):
+    from synth import phantom
+    ell = phantom.random_ellipsoids(wl.ellipsoids, wl.seed)
+    proj = phantom.project(ell, wl.n, wl.p, wl.r, device=dev)
+    if wl.photons:
+        proj = phantom.poisson_noise(proj, wl.n, wl.photons, wl.seed + 1000)
+    proj = proj.contiguous()
+    torch.cuda.synchronize()
+    return proj
+
+
+def run_workload(torch, pkg, wl, s, k, store, steps, warmup, direct=True, proj=None):
+    """Time FDK-OD steps (and direct FDK) on one workload; returns a dict."""
+    n, p, r, nz = wl.n, wl.p, wl.r, wl.nzv
+    if proj is None:
+        log(f"[bench] generating {wl.name} on the GPU")
+        proj = make_scan(torch, wl, "cuda:0")
+    plan = pkg.Plan(n, p, r, s=s, skip=k, nz=nz, store=store)
+    filt = plan.empty_filtered()
+    ws = plan.empty_workspace()
+    vol = plan.empty_volume()
+    stages = [("bounds", lambda: plan.bounds()),
+              ("filter", lambda: plan.filter(proj, filt)),
+              ("decompose", lambda: plan.decompose(filt, ws)),
+              ("reconstruct", lambda: plan.reconstruct(filt, ws, vol))]
+    log(f"[bench] {wl.name} FDK-OD s={s} k={k} store={store}: P'={plan.p_dec}, "
+        f"squares={plan.squares}, workspace {plan.workspace_bytes / 1e9:.2f} GB")
+    per, step_ms, wall = timed_steps(torch, stages, steps, warmup)
+    log(f"[bench] FDK-OD per stage (ms): " + ", ".join(f"{a}={b:.3f}" for a, b in per.items()))
+    out = dict(plan=plan, proj=proj, vol=vol, per=per, step_ms=step_ms, wall=wall, direct=None)
+    if direct:
+        dplan = pkg.Plan(n, p, r, s=0, nz=nz, store=store)
+        dvol = dplan.empty_volume()
+        dstages = [("filter", lambda: dplan.filter(proj, filt)),
+                   ("reconstruct", lambda: dplan.reconstruct(filt, None, dvol))]
+        dsteps = max(1, min(steps, 3))
+        dper, dstep_ms, _ = timed_steps(torch, dstages, dsteps, 1)
+        log(f"[bench] direct FDK per stage (ms): " + ", ".join(f"{a}={b:.3f}" for a, b in dper.items()))
+        out["direct"] = dict(ms_per_step=dstep_ms, stage_ms=dper)
+        del dvol
+        # the filter buffer was rewritten with the same values; rerun one
+        # FDK-OD step so vol holds its result for the parity sample
+        for _, fn in stages:
+            fn()
+        torch.cuda.synchronize()
+    return out
+
+
+def summarise(wl, s, k, store, res):
+    n, p, nz = wl.n, wl.p, wl.nzv
+    per, step_ms = res["per"], res["step_ms"]
+    updates_eq = n * n * nz * p
+    paper_ms = per["bounds"] + per["decompose"] + per["reconstruct"]
+    d = res["direct"]
+    return {
+        "workload": wl.name, "n": n, "nz": nz, "p": p, "r": wl.r, "s": s, "k": k,
+        "p_dec": res["plan"].p_dec, "store": store,
+        "ms_per_step": round(step_ms, 4),
+        "gvups": round(updates_eq / (step_ms * 1e-3) / 1e9, 3),
+        "stage_ms": {a: round(b, 4) for a, b in per.items()},
+        "gvups_paper_scope": round(updates_eq / (paper_ms * 1e-3) / 1e9, 3),
+        "gvups_exec_reconstruct": round(res["plan"].updates / (per["reconstruct"] * 1e-3) / 1e9, 3),
+        "direct_fdk": None if d is None else {
+            "ms_per_step": round(d["ms_per_step"], 4),
+            "gvups": round(updates_eq / (d["ms_per_step"] * 1e-3) / 1e9, 3),
+            "stage_ms": {a: round(b, 4) for a, b in d["stage_ms"].items()}},
+        "speedup_vs_direct": None if d is None else round(d["ms_per_step"] / step_ms, 3),
+        "speedup_vs_direct_paper_scope": None if d is None else
+            round(d["stage_ms"]["reconstruct"] / paper_ms, 3),
+    }
+
+
+def measured_traffic(wl, s, store):
+    """HBM bytes per backprojection launch from the committed rocprofv3 counter
+    summary, or None when the kernel source or the workload differs from the
+    one that was profiled."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "hbm_traffic.json")) as f:
+            rec = json.load(f)["k_backproject"]
+        with open(os.path.join(ROOT, "paper_1708_07515_amd", "csrc", "k_backproject.hip"), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    if sha != rec["source_sha256"] or (rec["workload"], rec["s"], rec["store"]) != (wl.name, s, store):
+        return None
+    return rec["read_bytes"] + rec["write_bytes"]
+
+
+def cpu_baseline(proj_cpu, wl, s, k, gpu_vol, count):
+    """Time the FP64 oracle (one thread) on ``count`` sampled slices of the same
+    workload, and compare those slices with the GPU result."""
     from threadpoolctl import threadpool_limits
     from oracle import fdk as ofdk, fdkod as ofdkod, metrics
 
-    sl = [wl.nzv // 2 + 7]
+    sl = list(metrics.sampled_slices(wl.nzv, count))
     arr = proj_cpu.numpy()
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
@@ -86,114 +182,91 @@ def cpu_baseline(proj_cpu, wl, s, k, gpu_vol):
     err = metrics.rel_rmse(got, ref)
     mx, mxr = metrics.max_abs(got, ref)
     gv = wl.n * wl.n * len(sl) * wl.p / dt / 1e9
-    return dict(value=gv, unit="GVUPS", cores=1, kind="oracle",
-                sample=f"1 slice (l={sl[0]}) of {wl.name}, s={s}, k={k}: {dt:.1f} s",
-                seconds=dt), dict(rel_rmse=err, max_abs=mx, max_abs_rel=mxr, slices=sl)
+    return (dict(value=gv, unit="GVUPS", cores=1, kind="oracle",
+                 sample=f"{len(sl)} sampled slices (incl. top and bottom) of {wl.name}, "
+                        f"s={s}, k={k}, FP64 NumPy, one thread: {dt:.1f} s",
+                 seconds=round(dt, 2)),
+            dict(rel_rmse=err, max_abs=mx, max_abs_rel=mxr, slices=[int(x) for x in sl]))
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path "
-              "shards by z-slab across GPUs but that is not built here", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the path would "
+              "shard by z-slab across GPUs, which this build does not include", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     import paper_1708_07515_amd as pkg
-    from synth import configs, phantom
+    from synth import configs
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 1 GiB read + 1 GiB written")
+        del a, b
 
     wl = configs.ALL[args.workload]
     s = args.s if args.s is not None else max(wl.s)
     k = args.skip if args.skip is not None else wl.k
     store = args.store or wl.store[0]
-    n, p, r, nz = wl.n, wl.p, wl.r, wl.nzv
-    dev = "cuda:0"
-
-    log(f"[bench] generating {wl.name} on the GPU")
-    ell = phantom.random_ellipsoids(wl.ellipsoids, wl.seed)
-    proj = phantom.project(ell, n, p, r, device=dev)
-    if wl.photons:
-        proj = phantom.poisson_noise(proj, n, wl.photons, wl.seed + 1000)
-    proj = proj.contiguous()
-    torch.cuda.synchronize()
-
-    plan = pkg.Plan(n, p, r, s=s, skip=k, nz=nz, store=store)
-    filt = plan.empty_filtered()
-    ws = plan.empty_workspace()
-    vol = plan.empty_volume()
-    stages = [("bounds", lambda: plan.bounds()),
-              ("filter", lambda: plan.filter(proj, filt)),
-              ("decompose", lambda: plan.decompose(filt, ws)),
-              ("reconstruct", lambda: plan.reconstruct(filt, ws, vol))]
-    log(f"[bench] FDK-OD s={s} k={k} store={store}: P'={plan.p_dec}, squares={plan.squares}, "
-        f"workspace {plan.workspace_bytes / 1e9:.2f} GB")
-    per, step_ms, wall = timed_steps(torch, stages, args.steps, args.warmup)
-    log(f"[bench] FDK-OD per stage (ms): " + ", ".join(f"{a}={b:.3f}" for a, b in per.items()))
-
-    direct = None
-    if not args.no_direct:
-        dplan = pkg.Plan(n, p, r, s=0, nz=nz, store=store)
-        dvol = dplan.empty_volume()
-        dstages = [("filter", lambda: dplan.filter(proj, filt)),
-                   ("reconstruct", lambda: dplan.reconstruct(filt, None, dvol))]
-        dsteps = max(1, min(args.steps, 3))
-        dper, dstep_ms, _ = timed_steps(torch, dstages, dsteps, 1)
-        direct = dict(ms_per_step=dstep_ms, stage_ms=dper,
-                      gvups=n * n * nz * p / (dstep_ms * 1e-3) / 1e9,
-                      gvups_reconstruct=n * n * nz * p / (dper["reconstruct"] * 1e-3) / 1e9)
-        log(f"[bench] direct FDK per stage (ms): " + ", ".join(f"{a}={b:.3f}" for a, b in dper.items()))
-        # the filter buffer was overwritten with the same values; rerun once to
-        # leave the FDK-OD output in place for the parity sample
-        for _, fn in stages:
-            fn()
-        torch.cuda.synchronize()
-
-    updates_eq = n * n * nz * p
-    value = updates_eq / (step_ms * 1e-3) / 1e9
-    paper_ms = per["bounds"] + per["decompose"] + per["reconstruct"]
-    rec_ms = per["reconstruct"]
-    flops = FLOPS_PER_UPDATE * plan.updates
-    achieved = flops / (rec_ms * 1e-3) / 1e12
+    res = run_workload(torch, pkg, wl, s, k, store, args.steps, args.warmup,
+                       direct=not args.no_direct)
+    main_sum = summarise(wl, s, k, store, res)
+    plan = res["plan"]
+    rec_ms = res["per"]["reconstruct"]
+    achieved = FLOPS_PER_UPDATE * plan.updates / (rec_ms * 1e-3) / 1e12
     roofline = dict(bound="alu", kernel="k_backproject", achieved=round(achieved, 3),
-                    peak=VALU_PEAK_TFLOPS, unit="TFLOP/s", frac=round(achieved / VALU_PEAK_TFLOPS, 4),
-                    traffic=None, flops_per_update=FLOPS_PER_UPDATE, updates=plan.updates)
+                    peak=VALU_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / VALU_PEAK_TFLOPS, 4),
+                    traffic=measured_traffic(wl, s, store),
+                    flops_per_update=FLOPS_PER_UPDATE, updates=plan.updates,
+                    avg_ms=round(rec_ms, 4))
 
     cpu = parity = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a bounded sample")
-        cpu, parity = cpu_baseline(proj.cpu(), wl, s, k, vol)
+        cpu, parity = cpu_baseline(res["proj"].cpu(), wl, s, k, res["vol"], args.cpu_slices)
+    del res
+
+    large = None
+    if not args.no_large and wl.name != "cone2000_p720":
+        torch.cuda.empty_cache()
+        lw = configs.C5
+        lres = run_workload(torch, pkg, lw, max(lw.s), lw.k, lw.store[0], 2, 1,
+                            direct=not args.no_direct)
+        large = summarise(lw, max(lw.s), lw.k, lw.store[0], lres)
+        del lres
+        torch.cuda.empty_cache()
 
     out = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": main_sum["gvups"],
         "unit": "GVUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(step_ms, 4),
+        "ms_per_step": main_sum["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if store == "f32" else f"{store}-storage/f32",
         "data": f"synthetic: seeded {wl.ellipsoids}-ellipsoid phantom"
                 + (f", Poisson noise {wl.photons:g} photons" if wl.photons else ""),
-        "config": {"workload": wl.name, "n": n, "nz": nz, "p": p, "r": r, "s": s, "k": k,
-                   "p_dec": plan.p_dec, "store": store},
-        "stage_ms": {a: round(b, 4) for a, b in per.items()},
-        "gvups_paper_scope": round(updates_eq / (paper_ms * 1e-3) / 1e9, 3),
-        "gvups_exec_reconstruct": round(plan.updates / (rec_ms * 1e-3) / 1e9, 3),
-        "direct_fdk": None if direct is None else {
-            "ms_per_step": round(direct["ms_per_step"], 4),
-            "gvups": round(direct["gvups"], 3),
-            "stage_ms": {a: round(b, 4) for a, b in direct["stage_ms"].items()}},
-        "speedup_vs_direct": None if direct is None else round(direct["ms_per_step"] / step_ms, 3),
-        "speedup_vs_direct_paper_scope": None if direct is None else
-            round(direct["stage_ms"]["reconstruct"] / paper_ms, 3),
+        "config": {"workload": wl.name, "n": wl.n, "nz": wl.nzv, "p": wl.p, "r": wl.r,
+                   "s": s, "k": k, "p_dec": main_sum["p_dec"], "store": store},
+        "stage_ms": main_sum["stage_ms"],
+        "gvups_paper_scope": main_sum["gvups_paper_scope"],
+        "gvups_exec_reconstruct": main_sum["gvups_exec_reconstruct"],
+        "direct_fdk": main_sum["direct_fdk"],
+        "speedup_vs_direct": main_sum["speedup_vs_direct"],
+        "speedup_vs_direct_paper_scope": main_sum["speedup_vs_direct_paper_scope"],
         "parity": parity,
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "wall_s_timed": round(wall, 4),
+        "large_workload": large,
     }
     print(json.dumps(out), flush=True)
 
