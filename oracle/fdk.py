@@ -129,7 +129,10 @@ def filter_rows(proj, r, rows):
     n = proj.shape[2]
     nv = proj.shape[1]
     pw = np.asarray(proj[:, rows, :], dtype=np.float64) * cosine_weight(n, r, rows)[None]
-    return FilteredRows(rows, ramp_filter(pw), nv)
+    # the Toeplitz product is the definition; above 512 columns the same linear
+    # convolution is taken by FFT (equal to 1e-10, see the filter pins)
+    filt = ramp_filter(pw) if n <= 512 else ramp_filter_fft(pw)
+    return FilteredRows(rows, filt, nv)
 
 
 def rows_for_points(n, r, betas, x, y, z):

@@ -1,0 +1,100 @@
+"""GPU parity at the full workload sizes, on outputs the FP64 oracle can
+compute one by one: sampled slices (1024^3) and sampled voxel clusters
+(2000^3), in the same launch configuration that bench.py times."""
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1708_07515_amd as pkg
+from oracle import fdkod as ofdkod, metrics
+from gpu_common import DEV, log, report, require_gpu
+from synth import configs, phantom
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+class DeviceRows:
+    """Array-like view of projections resident on the GPU: the oracle's
+    proj[:, rows, :] copies only those detector rows to the host."""
+
+    def __init__(self, t):
+        self.t = t
+        self.shape = tuple(t.shape)
+
+    def __getitem__(self, key):
+        _, rows, _ = key
+        idx = torch.as_tensor(np.asarray(rows), device=self.t.device)
+        return self.t.index_select(1, idx).cpu().numpy()
+
+
+def reconstruct(proj, wl, s, store):
+    with pkg.Plan(wl.n, wl.p, wl.r, s=s, skip=wl.k, nz=wl.nzv, store=store) as plan:
+        filt = plan.empty_filtered()
+        vol = plan.empty_volume()
+        ws = plan.empty_workspace()
+        plan.filter(proj, filt)
+        plan.backproject(filt, vol, ws)
+        torch.cuda.synchronize()
+        del filt, ws
+        return vol
+
+
+def scan_on_gpu(wl):
+    ell = phantom.random_ellipsoids(wl.ellipsoids, wl.seed)
+    proj = phantom.project(ell, wl.n, wl.p, wl.r, device=DEV).contiguous()
+    torch.cuda.synchronize()
+    return proj
+
+
+def test_precision_forms_1024():
+    # cone1024_p720, s=3: filtered and decimated data stored as FP32, FP16 and
+    # BF16 with FP32 arithmetic; errors against the plain FP64 oracle on the
+    # top and the central slice
+    wl = configs.C3
+    s = 3
+    proj = scan_on_gpu(wl)
+    slices = [0, wl.nzv // 2]
+    ref = ofdkod.fdkod(DeviceRows(proj), wl.r, s, wl.k, slices=slices, nz=wl.nzv)
+    tol = {"f32": 1e-4, "f16": 2e-3, "bf16": 2e-3}
+    for store in ("f32", "f16", "bf16"):
+        vol = reconstruct(proj, wl, s, store)
+        got = vol[slices].double().cpu().numpy()
+        del vol
+        torch.cuda.empty_cache()
+        err, _ = report(f"cone1024_p720 s=3 {store} slices {slices}", got, ref)
+        assert err <= tol[store]
+
+
+def _clusters(n, nz):
+    # 4x4 (x, y) patches on two slices at the centre, an edge and a corner,
+    # the top and bottom slices included
+    out = []
+    for (l, j, i) in [(0, n // 2 - 2, n // 2 - 2), (nz - 1, 3, n - 7), (nz // 2, n - 5, 2),
+                      (nz // 3, n // 4, 3 * n // 4)]:
+        for dl in (0, 1):
+            for dj in range(4):
+                for di in range(4):
+                    out.append((min(l + dl, nz - 1), j + dj, i + di))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("store,tol", [("bf16", 2e-3), ("f32", 1e-4)])
+def test_n2000_sampled_voxels(store, tol):
+    wl = configs.C5
+    s = max(wl.s)
+    proj = scan_on_gpu(wl)
+    idx = _clusters(wl.n, wl.nzv)
+    vol = reconstruct(proj, wl, s, store)
+    got = vol[idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy()
+    del vol
+    torch.cuda.empty_cache()
+    log(f"oracle on {len(idx)} voxels of cone2000_p720")
+    ref = ofdkod.fdkod_points(DeviceRows(proj), wl.r, s, wl.k, idx, nz=wl.nzv)
+    err, _ = report(f"cone2000_p720 s={s} {store} {len(idx)} voxels", got, ref)
+    assert err <= tol
