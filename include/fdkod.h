@@ -145,6 +145,82 @@ fdkod_status fdkod_reconstruct(fdkod_plan_t plan, const void* filt, const void* 
 fdkod_status fdkod_backproject(fdkod_plan_t plan, const void* filt, float* vol,
                                void* ws, fdkod_stream_t stream);
 
+/* ------------------------------------------------------------------ tuning
+ * Kernel shapes are chosen per plan: the backprojection's slices per thread
+ * and LDS footprint / angles per stage, and the decimation's column chunks.
+ * fdkod_plan_create picks a default that holds the plan's geometry (or the
+ * entry of the file named by the environment variable FDKOD_TUNE_CACHE);
+ * fdkod_tune measures the alternatives.                                    */
+typedef struct {
+    int32_t z_run;            /* slices per backprojection thread: 16 or 32 */
+    int32_t tile_w, tile_h;   /* LDS footprint of a 16 x 16 x z_run block: 32/64 x 48/64 */
+    int32_t angles_per_stage; /* angles staged in LDS per barrier: 1, 2 or 4 */
+    int32_t decim_chunks;     /* 64-column chunks per decimation wavefront: 1, 2, 4 or 8 */
+    float bp_ms;              /* backprojection time measured by fdkod_tune (else 0) */
+    float decim_ms;           /* decimation time measured by fdkod_tune (else 0) */
+} fdkod_tuning;
+
+/* The plan's current kernel shapes. */
+fdkod_status fdkod_get_tuning(fdkod_plan_t plan, fdkod_tuning* out);
+
+/* Apply kernel shapes; E_UNSUPPORTED if the variant does not exist or its LDS
+ * footprint cannot hold the plan's block footprint (the plan is unchanged). */
+fdkod_status fdkod_set_tuning(fdkod_plan_t plan, const fdkod_tuning* t);
+
+/* Autotuner: times every valid backprojection variant (fdkod_reconstruct)
+ * and decimation chunking (fdkod_decompose) on the caller's buffers and
+ * stream (one warm-up and three timed runs each), applies the fastest and
+ * returns it.  Overwrites vol and ws.  Synchronises the stream; not for use
+ * under graph capture.  When FDKOD_TUNE_CACHE names a file, the choice is
+ * appended to it, keyed by device and plan parameters. */
+fdkod_status fdkod_tune(fdkod_plan_t plan, const void* filt, void* ws, float* vol,
+                        fdkod_stream_t stream, fdkod_tuning* out);
+
+/* ------------------------------------------------------------------ batches
+ * Many volumes of different sizes reconstructed together (the decomposition of
+ * Sec. 2.1 applied to every volume): one grouped decimation launch over all
+ * volumes' (square, row) tasks and one persistent backprojection launch whose
+ * workgroups take (volume, square, 16 x 16 tile, slab) items from a ticket
+ * queue, largest first.  The launch sequence can be captured in a hipGraph. */
+typedef struct fdkod_batch_s* fdkod_batch_t;
+
+/* Create a batch of `count` plans (1..4096) on `device`; every plan is
+ * validated and created as by fdkod_plan_create.  All must share the store
+ * type.  Synchronises. */
+fdkod_status fdkod_batch_create(const fdkod_params* prms, int32_t count, int device,
+                                fdkod_batch_t* out);
+fdkod_status fdkod_batch_destroy(fdkod_batch_t batch);
+
+/* The plan of volume `index` (owned by the batch; do not destroy). */
+fdkod_status fdkod_batch_plan(fdkod_batch_t batch, int32_t index, fdkod_plan_t* out);
+
+/* Bind the device buffers of every volume (host arrays of `count` device
+ * pointers, laid out as for the single-plan calls; ws[i] may be NULL when
+ * volume i has s = 0).  Copies the pointer tables to the device
+ * (synchronously) and invalidates a captured graph. */
+fdkod_status fdkod_batch_bind(fdkod_batch_t batch, const float* const* proj, void* const* filt,
+                              void* const* ws, float* const* vol);
+
+/* Enqueue bounds and filtering of every volume, the grouped decimation and the
+ * persistent backprojection on `stream`.  Asynchronous, allocates nothing;
+ * capture-safe (the ticket counter is cleared by a kernel, not a memset). */
+fdkod_status fdkod_batch_run(fdkod_batch_t batch, fdkod_stream_t stream);
+
+/* Capture fdkod_batch_run on `stream` (not the null stream) into a hipGraph
+ * and instantiate it; fdkod_batch_replay launches it on any stream. */
+fdkod_status fdkod_batch_capture(fdkod_batch_t batch, fdkod_stream_t stream);
+fdkod_status fdkod_batch_replay(fdkod_batch_t batch, fdkod_stream_t stream);
+
+/* Autotuner for the batch: times the persistent backprojection variants that
+ * hold every volume's footprint and the decimation chunkings on the bound
+ * buffers, applies the fastest (and invalidates a captured graph). */
+fdkod_status fdkod_batch_tune(fdkod_batch_t batch, fdkod_stream_t stream, fdkod_tuning* out);
+
+/* Work items of the persistent launch, its workgroups, and the direct-
+ * equivalent voxel-angle updates of one run (sum over volumes N^2 N_z P). */
+fdkod_status fdkod_batch_info(fdkod_batch_t batch, int64_t* items, int32_t* blocks,
+                              int64_t* updates_eq);
+
 /* Copy the bounds tables to host memory (any pointer may be NULL to skip):
  *   ac_p    float [4^s][P]   a_c(beta_p), centre trajectory at original angles
  *   ac_m    float [4^s][P']  a_c(beta'_m) at decimated angles

@@ -5,7 +5,7 @@ of the reconstruction runs in the library's HIP kernels; this package only
 marshals arguments.  Torch tensors supply device memory and streams.
 """
 
-from ._lib import (FdkodError, Plan, STORE_TYPES, library_path, load_library,  # noqa: F401
-                   validate)
+from ._lib import (Batch, FdkodError, Plan, STORE_TYPES, library_path,  # noqa: F401
+                   load_library, validate)
 
-__all__ = ["Plan", "FdkodError", "validate", "load_library", "library_path", "STORE_TYPES"]
+__all__ = ["Plan", "Batch", "FdkodError", "validate", "load_library", "library_path", "STORE_TYPES"]

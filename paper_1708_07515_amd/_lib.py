@@ -40,6 +40,16 @@ class Info(ctypes.Structure):
                 ("updates", ctypes.c_int64)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("z_run", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("angles_per_stage", ctypes.c_int32), ("decim_chunks", ctypes.c_int32),
+                ("bp_ms", ctypes.c_float), ("decim_ms", ctypes.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_VP = ctypes.c_void_p
 EXPORTS = {
     "fdkod_validate": (ctypes.c_int, [ctypes.POINTER(Params)]),
     "fdkod_plan_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int,
@@ -56,6 +66,21 @@ EXPORTS = {
     "fdkod_backproject": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p]),
     "fdkod_get_bounds": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 7),
+    "fdkod_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning)]),
+    "fdkod_set_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning)]),
+    "fdkod_tune": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(Tuning)]),
+    "fdkod_batch_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_int,
+                                          ctypes.POINTER(_VP)]),
+    "fdkod_batch_destroy": (ctypes.c_int, [_VP]),
+    "fdkod_batch_plan": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(_VP)]),
+    "fdkod_batch_bind": (ctypes.c_int, [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                                        ctypes.POINTER(_VP), ctypes.POINTER(_VP)]),
+    "fdkod_batch_run": (ctypes.c_int, [_VP, _VP]),
+    "fdkod_batch_capture": (ctypes.c_int, [_VP, _VP]),
+    "fdkod_batch_replay": (ctypes.c_int, [_VP, _VP]),
+    "fdkod_batch_tune": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(Tuning)]),
+    "fdkod_batch_info": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
     "fdkod_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "fdkod_last_error": (ctypes.c_char_p, []),
     "fdkod_version": (ctypes.c_int32, []),
@@ -111,19 +136,45 @@ def _stream_ptr(stream):
 class Plan:
     """An FDK-OD plan: geometry tables on one device, sizes of the buffers."""
 
-    def __init__(self, n, p, r, s=0, skip=0, nz=0, store="f32", device=0):
+    def __init__(self, n, p, r, s=0, skip=0, nz=0, store="f32", device=0, _handle=None):
         self._lib = load_library()
         self.params = _params(n, p, r, s, skip, nz, store)
         self.n, self.p, self.r, self.s, self.skip = int(n), int(p), float(r), int(s), int(skip)
         self.nz = int(nz) or int(n)
         self.store = self.params.store
         self.device = int(device)
-        h = ctypes.c_void_p()
-        _check(self._lib.fdkod_plan_create(ctypes.byref(self.params), self.device, ctypes.byref(h)))
+        self._owned = _handle is None
+        if _handle is None:
+            h = ctypes.c_void_p()
+            _check(self._lib.fdkod_plan_create(ctypes.byref(self.params), self.device, ctypes.byref(h)))
+        else:
+            h = _handle
         self._h = h
         info = Info()
         _check(self._lib.fdkod_plan_info(h, ctypes.byref(info)))
         self.info = info
+
+    # kernel shapes ----------------------------------------------------------
+    def get_tuning(self):
+        t = Tuning()
+        _check(self._lib.fdkod_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        t = Tuning()
+        _check(self._lib.fdkod_get_tuning(self._h, ctypes.byref(t)))
+        for k, v in kw.items():
+            setattr(t, k, v)
+        _check(self._lib.fdkod_set_tuning(self._h, ctypes.byref(t)))
+
+    def tune(self, filt, ws, vol, stream=None):
+        """Autotune on the given buffers (overwrites vol and ws); returns the choice."""
+        t = Tuning()
+        _check(self._lib.fdkod_tune(self._h, ctypes.c_void_p(filt.data_ptr()),
+                                    ctypes.c_void_p(ws.data_ptr() if ws is not None else 0),
+                                    ctypes.c_void_p(vol.data_ptr()), _stream_ptr(stream),
+                                    ctypes.byref(t)))
+        return t.as_dict()
 
     # sizes ---------------------------------------------------------------
     @property
@@ -243,8 +294,86 @@ class Plan:
         return dict(ac_p=ac_p, ac_m=ac_m, amin=amin, amax=amax, u0=u0, width=width, rect=rect)
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and getattr(self, "_owned", True):
             self._lib.fdkod_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Batch:
+    """Many volumes reconstructed together: grouped decimation, one persistent
+    backprojection launch, optional hipGraph capture."""
+
+    def __init__(self, volumes, store="f32", device=0):
+        """volumes: list of dicts with keys n, p, r and optional s, skip, nz."""
+        self._lib = load_library()
+        self.device = int(device)
+        prms = [_params(v["n"], v["p"], v["r"], v.get("s", 0), v.get("skip", 0), v.get("nz", 0), store)
+                for v in volumes]
+        arr = (Params * len(prms))(*prms)
+        h = ctypes.c_void_p()
+        _check(self._lib.fdkod_batch_create(arr, len(prms), self.device, ctypes.byref(h)))
+        self._h = h
+        self.plans = []
+        for i, v in enumerate(volumes):
+            ph = ctypes.c_void_p()
+            _check(self._lib.fdkod_batch_plan(h, i, ctypes.byref(ph)))
+            self.plans.append(Plan(v["n"], v["p"], v["r"], v.get("s", 0), v.get("skip", 0),
+                                   v.get("nz", 0), store, device, _handle=ph))
+        self._bound = None
+
+    def __len__(self):
+        return len(self.plans)
+
+    def bind(self, proj, filt, ws, vol):
+        """Lists of tensors, one per volume (ws entries may be None for s = 0)."""
+        n = len(self.plans)
+        for i, pl in enumerate(self.plans):
+            import torch
+            pl._chk(proj[i], (pl.p, pl.n, pl.n), torch.float32, f"proj[{i}]")
+            pl._chk(filt[i], (pl.p, pl.n, pl.n), pl.store_torch_dtype(), f"filt[{i}]")
+            pl._chk(vol[i], (pl.nz, pl.n, pl.n), torch.float32, f"vol[{i}]")
+            pl._chk_ws(ws[i])
+        ptrs = lambda ts: (_VP * n)(*[t.data_ptr() if t is not None else 0 for t in ts])  # noqa: E731
+        _check(self._lib.fdkod_batch_bind(self._h, ptrs(proj), ptrs(filt), ptrs(ws), ptrs(vol)))
+        self._bound = (list(proj), list(filt), list(ws), list(vol))   # keep the tensors alive
+
+    def run(self, stream=None):
+        _check(self._lib.fdkod_batch_run(self._h, _stream_ptr(stream)))
+
+    def capture(self, stream):
+        _check(self._lib.fdkod_batch_capture(self._h, ctypes.c_void_p(stream.cuda_stream)))
+
+    def replay(self, stream=None):
+        _check(self._lib.fdkod_batch_replay(self._h, _stream_ptr(stream)))
+
+    def tune(self, stream=None):
+        t = Tuning()
+        _check(self._lib.fdkod_batch_tune(self._h, _stream_ptr(stream), ctypes.byref(t)))
+        return t.as_dict()
+
+    def info(self):
+        items, blocks, upd = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+        _check(self._lib.fdkod_batch_info(self._h, ctypes.byref(items), ctypes.byref(blocks),
+                                          ctypes.byref(upd)))
+        return dict(items=items.value, blocks=blocks.value, updates_eq=upd.value)
+
+    def close(self):
+        for p in self.plans:
+            p._h = None
+        if getattr(self, "_h", None):
+            self._lib.fdkod_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -1,0 +1,379 @@
+// Batches of uneven volumes (C ABI in include/fdkod.h): every volume keeps its
+// own plan (squares, bounds, schedule); the decimation of all volumes runs as
+// one grouped launch and the backprojection as one persistent launch that
+// takes (volume, square, tile, slab) items from a ticket queue, largest first.
+// The launch sequence is capture-safe and can be replayed as a hipGraph.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "fdkod.h"
+#include "internal.h"
+#include "plan.h"
+
+using namespace fdkod;
+
+struct fdkod_batch_s {
+    int device = 0, count = 0, store = 0;
+    std::vector<fdkod_plan_t> plans;
+    BpVariant bpv{32, 32, 48, 2};
+    int dec_chunks = 1;
+    int bp_blocks = 0;
+    int nitems = 0;
+    int64_t updates_eq = 0;
+    // device tables
+    BatchItem* d_items = nullptr;
+    int items_cap = 0;
+    BpVol* d_vols = nullptr;
+    DecimVol* d_dvols = nullptr;
+    int* d_task_start = nullptr;
+    unsigned* d_counter = nullptr;
+    std::vector<void*> allocs;
+    // bound buffers
+    bool bound = false;
+    std::vector<const float*> proj;
+    std::vector<void*> filt, ws;
+    std::vector<float*> vol;
+    int ndec = 0, dec_ntasks = 0;
+    // captured launch sequence
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void drop_graph(fdkod_batch_t b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+void release_batch(fdkod_batch_t b) {
+    if (!b) return;
+    drop_graph(b);
+    int prev = 0;
+    if (hipGetDevice(&prev) == hipSuccess) {
+        (void)hipSetDevice(b->device);
+        for (void* p : b->allocs) (void)hipFree(p);
+        (void)hipSetDevice(prev);
+    }
+    for (fdkod_plan_t p : b->plans) fdkod_plan_destroy(p);
+    delete b;
+}
+
+// A variant usable by every volume of the batch.
+bool holds_all(const fdkod_batch_t b, const BpVariant& v) {
+    for (fdkod_plan_t p : b->plans)
+        if (!variant_holds(p, v)) return false;
+    return true;
+}
+
+// Work items of the persistent backprojection for the current z run, ordered
+// by decreasing work (tile voxels x decimated angles), ties by volume.
+fdkod_status build_items(fdkod_batch_t b) {
+    std::vector<std::pair<int64_t, BatchItem>> w;
+    for (int vb = 0; vb < b->count; ++vb) {
+        const fdkod_plan_s* pl = b->plans[vb];
+        const int nzt = bp_zslabs(pl->nz, b->bpv.zrun);
+        for (int q = 0; q < pl->nsq; ++q) {
+            const SquareDesc& d = pl->sq[q];
+            for (int y = d.y0; y < d.y1; y += kTileXY)
+                for (int x = d.x0; x < d.x1; x += kTileXY) {
+                    const int64_t vox = (int64_t)std::min(kTileXY, d.x1 - x) * std::min(kTileXY, d.y1 - y);
+                    for (int zt = 0; zt < nzt; ++zt) {
+                        const int zc = std::min(b->bpv.zrun, pl->nz - zt * b->bpv.zrun);
+                        w.push_back({vox * zc * pl->pd, BatchItem{vb, q, x, y, zt, 0, 0, 0}});
+                    }
+                }
+        }
+    }
+    std::stable_sort(w.begin(), w.end(), [](const auto& a, const auto& c) { return a.first > c.first; });
+    if ((int64_t)w.size() > (int64_t)1 << 30) return fail(FDKOD_E_UNSUPPORTED, "too many work items");
+    std::vector<BatchItem> items(w.size());
+    for (size_t i = 0; i < w.size(); ++i) items[i] = w[i].second;
+    if ((int)items.size() > b->items_cap) {
+        fdkod_status st = dev_alloc(b->allocs, (void**)&b->d_items, sizeof(BatchItem) * items.size());
+        if (st != FDKOD_OK) return st;
+        b->items_cap = (int)items.size();
+    }
+    HIP_TRY(hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice),
+            "hipMemcpy items");
+    b->nitems = (int)items.size();
+    const int occ = backproject_batch_occupancy(b->bpv, b->store);
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, b->device), "hipGetDeviceProperties");
+    b->bp_blocks = std::max(1, occ) * prop.multiProcessorCount;
+    return FDKOD_OK;
+}
+
+// Per-volume argument tables for the bound buffers and the current chunking.
+fdkod_status upload_tables(fdkod_batch_t b) {
+    std::vector<BpVol> vols(b->count);
+    std::vector<DecimVol> dvols;
+    std::vector<int> start{0};
+    for (int vb = 0; vb < b->count; ++vb) {
+        const fdkod_plan_s* pl = b->plans[vb];
+        vols[vb] = bp_vol(pl, b->filt[vb], b->ws[vb], b->vol[vb]);
+        if (pl->s > 0) {
+            dvols.push_back(decim_args(pl, b->filt[vb], b->ws[vb], b->dec_chunks));
+            start.push_back(start.back() + dvols.back().ntasks);
+        }
+    }
+    b->ndec = (int)dvols.size();
+    b->dec_ntasks = start.back();
+    HIP_TRY(hipMemcpy(b->d_vols, vols.data(), sizeof(BpVol) * vols.size(), hipMemcpyHostToDevice),
+            "hipMemcpy volumes");
+    if (!dvols.empty()) {
+        HIP_TRY(hipMemcpy(b->d_dvols, dvols.data(), sizeof(DecimVol) * dvols.size(), hipMemcpyHostToDevice),
+                "hipMemcpy decimation volumes");
+        HIP_TRY(hipMemcpy(b->d_task_start, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice),
+                "hipMemcpy task offsets");
+    }
+    return FDKOD_OK;
+}
+
+fdkod_status run_decimate(fdkod_batch_t b, hipStream_t st) {
+    if (b->ndec == 0) return FDKOD_OK;
+    DecimBatchArgs a{b->d_dvols, b->d_task_start, b->ndec, b->dec_ntasks};
+    HIP_TRY(launch_decimate_batch(a, b->dec_chunks, b->store, st), "batched decimation launch");
+    return FDKOD_OK;
+}
+
+fdkod_status run_backproject(fdkod_batch_t b, hipStream_t st) {
+    HIP_TRY(launch_reset_counter(b->d_counter, st), "counter reset launch");
+    BpBatchArgs a{b->d_vols, b->d_items, b->nitems, b->d_counter};
+    HIP_TRY(launch_backproject_batch(a, b->bpv, b->store, b->bp_blocks, st), "persistent backprojection launch");
+    return FDKOD_OK;
+}
+
+template <class F>
+fdkod_status time_ms(hipStream_t st, int reps, F fn, float* ms) {
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+    fdkod_status r = fn();
+    if (r == FDKOD_OK) {
+        (void)hipEventRecord(e0, st);
+        for (int i = 0; i < reps && r == FDKOD_OK; ++i) r = fn();
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float t = 0.0f;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        *ms = t / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+fdkod_status fdkod_batch_create(const fdkod_params* prms, int32_t count, int device, fdkod_batch_t* out) {
+    if (!out) return fail(FDKOD_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!prms || count < 1 || count > 4096) return fail(FDKOD_E_ARG, "count must be in [1, 4096]");
+    for (int i = 0; i < count; ++i) {
+        fdkod_status st = fdkod_validate(&prms[i]);
+        if (st != FDKOD_OK) return st;
+        if (prms[i].store != prms[0].store) return fail(FDKOD_E_ARG, "all volumes of a batch share the store type");
+    }
+    fdkod_batch_t b = new fdkod_batch_s();
+    b->device = device;
+    b->count = count;
+    b->store = prms[0].store;
+    for (int i = 0; i < count; ++i) {
+        fdkod_plan_t p = nullptr;
+        fdkod_status st = fdkod_plan_create(&prms[i], device, &p);
+        if (st != FDKOD_OK) {
+            release_batch(b);
+            return st;
+        }
+        b->plans.push_back(p);
+        b->updates_eq += (int64_t)p->n * p->n * p->nz * p->p;
+    }
+    int prev = 0;
+    HIP_TRY(hipGetDevice(&prev), "hipGetDevice");
+    HIP_TRY(hipSetDevice(device), "hipSetDevice");
+    auto bail = [&](fdkod_status code) {
+        release_batch(b);
+        (void)hipSetDevice(prev);
+        return code;
+    };
+    // common kernel shapes: the longest z run every volume supports, the
+    // largest footprint among the volumes, chunks for the widest square
+    bool ok = false;
+    for (int zr : {32, 16}) {
+        int tw = 0, th = 0;
+        bool all = true;
+        for (fdkod_plan_t p : b->plans) {
+            int w = 0, h = 0;
+            if (!bp_tiles_for(p->n, p->nz, p->r, zr, &w, &h)) {
+                all = false;
+                break;
+            }
+            tw = std::max(tw, w);
+            th = std::max(th, h);
+        }
+        if (!all) continue;
+        b->bpv = BpVariant{zr, tw, th, 2};
+        if (!backproject_variant_exists(b->bpv)) b->bpv.g = 1;
+        ok = holds_all(b, b->bpv);
+        if (ok) break;
+    }
+    if (!ok) return bail(fail(FDKOD_E_UNSUPPORTED, "no backprojection variant holds every volume"));
+    int wmax = 0;
+    for (fdkod_plan_t p : b->plans)
+        if (p->s > 0) wmax = std::max(wmax, p->wmax);
+    b->dec_chunks = 1;
+    while (b->dec_chunks < 8 && 64 * b->dec_chunks < wmax) b->dec_chunks <<= 1;
+
+    fdkod_status st;
+    if ((st = dev_alloc(b->allocs, (void**)&b->d_vols, sizeof(BpVol) * count)) != FDKOD_OK) return bail(st);
+    if ((st = dev_alloc(b->allocs, (void**)&b->d_dvols, sizeof(DecimVol) * count)) != FDKOD_OK) return bail(st);
+    if ((st = dev_alloc(b->allocs, (void**)&b->d_task_start, sizeof(int) * (count + 1))) != FDKOD_OK)
+        return bail(st);
+    if ((st = dev_alloc(b->allocs, (void**)&b->d_counter, 256)) != FDKOD_OK) return bail(st);
+    if ((st = build_items(b)) != FDKOD_OK) return bail(st);
+    (void)hipSetDevice(prev);
+    *out = b;
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_batch_destroy(fdkod_batch_t batch) {
+    release_batch(batch);
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_batch_plan(fdkod_batch_t b, int32_t index, fdkod_plan_t* out) {
+    if (!b || !out || index < 0 || index >= b->count) return fail(FDKOD_E_ARG, "bad batch index");
+    *out = b->plans[index];
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_batch_bind(fdkod_batch_t b, const float* const* proj, void* const* filt,
+                              void* const* ws, float* const* vol) {
+    if (!b || !proj || !filt || !ws || !vol) return fail(FDKOD_E_ARG, "NULL argument");
+    for (int i = 0; i < b->count; ++i)
+        if (!proj[i] || !filt[i] || !vol[i] || (b->plans[i]->s > 0 && !ws[i]))
+            return fail(FDKOD_E_ARG, "NULL buffer in batch binding");
+    b->proj.assign(proj, proj + b->count);
+    b->filt.assign(filt, filt + b->count);
+    b->ws.assign(ws, ws + b->count);
+    b->vol.assign(vol, vol + b->count);
+    drop_graph(b);
+    fdkod_status st = upload_tables(b);
+    b->bound = st == FDKOD_OK;
+    return st;
+}
+
+fdkod_status fdkod_batch_run(fdkod_batch_t b, fdkod_stream_t stream) {
+    if (!b) return fail(FDKOD_E_ARG, "batch is NULL");
+    if (!b->bound) return fail(FDKOD_E_STATE, "batch buffers are not bound");
+    hipStream_t st = (hipStream_t)stream;
+    fdkod_status r;
+    for (int i = 0; i < b->count; ++i) {
+        if ((r = fdkod_bounds(b->plans[i], stream)) != FDKOD_OK) return r;
+        if ((r = fdkod_filter(b->plans[i], b->proj[i], b->filt[i], stream)) != FDKOD_OK) return r;
+    }
+    if ((r = run_decimate(b, st)) != FDKOD_OK) return r;
+    return run_backproject(b, st);
+}
+
+fdkod_status fdkod_batch_capture(fdkod_batch_t b, fdkod_stream_t stream) {
+    if (!b) return fail(FDKOD_E_ARG, "batch is NULL");
+    if (!stream) return fail(FDKOD_E_ARG, "graph capture needs a non-null stream");
+    if (!b->bound) return fail(FDKOD_E_STATE, "batch buffers are not bound");
+    drop_graph(b);
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    const fdkod_status r = fdkod_batch_run(b, stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &g);
+    if (r != FDKOD_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return r;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_batch_replay(fdkod_batch_t b, fdkod_stream_t stream) {
+    if (!b) return fail(FDKOD_E_ARG, "batch is NULL");
+    if (!b->exec) return fail(FDKOD_E_STATE, "no captured graph (call fdkod_batch_capture)");
+    HIP_TRY(hipGraphLaunch(b->exec, (hipStream_t)stream), "hipGraphLaunch");
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_batch_tune(fdkod_batch_t b, fdkod_stream_t stream, fdkod_tuning* out) {
+    if (!b) return fail(FDKOD_E_ARG, "batch is NULL");
+    if (!b->bound) return fail(FDKOD_E_STATE, "batch buffers are not bound");
+    hipStream_t st = (hipStream_t)stream;
+    drop_graph(b);
+    fdkod_status r;
+    for (int i = 0; i < b->count; ++i)
+        if ((r = fdkod_filter(b->plans[i], b->proj[i], b->filt[i], stream)) != FDKOD_OK) return r;
+    float dec_best = 0.0f;
+    if (b->ndec > 0) {
+        float best = 1e30f;
+        int bestc = b->dec_chunks;
+        for (int c : {1, 2, 4, 8}) {
+            b->dec_chunks = c;
+            if ((r = upload_tables(b)) != FDKOD_OK) return r;
+            float ms = 0.0f;
+            if ((r = time_ms(st, 3, [&] { return run_decimate(b, st); }, &ms)) != FDKOD_OK) return r;
+            if (ms < best) {
+                best = ms;
+                bestc = c;
+            }
+        }
+        b->dec_chunks = bestc;
+        dec_best = best;
+        if ((r = upload_tables(b)) != FDKOD_OK) return r;
+        if ((r = run_decimate(b, st)) != FDKOD_OK) return r;
+    }
+    float best = 1e30f;
+    BpVariant bestv = b->bpv;
+    for (int zr : {32, 16})
+        for (int tw : {32, 64})
+            for (int th : {48, 64})
+                for (int g : {1, 2, 4}) {
+                    const BpVariant v{zr, tw, th, g};
+                    if (!holds_all(b, v)) continue;
+                    b->bpv = v;
+                    if ((r = build_items(b)) != FDKOD_OK) return r;
+                    float ms = 0.0f;
+                    if ((r = time_ms(st, 3, [&] { return run_backproject(b, st); }, &ms)) != FDKOD_OK) return r;
+                    if (ms < best) {
+                        best = ms;
+                        bestv = v;
+                    }
+                }
+    b->bpv = bestv;
+    if ((r = build_items(b)) != FDKOD_OK) return r;
+    if (out) {
+        out->z_run = b->bpv.zrun;
+        out->tile_w = b->bpv.tile_w;
+        out->tile_h = b->bpv.tile_h;
+        out->angles_per_stage = b->bpv.g;
+        out->decim_chunks = b->dec_chunks;
+        out->bp_ms = best;
+        out->decim_ms = dec_best;
+    }
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_batch_info(fdkod_batch_t b, int64_t* items, int32_t* blocks, int64_t* updates_eq) {
+    if (!b) return fail(FDKOD_E_ARG, "batch is NULL");
+    if (items) *items = b->nitems;
+    if (blocks) *blocks = b->bp_blocks;
+    if (updates_eq) *updates_eq = b->updates_eq;
+    return FDKOD_OK;
+}
+
+}  // extern "C"

@@ -1,21 +1,24 @@
 // Host side of the C ABI declared in include/fdkod.h: parameter validation,
 // plan tables (built in FP64, stored in FP32), workspace layout, kernel
-// variant choice and launch sequencing.
+// variant choice, the autotuner and launch sequencing for one plan.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
 #include "fdkod.h"
 #include "internal.h"
 #include "dtype.h"
+#include "plan.h"
 
 using namespace fdkod;
 
-namespace {
+namespace fdkod {
 
 thread_local std::string g_last_error;
 
@@ -28,11 +31,21 @@ fdkod_status hip_fail(hipError_t e, const char* what) {
     return fail(FDKOD_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr, what)                               \
-    do {                                                  \
-        hipError_t e_ = (expr);                           \
-        if (e_ != hipSuccess) return hip_fail(e_, what);  \
-    } while (0)
+fdkod_status dev_alloc(std::vector<void*>& owner, void** ptr, size_t bytes) {
+    if (std::getenv("FDKOD_FAULT") && std::strcmp(std::getenv("FDKOD_FAULT"), "nomem") == 0)
+        return fail(FDKOD_E_NOMEM, "allocation refused (FDKOD_FAULT=nomem)");
+    hipError_t e = hipMalloc(ptr, bytes ? bytes : 1);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FDKOD_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    owner.push_back(*ptr);
+    return FDKOD_OK;
+}
+
+}  // namespace fdkod
+
+namespace {
 
 int64_t floordiv(int64_t a, int64_t b) {
     int64_t q = a / b;
@@ -82,55 +95,11 @@ std::vector<DecimStep> build_schedule(int P, int pd) {
 
 }  // namespace
 
-struct fdkod_plan_s {
-    fdkod_params prm{};
-    int device = 0;
-    int n = 0, nz = 0, p = 0, s = 0, k = 0, d = 1, pd = 0, nsq = 1, store = 0;
-    int logm = 0;
-    double r = 0;
-    std::vector<SquareDesc> sq;
-    std::vector<int2> grid;
-    // decomposition kernel shape
-    int dec_chunks = 1, dec_tasks_per_sq = 1;
-    // backprojection kernel shape
-    int zrun = 32, tile_w = 32, tile_h = 48, ntiles = 0, nzt = 0;
-    bool bp_ok = false;     // the block footprint fits the largest LDS tile
-    int64_t ws_elems = 0;
-    // device tables
-    SquareDesc* d_sq = nullptr;
-    float2* d_trig_p = nullptr;
-    float2* d_trig_m = nullptr;
-    float* d_ac_p = nullptr;
-    int2* d_crop = nullptr;
-    float4* d_geo_m = nullptr;
-    int2* d_grid = nullptr;
-    int2* d_grid_direct = nullptr;
-    DecimStep* d_sched = nullptr;
-    int nsched = 0;
-    float2* d_resp = nullptr;
-    float* d_gtail = nullptr;
-    float2* d_tw = nullptr;
-    BpTile* d_tiles = nullptr;
-    std::vector<void*> allocs;
-};
-
 namespace {
-
-fdkod_status dev_alloc(fdkod_plan_t pl, void** ptr, size_t bytes) {
-    if (std::getenv("FDKOD_FAULT") && std::strcmp(std::getenv("FDKOD_FAULT"), "nomem") == 0)
-        return fail(FDKOD_E_NOMEM, "allocation refused (FDKOD_FAULT=nomem)");
-    hipError_t e = hipMalloc(ptr, bytes ? bytes : 1);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(FDKOD_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-    }
-    pl->allocs.push_back(*ptr);
-    return FDKOD_OK;
-}
 
 template <class T>
 fdkod_status upload(fdkod_plan_t pl, T** dptr, const std::vector<T>& h) {
-    fdkod_status st = dev_alloc(pl, (void**)dptr, h.size() * sizeof(T));
+    fdkod_status st = dev_alloc(pl->allocs, (void**)dptr, h.size() * sizeof(T));
     if (st != FDKOD_OK) return st;
     if (!h.empty()) HIP_TRY(hipMemcpy(*dptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice),
                             "hipMemcpy");
@@ -226,10 +195,15 @@ void ramp_tables(int n, int m, std::vector<float2>& resp, std::vector<float>& gt
     for (int u = 0; u < n; ++u) gtail[u] = (float)gat(u - n);
 }
 
+
+}  // namespace
+
+namespace fdkod {
+
 // Choose the backprojection LDS footprint (TW x TH samples) that holds the
 // footprint of a 16 x 16 x zrun voxel block at any angle, from the slice's
 // smallest depth Dmin = R - (N-1)/sqrt(2).
-bool choose_bp_tiles(int n, int nz, double r, int zrun, int* tw, int* th) {
+bool bp_tiles_for(int n, int nz, double r, int zrun, int* tw, int* th) {
     const double c = (n - 1) / 2.0;
     const double dmin = r - c * std::sqrt(2.0);
     const double mag = r / dmin;
@@ -243,6 +217,119 @@ bool choose_bp_tiles(int n, int nz, double r, int zrun, int* tw, int* th) {
     *tw = need_c <= 32 ? 32 : (need_c <= 64 ? 64 : 0);
     *th = need_r <= 48 ? 48 : (need_r <= 64 ? 64 : 0);
     return *tw && *th;
+}
+
+
+DecimVol decim_args(const fdkod_plan_s* pl, const void* filt, void* ws, int chunks) {
+    DecimVol a;
+    a.filt = filt;
+    a.ws = ws;
+    a.squares = pl->d_sq;
+    a.grid = pl->d_grid;
+    a.crop = pl->d_crop;
+    a.sched = pl->d_sched;
+    a.nsched = pl->nsched;
+    a.n = pl->n;
+    a.p = pl->p;
+    a.pd = pl->pd;
+    a.nsq = pl->nsq;
+    a.tasks_per_sq = dec_tasks_per_sq(pl->wmax, chunks);
+    a.ntasks = pl->nsq * pl->n * a.tasks_per_sq;
+    return a;
+}
+
+// A variant is usable for a plan when it exists and its LDS footprint holds
+// the plan's block footprint for its z run.
+bool variant_holds(const fdkod_plan_s* pl, const BpVariant& v) {
+    if (!backproject_variant_exists(v)) return false;
+    int tw = 0, th = 0;
+    if (!bp_tiles_for(pl->n, pl->nz, pl->r, v.zrun, &tw, &th)) return false;
+    return v.tile_w >= tw && v.tile_h >= th;
+}
+
+BpVol bp_vol(const fdkod_plan_s* pl, const void* filt, const void* ws, float* vol) {
+    const bool direct = pl->s == 0;
+    BpVol v;
+    v.data = direct ? filt : ws;
+    v.vol = vol;
+    v.squares = pl->d_sq;
+    v.grid = direct ? pl->d_grid_direct : pl->d_grid;
+    v.trig = pl->d_trig_m;
+    v.n = pl->n;
+    v.nz = pl->nz;
+    v.pd = pl->pd;
+    v.row_stride_direct = direct ? pl->n : 0;
+    v.r = (float)pl->r;
+    v.cu = (float)((pl->n - 1) / 2.0);
+    v.cv = v.cu;
+    v.cz = (float)((pl->nz - 1) / 2.0);
+    v.scale = (float)(M_PI / pl->pd);
+    return v;
+}
+
+}  // namespace fdkod
+
+namespace {
+
+
+std::string tune_key(const fdkod_plan_s* pl) {
+    std::ostringstream k;
+    k << "gfx950 n=" << pl->n << " nz=" << pl->nz << " p=" << pl->p << " r=" << pl->r
+      << " s=" << pl->s << " k=" << pl->k << " store=" << pl->store;
+    return k.str();
+}
+
+// Last entry of the tuning cache file for this plan, if any.
+bool tune_cache_lookup(const fdkod_plan_s* pl, BpVariant* v, int* chunks) {
+    const char* path = std::getenv("FDKOD_TUNE_CACHE");
+    if (!path || !*path) return false;
+    std::ifstream f(path);
+    if (!f) return false;
+    const std::string key = tune_key(pl) + " :";
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        if (line.compare(0, key.size(), key) != 0) continue;
+        std::istringstream in(line.substr(key.size()));
+        BpVariant t{};
+        int c = 0;
+        if (in >> t.zrun >> t.tile_w >> t.tile_h >> t.g >> c) {
+            *v = t;
+            *chunks = c;
+            found = true;
+        }
+    }
+    return found;
+}
+
+void tune_cache_store(const fdkod_plan_s* pl) {
+    const char* path = std::getenv("FDKOD_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::ofstream f(path, std::ios::app);
+    if (!f) return;
+    f << tune_key(pl) << " : " << pl->bpv.zrun << " " << pl->bpv.tile_w << " " << pl->bpv.tile_h
+      << " " << pl->bpv.g << " " << pl->dec_chunks << "\n";
+}
+
+// Time `fn` on `st`: one warm-up, then the mean of `reps` runs (ms).
+template <class F>
+fdkod_status time_ms(hipStream_t st, int reps, F fn, float* ms) {
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+    fdkod_status r = fn();
+    if (r == FDKOD_OK) {
+        (void)hipEventRecord(e0, st);
+        for (int i = 0; i < reps && r == FDKOD_OK; ++i) r = fn();
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float t = 0.0f;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        *ms = t / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return r;
 }
 
 }  // namespace
@@ -262,7 +349,7 @@ const char* fdkod_status_str(fdkod_status st) {
     return "unknown status";
 }
 
-const char* fdkod_last_error(void) { return g_last_error.c_str(); }
+const char* fdkod_last_error(void) { return fdkod::g_last_error.c_str(); }
 
 int32_t fdkod_version(void) { return 100; }
 
@@ -365,13 +452,13 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
     if ((st = upload(pl, &pl->d_sched, sched)) != FDKOD_OK) return bail(st);
     if ((st = upload(pl, &pl->d_grid_direct, std::vector<int2>{make_int2(0, pl->n)})) != FDKOD_OK)
         return bail(st);
-    if ((st = dev_alloc(pl, (void**)&pl->d_ac_p, sizeof(float) * (size_t)pl->nsq * pl->p)) != FDKOD_OK)
+    if ((st = dev_alloc(pl->allocs, (void**)&pl->d_ac_p, sizeof(float) * (size_t)pl->nsq * pl->p)) != FDKOD_OK)
         return bail(st);
-    if ((st = dev_alloc(pl, (void**)&pl->d_geo_m, sizeof(float4) * (size_t)pl->nsq * pl->pd)) != FDKOD_OK)
+    if ((st = dev_alloc(pl->allocs, (void**)&pl->d_geo_m, sizeof(float4) * (size_t)pl->nsq * pl->pd)) != FDKOD_OK)
         return bail(st);
-    if ((st = dev_alloc(pl, (void**)&pl->d_crop, sizeof(int2) * (size_t)pl->nsq * pl->nsched)) != FDKOD_OK)
+    if ((st = dev_alloc(pl->allocs, (void**)&pl->d_crop, sizeof(int2) * (size_t)pl->nsq * pl->nsched)) != FDKOD_OK)
         return bail(st);
-    if ((st = dev_alloc(pl, (void**)&pl->d_grid, sizeof(int2) * (size_t)pl->nsq)) != FDKOD_OK)
+    if ((st = dev_alloc(pl->allocs, (void**)&pl->d_grid, sizeof(int2) * (size_t)pl->nsq)) != FDKOD_OK)
         return bail(st);
 
     // bounds kernel, then one synchronisation to lay out the workspace
@@ -385,12 +472,12 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
         hipError_t e = hipMemcpy(pl->grid.data(), pl->d_grid, sizeof(int2) * pl->nsq, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return bail(hip_fail(e, "hipMemcpy grid"));
     }
-    int wmax = 0;
     int64_t off = 0;
+    pl->wmax = 0;
     for (int q = 0; q < pl->nsq; ++q) {
         const int w = pl->grid[q].y;
         if (w < 2 || w > 4 * pl->n + 8) return bail(fail(FDKOD_E_HIP, "bounds kernel produced an invalid width"));
-        wmax = std::max(wmax, w);
+        pl->wmax = std::max(pl->wmax, w);
         pl->sq[q].y_off = off;
         off += (int64_t)w * pl->pd * pl->n;
         off = (off + 63) & ~(int64_t)63;     // 256-byte aligned planes for FP32
@@ -401,20 +488,30 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
         if (e != hipSuccess) return bail(hip_fail(e, "hipMemcpy squares"));
     }
 
-    // decomposition kernel shape: 64 * chunks local columns per wavefront
+    // default kernel shapes: 64 * chunks local columns per decimation wavefront
+    // (the smallest power of two covering the widest square, at most 8), and
+    // the longest z run whose block footprint fits an LDS tile, two angles per
+    // stage
     int ch = 1;
-    while (ch < 8 && 64 * ch < wmax) ch <<= 1;
+    while (ch < 8 && 64 * ch < pl->wmax) ch <<= 1;
     pl->dec_chunks = ch;
-    pl->dec_tasks_per_sq = (wmax + 64 * ch - 1) / (64 * ch);
-
-    // backprojection kernel shape and tiles
-    // the longest z run whose footprint fits the largest LDS tile
     pl->bp_ok = false;
     for (int zr : {32, 16}) {
-        if (choose_bp_tiles(pl->n, pl->nz, pl->r, zr, &pl->tile_w, &pl->tile_h)) {
-            pl->zrun = zr;
+        int tw = 0, th = 0;
+        if (bp_tiles_for(pl->n, pl->nz, pl->r, zr, &tw, &th)) {
+            pl->bpv = BpVariant{zr, tw, th, 2};
+            if (!backproject_variant_exists(pl->bpv)) pl->bpv.g = 1;
             pl->bp_ok = true;
             break;
+        }
+    }
+    {
+        BpVariant cv{};
+        int cc = 0;
+        if (pl->bp_ok && tune_cache_lookup(pl, &cv, &cc) && variant_holds(pl, cv) &&
+            (cc == 1 || cc == 2 || cc == 4 || cc == 8)) {
+            pl->bpv = cv;
+            pl->dec_chunks = cc;
         }
     }
     std::vector<BpTile> tiles;
@@ -424,8 +521,7 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
             for (int x = d.x0; x < d.x1; x += kTileXY) tiles.push_back(BpTile{q, x, y, 0});
     }
     pl->ntiles = (int)tiles.size();
-    pl->nzt = (pl->nz + pl->zrun - 1) / pl->zrun;
-    if ((int64_t)pl->ntiles * pl->nzt > (int64_t)1 << 30)
+    if ((int64_t)pl->ntiles * bp_zslabs(pl->nz, 16) > (int64_t)1 << 30)
         return bail(fail(FDKOD_E_UNSUPPORTED, "volume too large for one launch"));
     if ((st = upload(pl, &pl->d_tiles, tiles)) != FDKOD_OK) return bail(st);
 
@@ -445,10 +541,8 @@ fdkod_status fdkod_plan_info(fdkod_plan_t pl, fdkod_info* info) {
     info->p_dec = pl->pd;
     info->d = pl->d;
     info->fft_len = 1 << pl->logm;
-    int wmax = 0;
-    for (auto& g : pl->grid) wmax = std::max(wmax, (int)g.y);
-    info->max_width = wmax;
-    info->z_run = pl->zrun;
+    info->max_width = pl->wmax;
+    info->z_run = pl->bpv.zrun;
     info->filtered_bytes = (int64_t)pl->p * pl->n * pl->n * store_bytes(pl->store);
     info->workspace_bytes = pl->ws_elems * store_bytes(pl->store);
     info->volume_bytes = (int64_t)pl->nz * pl->n * pl->n * 4;
@@ -498,20 +592,7 @@ fdkod_status fdkod_decompose(fdkod_plan_t pl, const void* filt, void* ws, fdkod_
     if (!pl || !filt) return fail(FDKOD_E_ARG, "NULL argument");
     if (pl->s == 0) return FDKOD_OK;
     if (!ws) return fail(FDKOD_E_ARG, "workspace is NULL");
-    DecimArgs a;
-    a.filt = filt;
-    a.ws = ws;
-    a.squares = pl->d_sq;
-    a.grid = pl->d_grid;
-    a.crop = pl->d_crop;
-    a.sched = pl->d_sched;
-    a.nsched = pl->nsched;
-    a.n = pl->n;
-    a.p = pl->p;
-    a.pd = pl->pd;
-    a.nsq = pl->nsq;
-    a.tasks_per_sq = pl->dec_tasks_per_sq;
-    a.ntasks = pl->nsq * pl->n * pl->dec_tasks_per_sq;
+    const DecimVol a = decim_args(pl, filt, ws, pl->dec_chunks);
     HIP_TRY(launch_decimate(a, pl->dec_chunks, pl->store, (hipStream_t)stream), "decimate kernel launch");
     return FDKOD_OK;
 }
@@ -525,27 +606,13 @@ fdkod_status fdkod_reconstruct(fdkod_plan_t pl, const void* filt, const void* ws
     if (!pl->bp_ok)
         return fail(FDKOD_E_UNSUPPORTED, "R too small: a block's detector footprint exceeds 64 x 64");
     BpArgs a;
-    a.data = direct ? filt : ws;
-    a.vol = vol;
-    a.squares = pl->d_sq;
-    a.grid = direct ? pl->d_grid_direct : pl->d_grid;
-    a.trig = pl->d_trig_m;
+    a.v = bp_vol(pl, filt, ws, vol);
     a.tiles = pl->d_tiles;
     a.ntiles = pl->ntiles;
-    a.nzt = pl->nzt;
-    a.nlogical = pl->ntiles * pl->nzt;
+    a.nzt = bp_zslabs(pl->nz, pl->bpv.zrun);
+    a.nlogical = a.ntiles * a.nzt;
     a.chunk = (a.nlogical + 7) / 8;
-    a.n = pl->n;
-    a.nz = pl->nz;
-    a.pd = pl->pd;
-    a.row_stride_direct = direct ? pl->n : 0;
-    a.r = (float)pl->r;
-    a.cu = (float)((pl->n - 1) / 2.0);
-    a.cv = a.cu;
-    a.cz = (float)((pl->nz - 1) / 2.0);
-    a.scale = (float)(M_PI / pl->pd);
-    HIP_TRY(launch_backproject(a, pl->zrun, pl->tile_w, pl->tile_h, pl->store, (hipStream_t)stream),
-            "backprojection kernel launch");
+    HIP_TRY(launch_backproject(a, pl->bpv, pl->store, (hipStream_t)stream), "backprojection kernel launch");
     return FDKOD_OK;
 }
 
@@ -590,6 +657,79 @@ fdkod_status fdkod_get_bounds(fdkod_plan_t pl, float* ac_p, float* ac_m, float* 
     }
     (void)hipSetDevice(prev);
     return FDKOD_OK;
+}
+
+fdkod_status fdkod_get_tuning(fdkod_plan_t pl, fdkod_tuning* out) {
+    if (!pl || !out) return fail(FDKOD_E_ARG, "NULL argument");
+    out->z_run = pl->bpv.zrun;
+    out->tile_w = pl->bpv.tile_w;
+    out->tile_h = pl->bpv.tile_h;
+    out->angles_per_stage = pl->bpv.g;
+    out->decim_chunks = pl->dec_chunks;
+    out->bp_ms = pl->tuned_bp_ms;
+    out->decim_ms = pl->tuned_dec_ms;
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_set_tuning(fdkod_plan_t pl, const fdkod_tuning* t) {
+    if (!pl || !t) return fail(FDKOD_E_ARG, "NULL argument");
+    const BpVariant v{t->z_run, t->tile_w, t->tile_h, t->angles_per_stage};
+    if (!variant_holds(pl, v))
+        return fail(FDKOD_E_UNSUPPORTED, "backprojection variant missing or too small for this geometry");
+    const int c = t->decim_chunks;
+    if (!(c == 1 || c == 2 || c == 4 || c == 8)) return fail(FDKOD_E_UNSUPPORTED, "decim_chunks must be 1, 2, 4 or 8");
+    pl->bpv = v;
+    pl->dec_chunks = c;
+    pl->tuned_bp_ms = t->bp_ms;
+    pl->tuned_dec_ms = t->decim_ms;
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_tune(fdkod_plan_t pl, const void* filt, void* ws, float* vol,
+                        fdkod_stream_t stream, fdkod_tuning* out) {
+    if (!pl || !filt || !vol || (pl->s > 0 && !ws)) return fail(FDKOD_E_ARG, "NULL argument");
+    if (!pl->bp_ok) return fail(FDKOD_E_UNSUPPORTED, "no backprojection variant holds this geometry");
+    hipStream_t st = (hipStream_t)stream;
+    fdkod_status r = FDKOD_OK;
+    // decimation chunking (its output feeds the backprojection timings)
+    if (pl->s > 0) {
+        float best = 1e30f;
+        int bestc = pl->dec_chunks;
+        for (int c : {1, 2, 4, 8}) {
+            pl->dec_chunks = c;
+            float ms = 0.0f;
+            r = time_ms(st, 3, [&] { return fdkod_decompose(pl, filt, ws, stream); }, &ms);
+            if (r != FDKOD_OK) return r;
+            if (ms < best) {
+                best = ms;
+                bestc = c;
+            }
+        }
+        pl->dec_chunks = bestc;
+        pl->tuned_dec_ms = best;
+        if ((r = fdkod_decompose(pl, filt, ws, stream)) != FDKOD_OK) return r;
+    }
+    float best = 1e30f;
+    BpVariant bestv = pl->bpv;
+    for (int zr : {32, 16})
+        for (int tw : {32, 64})
+            for (int th : {48, 64})
+                for (int g : {1, 2, 4}) {
+                    const BpVariant v{zr, tw, th, g};
+                    if (!variant_holds(pl, v)) continue;
+                    pl->bpv = v;
+                    float ms = 0.0f;
+                    r = time_ms(st, 3, [&] { return fdkod_reconstruct(pl, filt, ws, vol, stream); }, &ms);
+                    if (r != FDKOD_OK) return r;
+                    if (ms < best) {
+                        best = ms;
+                        bestv = v;
+                    }
+                }
+    pl->bpv = bestv;
+    pl->tuned_bp_ms = best;
+    tune_cache_store(pl);
+    return out ? fdkod_get_tuning(pl, out) : FDKOD_OK;
 }
 
 }  // extern "C"

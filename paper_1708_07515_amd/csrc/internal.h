@@ -61,8 +61,8 @@ struct FilterArgs {
     float c;                // (N-1)/2
 };
 
-// Arguments of the crop + shift + decimate kernel.
-struct DecimArgs {
+// Arguments of the crop + shift + decimate kernel for one volume.
+struct DecimVol {
     const void* filt;       // [P][N][N] store type
     void* ws;               // decimated data, store type
     const SquareDesc* squares;
@@ -75,29 +75,66 @@ struct DecimArgs {
     int ntasks;             // nsq * n * tasks_per_sq
 };
 
-// Arguments of the backprojection kernel.
-struct BpArgs {
+// Many volumes in one launch: volume b owns tasks [task_start[b], task_start[b+1]).
+struct DecimBatchArgs {
+    const DecimVol* vols;
+    const int* task_start;  // [nvols + 1]
+    int nvols;
+    int ntasks;
+};
+
+// Per-volume parameters of the backprojection.
+struct BpVol {
     const void* data;       // decimated data (s > 0) or filtered projections (s = 0)
     float* vol;             // [nz][n][n]
     const SquareDesc* squares;
     const int2* grid;       // u0, W per square (direct: 0, N)
     const float2* trig;     // cos, sin of the reconstruction angles, [pd]
-    const BpTile* tiles;
-    int ntiles;             // xy tiles
-    int nzt;                // z tiles
-    int nlogical;           // ntiles * nzt
-    int chunk;              // logical WGs per XCD
     int n, nz, pd;
     int row_stride_direct;  // 0 for per-square layout [m][v][W_q]
     float r, cu, cv, cz;
     float scale;            // pi / P'
 };
 
+// Arguments of the backprojection kernel for one volume (grid launch).
+struct BpArgs {
+    BpVol v;
+    const BpTile* tiles;
+    int ntiles;             // xy tiles
+    int nzt;                // z tiles
+    int nlogical;           // ntiles * nzt
+    int chunk;              // logical WGs per XCD
+};
+
+// One work item of the batched (persistent) backprojection.
+struct BatchItem {
+    int vol, sq, x0, y0, zt, pad0, pad1, pad2;
+};
+
+struct BpBatchArgs {
+    const BpVol* vols;
+    const BatchItem* items;  // largest first
+    int nitems;
+    unsigned* counter;       // ticket counter, zeroed before each launch
+};
+
+// A backprojection kernel variant: slices per thread, LDS footprint
+// (columns x rows), angles staged per barrier.
+struct BpVariant {
+    int zrun, tile_w, tile_h, g;
+};
+
 hipError_t launch_bounds(const BoundsArgs& a, hipStream_t st);
 hipError_t launch_filter(const FilterArgs& a, int logm, int store, hipStream_t st);
-hipError_t launch_decimate(const DecimArgs& a, int chunks, int store, hipStream_t st);
-hipError_t launch_backproject(const BpArgs& a, int zrun, int tile_w, int tile_h,
-                              int store, hipStream_t st);
+hipError_t launch_decimate(const DecimVol& a, int chunks, int store, hipStream_t st);
+hipError_t launch_decimate_batch(const DecimBatchArgs& a, int chunks, int store, hipStream_t st);
+hipError_t launch_backproject(const BpArgs& a, const BpVariant& var, int store, hipStream_t st);
+hipError_t launch_backproject_batch(const BpBatchArgs& a, const BpVariant& var, int store,
+                                    int blocks, hipStream_t st);
+// workgroups of the batched kernel that fit on one CU (0 if the variant is unknown)
+int backproject_batch_occupancy(const BpVariant& var, int store);
+bool backproject_variant_exists(const BpVariant& var);
+hipError_t launch_reset_counter(unsigned* counter, hipStream_t st);
 
 // Limits the host checks before choosing a backprojection variant.
 constexpr int kTileXY = 16;      // voxels per tile side in x and y

@@ -28,28 +28,33 @@ typedef float f2v __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) const char* lds_cptr;
 typedef __attribute__((address_space(3))) const f2v* lds_f2ptr;
 
+// LDS of one workgroup: G staged footprints and their per-angle constants.
+template <int TW, int TH, int G>
+struct BpSmem {
+    float2 tile[G][TH * (TW + 1)];
+    int4 meta[G];      // c0, r0 (first column / row of the footprint), rows, -
+    float4 mgeo[G];    // cos, sin, Dc, Lc
+    float2 mgeo2[G];   // R / Dc, c_u - u0 - c0
+};
+
+// Backprojection of one 16 x 16 x ZR voxel block (tile tl, slab zt) of one
+// volume.  Every thread of the workgroup calls it (it contains barriers).
 template <int ZR, int TW, int TH, int G, int STORE>
-__global__ __launch_bounds__(256) void k_backproject(BpArgs a) {
+__device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& tl,
+                                         BpSmem<TW, TH, G>& sm) {
     using S = Store<STORE>;
     using T = typename S::T;
     constexpr int TWP = TW + 1;   // LDS row pitch in pairs (odd: spreads banks)
     static_assert(TWP <= 255, "ds_read2_b64 offset range");
-    __shared__ float2 tile[G][TH * TWP];
-    __shared__ int4 meta[G];      // c0, r0 (first column / row of the footprint), rows, -
-    __shared__ float4 mgeo[G];    // cos, sin, Dc, Lc
-    __shared__ float2 mgeo2[G];   // R / Dc, c_u - u0 - c0
-
-    // XCD-aware order: each XCD runs a contiguous range of logical blocks
-    const int b = blockIdx.x;
-    const int lblk = (b & 7) * a.chunk + (b >> 3);
-    if (lblk >= a.nlogical) return;               // before any barrier
-    const int zt = lblk / a.ntiles;
-    const BpTile tl = a.tiles[lblk - zt * a.ntiles];
-    const SquareDesc sq = a.squares[tl.sq];
-    const int2 gd = a.grid[tl.sq];
+    auto& tile = sm.tile;
+    auto& meta = sm.meta;
+    auto& mgeo = sm.mgeo;
+    auto& mgeo2 = sm.mgeo2;
+    const SquareDesc sq = v.squares[tl.sq];
+    const int2 gd = v.grid[tl.sq];
     const int u0 = gd.x, width = gd.y;
 
-    const int n = a.n;
+    const int n = v.n;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int ix1 = min(tl.x0 + 15, sq.x1 - 1);
     const int iy1 = min(tl.y0 + 15, sq.y1 - 1);
@@ -57,22 +62,22 @@ __global__ __launch_bounds__(256) void k_backproject(BpArgs a) {
     const bool own = (i <= ix1) && (j <= iy1);
     // offsets from the square centre; threads outside the square use the
     // block's last voxel so every address they form stays in bounds
-    const float dx = (float)min(i, ix1) - a.cu - sq.xc;
-    const float dy = (float)min(j, iy1) - a.cu - sq.yc;
-    const float bx0 = (float)tl.x0 - a.cu - sq.xc, bx1 = (float)ix1 - a.cu - sq.xc;
-    const float by0 = (float)tl.y0 - a.cu - sq.yc, by1 = (float)iy1 - a.cu - sq.yc;
+    const float dx = (float)min(i, ix1) - v.cu - sq.xc;
+    const float dy = (float)min(j, iy1) - v.cu - sq.yc;
+    const float bx0 = (float)tl.x0 - v.cu - sq.xc, bx1 = (float)ix1 - v.cu - sq.xc;
+    const float by0 = (float)tl.y0 - v.cu - sq.yc, by1 = (float)iy1 - v.cu - sq.yc;
 
     // the run covers ZR slices even past the volume's end (those voxels are
     // computed and discarded), so the staged rows always hold the whole run
     const int l0 = zt * ZR;
-    const float z0 = (float)l0 - a.cz;
-    const float zlast = (float)(l0 + ZR - 1) - a.cz;
+    const float z0 = (float)l0 - v.cz;
+    const float zlast = (float)(l0 + ZR - 1) - v.cz;
 
-    const bool direct = a.row_stride_direct != 0;
-    const int row_stride = direct ? a.row_stride_direct : width;
+    const bool direct = v.row_stride_direct != 0;
+    const int row_stride = direct ? v.row_stride_direct : width;
     const size_t plane = (size_t)n * row_stride;
-    const T* data = (const T*)a.data + (direct ? 0 : sq.y_off);
-    const float kq = a.cu - (float)u0;            // tau = rel + kq
+    const T* data = (const T*)v.data + (direct ? 0 : sq.y_off);
+    const float kq = v.cu - (float)u0;            // tau = rel + kq
 
     // staging map: a lane keeps one footprint column, rows strided by 256 / TW
     constexpr int RSTEP = 256 / TW;
@@ -84,13 +89,13 @@ __global__ __launch_bounds__(256) void k_backproject(BpArgs a) {
 #pragma unroll
     for (int k = 0; k < ZR; ++k) acc[k] = 0.0f;
 
-    for (int m0 = 0; m0 < a.pd; m0 += G) {
-        const int gcount = min(G, a.pd - m0);
+    for (int m0 = 0; m0 < v.pd; m0 += G) {
+        const int gcount = min(G, v.pd - m0);
         // footprint of the block at each angle of the batch
         if (threadIdx.x < gcount) {
             const int m = m0 + threadIdx.x;
-            const float2 t = a.trig[m];
-            const float dc = a.r + sq.xc * t.x + sq.yc * t.y;
+            const float2 t = v.trig[m];
+            const float dc = v.r + sq.xc * t.x + sq.yc * t.y;
             const float lc = sq.yc * t.x - sq.xc * t.y;
             const float rdc = 1.0f / dc;
             float tlo = INFINITY, thi = -INFINITY, vlo = INFINITY, vhi = -INFINITY;
@@ -98,11 +103,11 @@ __global__ __launch_bounds__(256) void k_backproject(BpArgs a) {
             for (int k = 0; k < 4; ++k) {
                 const float cx = (k & 1) ? bx1 : bx0;
                 const float cy = (k & 2) ? by1 : by0;
-                const float tau = rel_column(cx, cy, t.x, t.y, a.r, dc, lc, rdc) + kq;
+                const float tau = rel_column(cx, cy, t.x, t.y, v.r, dc, lc, rdc) + kq;
                 tlo = fminf(tlo, tau);
                 thi = fmaxf(thi, tau);
-                const float iu = a.r / (dc + cx * t.x + cy * t.y);
-                const float va = z0 * iu + a.cv, vb = zlast * iu + a.cv;
+                const float iu = v.r / (dc + cx * t.x + cy * t.y);
+                const float va = z0 * iu + v.cv, vb = zlast * iu + v.cv;
                 vlo = fminf(vlo, fminf(va, vb));
                 vhi = fmaxf(vhi, fmaxf(va, vb));
             }
@@ -111,7 +116,7 @@ __global__ __launch_bounds__(256) void k_backproject(BpArgs a) {
             const int rows = min((int)floorf(vhi) + 3 - r0, TH);
             meta[threadIdx.x] = make_int4(c0, r0, rows, 0);
             mgeo[threadIdx.x] = make_float4(t.x, t.y, dc, lc);
-            mgeo2[threadIdx.x] = make_float2(a.r * rdc, kq - (float)c0);
+            mgeo2[threadIdx.x] = make_float2(v.r * rdc, kq - (float)c0);
         }
         __syncthreads();
         // stage the footprints as (Y[c], Y[c+1] - Y[c]); columns outside
@@ -141,12 +146,12 @@ __global__ __launch_bounds__(256) void k_backproject(BpArgs a) {
             const float d = mg.z + dd;
             const float rd = __builtin_amdgcn_rcpf(d);
             const float tau = (dl * mg.z - mg.w * dd) * mg2.x * rd + mg2.y;
-            float invu = a.r * rd;
-            float w = a.scale * invu * invu;
+            float invu = v.r * rd;
+            float w = v.scale * invu * invu;
             const float tf = floorf(tau);
             const float fu = tau - tf;
             const int ci = min(max((int)tf, 0), TW - 2);
-            float v0 = fmaf(z0, invu, a.cv - (float)mt.y);
+            float v0 = fmaf(z0, invu, v.cv - (float)mt.y);
             // the row index is monotone in z: check the run's ends once; a
             // run outside the staged rows (never expected) contributes zero
             const float vend = fmaf((float)(ZR - 1), invu, v0);
@@ -173,39 +178,125 @@ __global__ __launch_bounds__(256) void k_backproject(BpArgs a) {
         __syncthreads();
     }
     if (own) {
+        const size_t slice = (size_t)n * n;
+        float* out = v.vol + (size_t)l0 * slice + (size_t)j * n + i;
+        const int kmax = min(ZR, v.nz - l0);
 #pragma unroll
         for (int k = 0; k < ZR; ++k) {
-            const int l = l0 + k;
-            if (l < a.nz) a.vol[((size_t)l * n + j) * n + i] = acc[k];
+            if (k < kmax) *out = acc[k];
+            out += slice;
         }
     }
 }
 
-template <int ZR, int TW, int TH>
-static void launch_bp_t(const BpArgs& a, int store, dim3 grid, hipStream_t st) {
-    constexpr int G = (TW * TH <= 1600) ? 2 : 1;
-    switch (store) {
-        case 0: hipLaunchKernelGGL((k_backproject<ZR, TW, TH, G, 0>), grid, dim3(256), 0, st, a); break;
-        case 1: hipLaunchKernelGGL((k_backproject<ZR, TW, TH, G, 1>), grid, dim3(256), 0, st, a); break;
-        default: hipLaunchKernelGGL((k_backproject<ZR, TW, TH, G, 2>), grid, dim3(256), 0, st, a); break;
+template <int ZR, int TW, int TH, int G, int STORE>
+__global__ __launch_bounds__(256) void k_backproject(BpArgs a) {
+    __shared__ BpSmem<TW, TH, G> sm;
+    // XCD-aware order: each XCD runs a contiguous range of logical blocks
+    const int b = blockIdx.x;
+    const int lblk = (b & 7) * a.chunk + (b >> 3);
+    if (lblk >= a.nlogical) return;               // before any barrier
+    const int zt = lblk / a.ntiles;
+    const BpTile tl = a.tiles[lblk - zt * a.ntiles];
+    bp_block<ZR, TW, TH, G, STORE>(a.v, zt, tl, sm);
+}
+
+// Persistent backprojection over the work items of many volumes: each
+// workgroup takes the next item from a ticket counter (items are ordered
+// largest first) until the tickets run past the end; every workgroup reaches
+// that exit.  The counter must be zero at launch (launch_reset_counter).
+template <int ZR, int TW, int TH, int G, int STORE>
+__global__ __launch_bounds__(256) void k_backproject_batch(BpBatchArgs a) {
+    __shared__ BpSmem<TW, TH, G> sm;
+    __shared__ int ticket;
+    for (;;) {
+        if (threadIdx.x == 0) ticket = (int)atomicAdd(a.counter, 1u);
+        __syncthreads();
+        const int it = ticket;
+        __syncthreads();          // all threads read the ticket before it is replaced
+        if (it >= a.nitems) break;
+        const BatchItem bi = a.items[it];
+        const BpVol v = a.vols[bi.vol];
+        bp_block<ZR, TW, TH, G, STORE>(v, bi.zt, BpTile{bi.sq, bi.x0, bi.y0, 0}, sm);
     }
 }
 
-hipError_t launch_backproject(const BpArgs& a, int zrun, int tile_w, int tile_h, int store,
-                              hipStream_t st) {
+__global__ void k_reset_counter(unsigned* c) {
+    if (threadIdx.x == 0) *c = 0u;
+}
+
+hipError_t launch_reset_counter(unsigned* counter, hipStream_t st) {
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
+    return hipGetLastError();
+}
+
+// Variant table: (zrun, TW, TH, G).  G is limited so that the LDS of one
+// workgroup stays within 64 KB.
+#define FDKOD_BP_VARIANTS(X)  \
+    X(32, 32, 48, 1) X(32, 32, 48, 2) X(32, 32, 48, 4) \
+    X(32, 32, 64, 1) X(32, 32, 64, 2) \
+    X(32, 64, 48, 1) X(32, 64, 48, 2) \
+    X(32, 64, 64, 1) \
+    X(16, 32, 48, 1) X(16, 32, 48, 2) X(16, 32, 48, 4) \
+    X(16, 32, 64, 1) X(16, 32, 64, 2) \
+    X(16, 64, 48, 1) X(16, 64, 48, 2) \
+    X(16, 64, 64, 1)
+
+bool backproject_variant_exists(const BpVariant& var) {
+#define FDKOD_X(Z, W, H, GG) \
+    if (var.zrun == Z && var.tile_w == W && var.tile_h == H && var.g == GG) return true;
+    FDKOD_BP_VARIANTS(FDKOD_X)
+#undef FDKOD_X
+    return false;
+}
+
+hipError_t launch_backproject(const BpArgs& a, const BpVariant& var, int store, hipStream_t st) {
     const dim3 grid(8 * a.chunk);
-#define FDKOD_BP_CASE(Z, W, H) \
-    if (zrun == Z && tile_w == W && tile_h == H) { launch_bp_t<Z, W, H>(a, store, grid, st); return hipGetLastError(); }
-    FDKOD_BP_CASE(32, 32, 48)
-    FDKOD_BP_CASE(32, 32, 64)
-    FDKOD_BP_CASE(32, 64, 48)
-    FDKOD_BP_CASE(32, 64, 64)
-    FDKOD_BP_CASE(16, 32, 48)
-    FDKOD_BP_CASE(16, 32, 64)
-    FDKOD_BP_CASE(16, 64, 48)
-    FDKOD_BP_CASE(16, 64, 64)
-#undef FDKOD_BP_CASE
+#define FDKOD_X(Z, W, H, GG)                                                                   \
+    if (var.zrun == Z && var.tile_w == W && var.tile_h == H && var.g == GG) {                  \
+        switch (store) {                                                                       \
+            case 0: hipLaunchKernelGGL((k_backproject<Z, W, H, GG, 0>), grid, dim3(256), 0, st, a); break; \
+            case 1: hipLaunchKernelGGL((k_backproject<Z, W, H, GG, 1>), grid, dim3(256), 0, st, a); break; \
+            default: hipLaunchKernelGGL((k_backproject<Z, W, H, GG, 2>), grid, dim3(256), 0, st, a); break; \
+        }                                                                                      \
+        return hipGetLastError();                                                              \
+    }
+    FDKOD_BP_VARIANTS(FDKOD_X)
+#undef FDKOD_X
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_backproject_batch(const BpBatchArgs& a, const BpVariant& var, int store,
+                                    int blocks, hipStream_t st) {
+#define FDKOD_X(Z, W, H, GG)                                                                   \
+    if (var.zrun == Z && var.tile_w == W && var.tile_h == H && var.g == GG) {                  \
+        switch (store) {                                                                       \
+            case 0: hipLaunchKernelGGL((k_backproject_batch<Z, W, H, GG, 0>), dim3(blocks), dim3(256), 0, st, a); break; \
+            case 1: hipLaunchKernelGGL((k_backproject_batch<Z, W, H, GG, 1>), dim3(blocks), dim3(256), 0, st, a); break; \
+            default: hipLaunchKernelGGL((k_backproject_batch<Z, W, H, GG, 2>), dim3(blocks), dim3(256), 0, st, a); break; \
+        }                                                                                      \
+        return hipGetLastError();                                                              \
+    }
+    FDKOD_BP_VARIANTS(FDKOD_X)
+#undef FDKOD_X
+    return hipErrorInvalidValue;
+}
+
+int backproject_batch_occupancy(const BpVariant& var, int store) {
+    int nb = 0;
+#define FDKOD_X(Z, W, H, GG)                                                                   \
+    if (var.zrun == Z && var.tile_w == W && var.tile_h == H && var.g == GG) {                  \
+        hipError_t e = hipErrorInvalidValue;                                                   \
+        switch (store) {                                                                       \
+            case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_backproject_batch<Z, W, H, GG, 0>, 256, 0); break; \
+            case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_backproject_batch<Z, W, H, GG, 1>, 256, 0); break; \
+            default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_backproject_batch<Z, W, H, GG, 2>, 256, 0); break; \
+        }                                                                                      \
+        return e == hipSuccess ? nb : 0;                                                       \
+    }
+    FDKOD_BP_VARIANTS(FDKOD_X)
+#undef FDKOD_X
+    return 0;
 }
 
 }  // namespace fdkod

@@ -28,22 +28,12 @@ __device__ __forceinline__ void* uniform_ptr(const T* p) {
     return (void*)(uintptr_t)(((uint64_t)hi << 32) | lo);
 }
 
+// One task: square q, detector row v, column group g of 64*CH columns, run by
+// one wavefront (lane = 0..63).
 template <int CH, int STORE>
-__global__ __launch_bounds__(256) void k_decimate(DecimArgs a) {
+__device__ __forceinline__ void decimate_task(const DecimVol& a, int task, int lane) {
     using S = Store<STORE>;
     using T = typename S::T;
-    // XCD-aware order: consecutive logical blocks share an XCD (and its L2)
-    const int nblk = gridDim.x;
-    const int chunk = nblk / 8;
-    const int b = blockIdx.x;
-    const int lblk = (b & 7) * chunk + (b >> 3);
-    // the wave index is uniform across the wave; say so, so that the task's
-    // square, row and buffer resources live in scalar registers
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int task = lblk * 4 + wave;
-    if (task >= a.ntasks) return;         // no barriers in this kernel
-
     // task = (v * nsq + q) * tasks_per_sq + g
     const int g = task % a.tasks_per_sq;
     const int vq = task / a.tasks_per_sq;
@@ -131,8 +121,39 @@ __global__ __launch_bounds__(256) void k_decimate(DecimArgs a) {
     }
 }
 
+template <int CH, int STORE>
+__global__ __launch_bounds__(256) void k_decimate(DecimVol a) {
+    // XCD-aware order: consecutive logical blocks share an XCD (and its L2)
+    const int nblk = gridDim.x;
+    const int chunk = nblk / 8;
+    const int b = blockIdx.x;
+    const int lblk = (b & 7) * chunk + (b >> 3);
+    // the wave index is uniform across the wave; say so, so that the task's
+    // square, row and buffer resources live in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int task = lblk * 4 + wave;
+    if (task >= a.ntasks) return;         // no barriers in this kernel
+    decimate_task<CH, STORE>(a, task, threadIdx.x & 63);
+}
+
+// Many volumes in one launch (tasks concatenated volume after volume).
+template <int CH, int STORE>
+__global__ __launch_bounds__(256) void k_decimate_batch(DecimBatchArgs a) {
+    const int nblk = gridDim.x;
+    const int chunk = nblk / 8;
+    const int b = blockIdx.x;
+    const int lblk = (b & 7) * chunk + (b >> 3);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int task = lblk * 4 + wave;
+    if (task >= a.ntasks) return;
+    int vb = 0;
+    while (vb + 1 < a.nvols && a.task_start[vb + 1] <= task) ++vb;
+    const DecimVol dv = a.vols[vb];
+    decimate_task<CH, STORE>(dv, task - a.task_start[vb], threadIdx.x & 63);
+}
+
 template <int CH>
-static void launch_ch(const DecimArgs& a, int store, dim3 grid, hipStream_t st) {
+static void launch_ch(const DecimVol& a, int store, dim3 grid, hipStream_t st) {
     switch (store) {
         case 0: hipLaunchKernelGGL((k_decimate<CH, 0>), grid, dim3(256), 0, st, a); break;
         case 1: hipLaunchKernelGGL((k_decimate<CH, 1>), grid, dim3(256), 0, st, a); break;
@@ -140,14 +161,39 @@ static void launch_ch(const DecimArgs& a, int store, dim3 grid, hipStream_t st) 
     }
 }
 
-hipError_t launch_decimate(const DecimArgs& a, int chunks, int store, hipStream_t st) {
-    const int blocks = (a.ntasks + 3) / 4;
-    const dim3 grid(((blocks + 7) / 8) * 8);   // a multiple of 8 for the XCD order
+template <int CH>
+static void launch_ch_batch(const DecimBatchArgs& a, int store, dim3 grid, hipStream_t st) {
+    switch (store) {
+        case 0: hipLaunchKernelGGL((k_decimate_batch<CH, 0>), grid, dim3(256), 0, st, a); break;
+        case 1: hipLaunchKernelGGL((k_decimate_batch<CH, 1>), grid, dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_decimate_batch<CH, 2>), grid, dim3(256), 0, st, a); break;
+    }
+}
+
+static dim3 decimate_grid(int ntasks) {
+    const int blocks = (ntasks + 3) / 4;
+    return dim3(((blocks + 7) / 8) * 8);   // a multiple of 8 for the XCD order
+}
+
+hipError_t launch_decimate(const DecimVol& a, int chunks, int store, hipStream_t st) {
+    const dim3 grid = decimate_grid(a.ntasks);
     switch (chunks) {
         case 1: launch_ch<1>(a, store, grid, st); break;
         case 2: launch_ch<2>(a, store, grid, st); break;
         case 4: launch_ch<4>(a, store, grid, st); break;
         case 8: launch_ch<8>(a, store, grid, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_decimate_batch(const DecimBatchArgs& a, int chunks, int store, hipStream_t st) {
+    const dim3 grid = decimate_grid(a.ntasks);
+    switch (chunks) {
+        case 1: launch_ch_batch<1>(a, store, grid, st); break;
+        case 2: launch_ch_batch<2>(a, store, grid, st); break;
+        case 4: launch_ch_batch<4>(a, store, grid, st); break;
+        case 8: launch_ch_batch<8>(a, store, grid, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -1,0 +1,72 @@
+// Host-side plan state shared by the single-plan and the batch entry points.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "fdkod.h"
+#include "internal.h"
+
+struct fdkod_plan_s {
+    fdkod_params prm{};
+    int device = 0;
+    int n = 0, nz = 0, p = 0, s = 0, k = 0, d = 1, pd = 0, nsq = 1, store = 0;
+    int logm = 0;
+    double r = 0;
+    std::vector<fdkod::SquareDesc> sq;
+    std::vector<int2> grid;
+    int wmax = 0;
+    // decomposition kernel shape
+    int dec_chunks = 1;
+    // backprojection kernel shape
+    fdkod::BpVariant bpv{32, 32, 48, 2};
+    bool bp_ok = false;     // some variant's LDS footprint holds a block's footprint
+    int ntiles = 0;
+    int64_t ws_elems = 0;
+    float tuned_bp_ms = 0.0f, tuned_dec_ms = 0.0f;
+    // device tables
+    fdkod::SquareDesc* d_sq = nullptr;
+    float2* d_trig_p = nullptr;
+    float2* d_trig_m = nullptr;
+    float* d_ac_p = nullptr;
+    int2* d_crop = nullptr;
+    float4* d_geo_m = nullptr;
+    int2* d_grid = nullptr;
+    int2* d_grid_direct = nullptr;
+    fdkod::DecimStep* d_sched = nullptr;
+    int nsched = 0;
+    float2* d_resp = nullptr;
+    float* d_gtail = nullptr;
+    float2* d_tw = nullptr;
+    fdkod::BpTile* d_tiles = nullptr;
+    std::vector<void*> allocs;
+};
+
+namespace fdkod {
+
+fdkod_status fail(fdkod_status st, const std::string& msg);
+fdkod_status hip_fail(hipError_t e, const char* what);
+// hipMalloc through the fault-injection switch (FDKOD_FAULT=nomem)
+fdkod_status dev_alloc(std::vector<void*>& owner, void** ptr, size_t bytes);
+
+// minimal LDS footprint (columns, rows) of a 16 x 16 x zrun block for a plan's
+// geometry; false when no tile holds it
+bool bp_tiles_for(int n, int nz, double r, int zrun, int* tw, int* th);
+// a backprojection variant exists and its LDS footprint holds the plan's
+bool variant_holds(const fdkod_plan_s* pl, const BpVariant& v);
+// tasks per square of the decimation for a chunk count
+inline int dec_tasks_per_sq(int wmax, int chunks) { return (wmax + 64 * chunks - 1) / (64 * chunks); }
+// z slabs of the backprojection for a variant
+inline int bp_zslabs(int nz, int zrun) { return (nz + zrun - 1) / zrun; }
+
+// argument blocks for one plan (data pointers supplied by the caller)
+DecimVol decim_args(const fdkod_plan_s* pl, const void* filt, void* ws, int chunks);
+BpVol bp_vol(const fdkod_plan_s* pl, const void* filt, const void* ws, float* vol);
+
+}  // namespace fdkod
+
+#define HIP_TRY(expr, what)                                     \
+    do {                                                        \
+        hipError_t e_ = (expr);                                 \
+        if (e_ != hipSuccess) return fdkod::hip_fail(e_, what); \
+    } while (0)

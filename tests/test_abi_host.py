@@ -77,3 +77,22 @@ def test_plan_create_reports_invalid_before_device():
     h = ctypes.c_void_p()
     assert lib.fdkod_plan_create(ctypes.byref(prm), 0, ctypes.byref(h)) == 2
     assert h.value is None
+
+
+def test_batch_validation_before_device():
+    lib = pkg.load_library()
+    good = _lib.Params(32, 0, 45, 128.0, 1, 0, 0, 0)
+    bad = _lib.Params(32, 0, 45, 10.0, 1, 0, 0, 0)          # R too small
+    mixed = _lib.Params(32, 0, 45, 128.0, 1, 0, 2, 0)       # another store type
+    h = ctypes.c_void_p()
+    arr = (_lib.Params * 2)(good, bad)
+    assert lib.fdkod_batch_create(arr, 2, 0, ctypes.byref(h)) == 2
+    arr = (_lib.Params * 2)(good, mixed)
+    assert lib.fdkod_batch_create(arr, 2, 0, ctypes.byref(h)) == 1
+    assert lib.fdkod_batch_create(arr, 0, 0, ctypes.byref(h)) == 1
+    assert h.value is None
+    assert lib.fdkod_batch_run(None, None) == 1
+    assert lib.fdkod_batch_replay(None, None) == 1
+    assert lib.fdkod_batch_destroy(None) == 0
+    assert lib.fdkod_get_tuning(None, None) == 1
+    assert lib.fdkod_tune(None, None, None, None, None, None) == 1
