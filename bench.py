@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-direct", action="store_true", help="skip timing direct FDK")
     ap.add_argument("--no-large", action="store_true", help="skip the N=2000 workload")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--cpu-slices", type=int, default=12)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy (for HBM counter calibration)")
@@ -146,6 +147,72 @@ def summarise(wl, s, k, store, res):
     }
 
 
+def batch_volumes(bw):
+    """The batched workload's volumes: sizes drawn with the workload's seed."""
+    import numpy as np
+    rng = np.random.default_rng(bw.seed)
+    sizes = rng.choice(np.array(bw.sizes), bw.count)
+    return [dict(n=int(n), p=int(round(bw.p_per_n * n)), r=float(bw.r_per_n * n),
+                 s=int(bw.levels[int(n)])) for n in sizes]
+
+
+def run_batch(torch, pkg, bw, steps):
+    """Time the batched workload: one captured hipGraph replay per step, after
+    the autotuner; and, for comparison, the same volumes one plan at a time."""
+    from synth import phantom
+    vols = batch_volumes(bw)
+    log(f"[bench] batch {bw.name}: {len(vols)} volumes, sizes {sorted(v['n'] for v in vols)}")
+    b = pkg.Batch(vols, store="bf16")
+    projs = []
+    for i, v in enumerate(vols):
+        ell = phantom.random_ellipsoids(bw.ellipsoids, 400 + i)
+        projs.append(phantom.project(ell, v["n"], v["p"], v["r"], device="cuda:0").contiguous())
+    filts = [pl.empty_filtered() for pl in b.plans]
+    wss = [pl.empty_workspace() if pl.s > 0 else None for pl in b.plans]
+    outs = [pl.empty_volume() for pl in b.plans]
+    b.bind(projs, filts, wss, outs)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        tuning = b.tune(st)
+        b.capture(st)
+        b.replay(st)
+        st.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(steps):
+            b.replay(st)
+        e1.record(st)
+        st.synchronize()
+        graph_ms = e0.elapsed_time(e1) / steps
+        # one plan after another, eager launches, same kernels per volume
+        def sequential():
+            for pl, pr, f, w, o in zip(b.plans, projs, filts, wss, outs):
+                pl.bounds(st)
+                pl.filter(pr, f, st)
+                pl.decompose(f, w, st)
+                pl.reconstruct(f, w, o, st)
+        sequential()
+        e0.record(st)
+        sequential()
+        e1.record(st)
+        st.synchronize()
+        seq_ms = e0.elapsed_time(e1)
+    info = b.info()
+    b.close()
+    return {
+        "workload": bw.name, "volumes": len(vols), "store": "bf16",
+        "sizes": {str(n): sum(1 for v in vols if v["n"] == n) for n in bw.sizes},
+        "updates_eq": info["updates_eq"], "work_items": info["items"],
+        "persistent_blocks": info["blocks"], "tuning": {k: (round(x, 4) if isinstance(x, float) else x)
+                                                         for k, x in tuning.items()},
+        "ms_per_run_graph": round(graph_ms, 4),
+        "gvups": round(info["updates_eq"] / (graph_ms * 1e-3) / 1e9, 3),
+        "ms_one_plan_at_a_time": round(seq_ms, 4),
+        "speedup_vs_one_plan_at_a_time": round(seq_ms / graph_ms, 3),
+    }
+
+
 def measured_traffic(wl, s, store):
     """HBM bytes per backprojection launch from the committed rocprofv3 counter
     summary, or None when the kernel source or the workload differs from the
@@ -241,6 +308,13 @@ def main():
         del lres
         torch.cuda.empty_cache()
 
+    batch = None
+    if not args.no_batch:
+        batch = run_batch(torch, pkg, configs.C4, 3)
+        log(f"[bench] batch: {batch['ms_per_run_graph']} ms per graph replay, "
+            f"{batch['ms_one_plan_at_a_time']} ms one plan at a time")
+        torch.cuda.empty_cache()
+
     out = {
         "metric": METRIC,
         "value": main_sum["gvups"],
@@ -267,6 +341,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "large_workload": large,
+        "batch_workload": batch,
     }
     print(json.dumps(out), flush=True)
 

@@ -146,8 +146,14 @@ __global__ __launch_bounds__(256) void k_decimate_batch(DecimBatchArgs a) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int task = lblk * 4 + wave;
     if (task >= a.ntasks) return;
-    int vb = 0;
-    while (vb + 1 < a.nvols && a.task_start[vb + 1] <= task) ++vb;
+    // the volume holding this task: last vb with task_start[vb] <= task
+    int lo = 0, hi = a.nvols - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.task_start[mid] <= task) lo = mid;
+        else hi = mid - 1;
+    }
+    const int vb = lo;
     const DecimVol dv = a.vols[vb];
     decimate_task<CH, STORE>(dv, task - a.task_start[vb], threadIdx.x & 63);
 }

@@ -16,7 +16,6 @@ densities add where they overlap.
 """
 
 from dataclasses import dataclass
-import math
 
 import numpy as np
 import torch
@@ -70,11 +69,12 @@ def _chords(src, dirn, ell, scale, device):
 
 
 def project(ell, n, p, r, device="cpu", out_dtype=torch.float32, angles=None,
-            rows=None):
+            rows=None, chunk_rays=1 << 24):
     """Exact line integrals [P, N_v, N] of the phantom (voxel-length units).
 
     ``angles`` / ``rows`` restrict the output to some projections / detector
-    rows (default: all).  Computed in float64, returned in ``out_dtype``."""
+    rows (default: all).  Computed in float64 for chunks of angles (about
+    ``chunk_rays`` rays at a time), returned in ``out_dtype``."""
     scale = n / 2.0
     c = (n - 1) / 2.0
     angles = np.arange(p) if angles is None else np.asarray(angles)
@@ -83,14 +83,17 @@ def project(ell, n, p, r, device="cpu", out_dtype=torch.float32, angles=None,
     b = torch.tensor(rows, dtype=torch.float64, device=device) - c
     bb, aa = torch.meshgrid(b, a, indexing="ij")
     out = torch.empty((len(angles), len(rows), n), dtype=out_dtype, device=device)
-    for t, pi in enumerate(angles):
-        beta = 2.0 * math.pi * float(pi) / p
-        cb, sb = math.cos(beta), math.sin(beta)
-        src = torch.tensor([-r * cb, -r * sb, 0.0], dtype=torch.float64, device=device)
-        q = torch.stack([-aa * sb, aa * cb, bb], dim=-1)
+    per = max(1, int(chunk_rays // (len(rows) * n)))
+    for t0 in range(0, len(angles), per):
+        idx = angles[t0:t0 + per]
+        beta = torch.tensor(2.0 * np.pi * idx.astype(np.float64) / p, dtype=torch.float64, device=device)
+        cb = torch.cos(beta)[:, None, None]
+        sb = torch.sin(beta)[:, None, None]
+        src = torch.stack([-r * cb, -r * sb, torch.zeros_like(cb)], dim=-1)      # [A, 1, 1, 3]
+        q = torch.stack([-aa[None] * sb, aa[None] * cb, bb[None].expand(len(idx), -1, -1)], dim=-1)
         d = q - src
         d = d / torch.linalg.norm(d, dim=-1, keepdim=True)
-        out[t] = _chords(src, d, ell, scale, device).to(out_dtype)
+        out[t0:t0 + len(idx)] = _chords(src, d, ell, scale, device).to(out_dtype)
     return out
 
 
