@@ -29,4 +29,4 @@ Parity status of every function is stated in its docstring ("pinned by" lists
 the independent facts the tests check it against).
 """
 
-from . import geometry, fdk, fdkod, storage, metrics  # noqa: F401
+from . import geometry, fdk, fdkod, storage, metrics, learned  # noqa: F401
