@@ -24,7 +24,10 @@
  *   projections  float32 [P][N][N]       (p, v, u), u fastest
  *   filtered     store type [P][N][N]    same layout (fdkod_filter output)
  *   workspace    store type, decimated sub-sinograms of every square,
- *                fdkod_plan_info().workspace_bytes bytes (unused when s = 0)
+ *                fdkod_plan_info().workspace_bytes bytes (unused when s = 0):
+ *                square q (q = by 2^s + bx) holds Y_q as [P'][N][W_q]
+ *                (m, v, j), j fastest, from element offset
+ *                sum_{q' < q} roundup(P' N W_q', 64)
  *   volume       float32 [N_z][N][N]     (l, j, i), x fastest
  *
  * Ownership and streams
@@ -232,6 +235,59 @@ fdkod_status fdkod_batch_info(fdkod_batch_t batch, int64_t* items, int32_t* bloc
  * Synchronises with the plan's device. */
 fdkod_status fdkod_get_bounds(fdkod_plan_t plan, float* ac_p, float* ac_m, float* amin_m,
                               float* amax_m, int32_t* u0, int32_t* width, int32_t* rect);
+
+/* ---------------------------------------------------------------------------
+ * Learned decimation filter.  Sec. 2.1 leaves the low-pass filter of the
+ * angular decimation open (the quality depends on its implementation).  This
+ * filter adds a trained correction R to the triangle decimation T of every
+ * square q and detector row v:
+ *
+ *   Y_q[m][v][j] = T[m][v][j] + R[m][v][j],   R = conv2(ReLU(conv1(S)))
+ *   conv1: H_k(p, j) = b1_k + sum_{a,b<5} W1[k][a][b] S((p + (a-2) d) mod P, j + b - 2)
+ *   R(m, j) = b2 + sum_{k,a,b<5} W2[k][a][b] A_k((c(m) + (a-2) d) mod P, j + b - 2)
+ *
+ * S(p, j) = Lin(filt[p][v][.], a_c(beta_p) + u0_q + j) is the cropped and
+ * shifted full-rate sub-sinogram (zero outside the columns [0, W_q)),
+ * A = ReLU(H) on [0, W_q) and zero outside, c(m) = floor(m P / P' + 1/2) mod P
+ * the original angle nearest to beta'_m, d = max(1, D / 4), k < 16 channels.
+ * Parameters: FDKOD_LEARNED_PARAMS BF16 values on the device, in the order
+ * W1 [16][5][5], b1 [16], W2 [16][5][5], b2.  Both convolutions multiply BF16
+ * operands (S, the weights, the activations) with FP32 accumulation.  With
+ * W2 = 0 and b2 = 0 the result is the triangle decimation.  Requires s > 0 and
+ * W_q <= 512 for every square (FDKOD_E_UNSUPPORTED otherwise).
+ * ------------------------------------------------------------------------- */
+#define FDKOD_LEARNED_PARAMS 817
+
+/* fdkod_decompose followed by the learned correction: ws receives Y. */
+fdkod_status fdkod_learned_decompose(fdkod_plan_t plan, const void* filt, void* ws,
+                                     const uint16_t* weights, fdkod_stream_t stream);
+
+/* Training: grad (float32 [FDKOD_LEARNED_PARAMS], overwritten) receives the
+ * gradient of sum_{q,m,v,j} R[m][v][j] dws[m][v][j] with respect to the
+ * parameters.  dws: float32, the workspace layout (workspace_bytes / element
+ * size elements).  The BF16 roundings of the forward pass are held fixed. */
+fdkod_status fdkod_learned_backward(fdkod_plan_t plan, const void* filt, const float* dws,
+                                    const uint16_t* weights, float* grad, fdkod_stream_t stream);
+
+/* Transpose of fdkod_reconstruct for s > 0: dws (float32, workspace layout,
+ * overwritten) receives, for every voxel with value resid and every decimated
+ * angle, resid * (pi / P') U^-2 spread over the four samples of its bilinear
+ * interpolation.  resid: float32 [N_z][N][N].  Uses float atomics, so the
+ * summation order (and the last bits) vary from run to run. */
+fdkod_status fdkod_reconstruct_adjoint(fdkod_plan_t plan, const float* resid, float* dws,
+                                       fdkod_stream_t stream);
+
+/* Squared-error residual on the current device: resid = 2 (f - ref) and
+ * *loss = sum (f - ref)^2 (float64, on the device), over count floats. */
+fdkod_status fdkod_sq_residual(const float* f, const float* ref, float* resid, double* loss,
+                               int64_t count, fdkod_stream_t stream);
+
+/* One AdamW step on the current device over count float32 master weights
+ * (bias-corrected moments m1, m2; decoupled weight decay), then their BF16
+ * copy w_bf16 (round to nearest even).  step counts from 1. */
+fdkod_status fdkod_adamw_step(float* master, float* m1, float* m2, const float* grad,
+                              uint16_t* w_bf16, int32_t count, int32_t step, float lr, float beta1,
+                              float beta2, float eps, float weight_decay, fdkod_stream_t stream);
 
 /* Static text for a status code. */
 const char* fdkod_status_str(fdkod_status st);

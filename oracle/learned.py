@@ -23,9 +23,12 @@ triangle.  16 channels, 5 x 5 taps: 817 parameters.  conv2 starts at zero,
 so the untrained network is exactly the plain decimation.
 
 Precision form of the GPU kernels (emulated here when bf16=True): weights are
-BF16 (rounded from an FP32 master copy); conv1 multiplies BF16 inputs (S) by
-BF16 weights with FP32 accumulation on matrix cores, conv2 runs in FP32 from
-FP32 activations; the conv1 weight gradient multiplies BF16 dH by BF16 S.
+BF16 (rounded from an FP32 master copy); both convolutions multiply BF16
+operands with FP32 accumulation on matrix cores: conv1 takes BF16 S, conv2
+takes the BF16-rounded activations.  The gradients are those of this rounded
+forward with the roundings held fixed: dW2 uses the BF16 activations, dA
+passes through the rounding unchanged, and the conv1 weight gradient
+multiplies BF16 dH by BF16 S.
 
 Pinned by (tests/test_oracle_learned.py): zero conv2 gives the plain
 decimation exactly; central finite differences of the loss match the analytic
@@ -109,6 +112,8 @@ def forward(s_sub, net, d_factor, pd, bf16=False):
     h = conv1(s_sub, net, used.reshape(-1), d, bf16)                 # [..., P'*5, 16, W]
     h = h.reshape(s_sub.shape[:-2] + (pd, TAPS, CH, s_sub.shape[-1]))
     a_act = np.maximum(h, 0.0)
+    if bf16:
+        a_act = storage.round_bf16(a_act)
     w2 = net["w2"]
     r = np.zeros(s_sub.shape[:-2] + (pd, s_sub.shape[-1])) + net["b2"][0]
     for a in range(TAPS):
@@ -131,6 +136,8 @@ def backward(s_sub, net, d_factor, pd, d_r, cache, bf16=False):
     d = cache["d"]
     h = cache["h"]                                                   # [..., P', 5, 16, W]
     a_act = np.maximum(h, 0.0)
+    if bf16:
+        a_act = storage.round_bf16(a_act)
     w2 = net["w2"]
     lead = tuple(range(d_r.ndim - 2))
     grads = dict(b2=np.array([d_r.sum()]))

@@ -81,6 +81,12 @@ EXPORTS = {
     "fdkod_batch_tune": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(Tuning)]),
     "fdkod_batch_info": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
+    "fdkod_learned_decompose": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "fdkod_learned_backward": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    "fdkod_reconstruct_adjoint": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "fdkod_sq_residual": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int64, _VP]),
+    "fdkod_adamw_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32]
+                         + [ctypes.c_float] * 5 + [_VP]),
     "fdkod_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "fdkod_last_error": (ctypes.c_char_p, []),
     "fdkod_version": (ctypes.c_int32, []),
@@ -124,6 +130,41 @@ def validate(n, p, r, s=0, skip=0, nz=0, store="f32"):
     """Host-only parameter check (no device needed)."""
     prm = _params(n, p, r, s, skip, nz, store)
     _check(load_library().fdkod_validate(ctypes.byref(prm)))
+
+
+LEARNED_PARAMS = 817
+
+
+def _dev_tensor(t, dtype, name, numel=None):
+    if t is None or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must hold {numel} elements")
+
+
+def sq_residual(f, ref, resid, loss, stream=None):
+    """resid = 2 (f - ref), loss[0] = sum (f - ref)^2 (float64 device scalar)."""
+    import torch
+    for t, nm in ((f, "f"), (ref, "ref"), (resid, "resid")):
+        _dev_tensor(t, torch.float32, nm, f.numel())
+    _dev_tensor(loss, torch.float64, "loss", 1)
+    _check(load_library().fdkod_sq_residual(
+        ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(ref.data_ptr()),
+        ctypes.c_void_p(resid.data_ptr()), ctypes.c_void_p(loss.data_ptr()), f.numel(),
+        _stream_ptr(stream)))
+
+
+def adamw_step(master, m1, m2, grad, w_bf16, step, lr, beta1=0.9, beta2=0.999, eps=1e-8,
+               weight_decay=0.0, stream=None):
+    """One AdamW step on the device; refreshes the BF16 copy w_bf16."""
+    import torch
+    n = master.numel()
+    for t, nm in ((master, "master"), (m1, "m1"), (m2, "m2"), (grad, "grad")):
+        _dev_tensor(t, torch.float32, nm, n)
+    _dev_tensor(w_bf16, torch.bfloat16, "w_bf16", n)
+    _check(load_library().fdkod_adamw_step(
+        *(ctypes.c_void_p(t.data_ptr()) for t in (master, m1, m2, grad, w_bf16)), n, int(step),
+        float(lr), float(beta1), float(beta2), float(eps), float(weight_decay), _stream_ptr(stream)))
 
 
 def _stream_ptr(stream):
@@ -276,6 +317,49 @@ class Plan:
         _check(self._lib.fdkod_backproject(
             self._h, ctypes.c_void_p(filt.data_ptr()), ctypes.c_void_p(vol.data_ptr()),
             ctypes.c_void_p(ws.data_ptr() if ws is not None else 0), _stream_ptr(stream)))
+
+    # learned decimation ---------------------------------------------------
+    @property
+    def workspace_elems(self):
+        return int(self.workspace_bytes) // _STORE_BYTES[self.store]
+
+    def _chk_weights(self, w):
+        import torch
+        self._chk(w, (LEARNED_PARAMS,), torch.bfloat16, "weights")
+
+    def _chk_dws(self, dws):
+        import torch
+        self._chk(dws, (self.workspace_elems,), torch.float32, "dws")
+
+    def learned_decompose(self, filt, ws, weights, stream=None):
+        """Triangle decimation plus the learned correction (ws receives Y)."""
+        self._chk(filt, (self.p, self.n, self.n), self.store_torch_dtype(), "filt")
+        self._chk_ws(ws)
+        self._chk_weights(weights)
+        _check(self._lib.fdkod_learned_decompose(
+            self._h, ctypes.c_void_p(filt.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+            ctypes.c_void_p(weights.data_ptr()), _stream_ptr(stream)))
+
+    def learned_backward(self, filt, dws, weights, grad, stream=None):
+        """grad = d/dweights of sum(R * dws) (float32 [817], overwritten)."""
+        import torch
+        self._chk(filt, (self.p, self.n, self.n), self.store_torch_dtype(), "filt")
+        self._chk_dws(dws)
+        self._chk_weights(weights)
+        self._chk(grad, (LEARNED_PARAMS,), torch.float32, "grad")
+        _check(self._lib.fdkod_learned_backward(
+            self._h, ctypes.c_void_p(filt.data_ptr()), ctypes.c_void_p(dws.data_ptr()),
+            ctypes.c_void_p(weights.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+            _stream_ptr(stream)))
+
+    def reconstruct_adjoint(self, resid, dws, stream=None):
+        """dws = transpose of the reconstruction applied to resid."""
+        import torch
+        self._chk(resid, (self.nz, self.n, self.n), torch.float32, "resid")
+        self._chk_dws(dws)
+        _check(self._lib.fdkod_reconstruct_adjoint(
+            self._h, ctypes.c_void_p(resid.data_ptr()), ctypes.c_void_p(dws.data_ptr()),
+            _stream_ptr(stream)))
 
     def get_bounds(self):
         """Bounds tables as numpy arrays (synchronises)."""

@@ -1,0 +1,121 @@
+// Host entry points of the learned decimation filter and its training step
+// (forward correction, weight gradient, transpose of the backprojection,
+// squared-error residual, AdamW).  Every call is asynchronous on the given
+// stream and allocates nothing.
+#include <cmath>
+
+#include "plan.h"
+
+using namespace fdkod;
+
+namespace {
+
+fdkod_status learned_check(const fdkod_plan_s* pl) {
+    if (pl->s == 0) return fail(FDKOD_E_UNSUPPORTED, "the learned decimation needs s > 0");
+    if (pl->wmax > kLearnedMaxWidth)
+        return fail(FDKOD_E_UNSUPPORTED, "a square is wider than 512 local columns");
+    return FDKOD_OK;
+}
+
+LearnedArgs learned_args(const fdkod_plan_s* pl, const void* filt, void* ws, const float* dws,
+                         const uint16_t* w, float* grad) {
+    LearnedArgs a;
+    a.filt = filt;
+    a.ws = ws;
+    a.dws = dws;
+    a.squares = pl->d_sq;
+    a.grid = pl->d_grid;
+    a.ac_p = pl->d_ac_p;
+    a.w = w;
+    a.grad = grad;
+    a.n = pl->n;
+    a.p = pl->p;
+    a.pd = pl->pd;
+    a.nsq = pl->nsq;
+    a.d = pl->d / 4 > 1 ? pl->d / 4 : 1;
+    a.ntasks = pl->nsq * pl->n;
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+fdkod_status fdkod_learned_decompose(fdkod_plan_t pl, const void* filt, void* ws, const uint16_t* weights,
+                                     fdkod_stream_t stream) {
+    if (!pl || !filt || !ws || !weights) return fail(FDKOD_E_ARG, "NULL argument");
+    fdkod_status st = learned_check(pl);
+    if (st != FDKOD_OK) return st;
+    if ((st = fdkod_decompose(pl, filt, ws, stream)) != FDKOD_OK) return st;
+    const LearnedArgs a = learned_args(pl, filt, ws, nullptr, weights, nullptr);
+    HIP_TRY(launch_learned_fwd(a, pl->store, (hipStream_t)stream), "learned decimation kernel launch");
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_learned_backward(fdkod_plan_t pl, const void* filt, const float* dws,
+                                    const uint16_t* weights, float* grad, fdkod_stream_t stream) {
+    if (!pl || !filt || !dws || !weights || !grad) return fail(FDKOD_E_ARG, "NULL argument");
+    fdkod_status st = learned_check(pl);
+    if (st != FDKOD_OK) return st;
+    const LearnedArgs a = learned_args(pl, filt, nullptr, dws, weights, grad);
+    HIP_TRY(launch_learned_bwd(a, pl->store, (hipStream_t)stream), "learned gradient kernel launch");
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_reconstruct_adjoint(fdkod_plan_t pl, const float* resid, float* dws,
+                                       fdkod_stream_t stream) {
+    if (!pl || !resid || !dws) return fail(FDKOD_E_ARG, "NULL argument");
+    if (pl->s == 0) return fail(FDKOD_E_UNSUPPORTED, "the adjoint is defined for s > 0");
+    AdjArgs a;
+    a.resid = resid;
+    a.dws = dws;
+    a.squares = pl->d_sq;
+    a.grid = pl->d_grid;
+    a.trig = pl->d_trig_m;
+    a.n = pl->n;
+    a.nz = pl->nz;
+    a.pd = pl->pd;
+    a.sq_side = 1 << pl->s;
+    a.r = (float)pl->r;
+    a.cu = (float)((pl->n - 1) / 2.0);
+    a.cv = a.cu;
+    a.cz = (float)((pl->nz - 1) / 2.0);
+    a.scale = (float)(M_PI / pl->pd);
+    a.ws_elems = pl->ws_elems;
+    HIP_TRY(launch_bp_adjoint(a, (hipStream_t)stream), "adjoint kernel launch");
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_sq_residual(const float* f, const float* ref, float* resid, double* loss, int64_t count,
+                               fdkod_stream_t stream) {
+    if (!f || !ref || !resid || !loss) return fail(FDKOD_E_ARG, "NULL argument");
+    if (count < 0) return fail(FDKOD_E_ARG, "negative count");
+    HIP_TRY(launch_residual(f, ref, resid, loss, count, (hipStream_t)stream), "residual kernel launch");
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_adamw_step(float* master, float* m1, float* m2, const float* grad, uint16_t* w_bf16,
+                              int32_t count, int32_t step, float lr, float beta1, float beta2, float eps,
+                              float weight_decay, fdkod_stream_t stream) {
+    if (!master || !m1 || !m2 || !grad || !w_bf16) return fail(FDKOD_E_ARG, "NULL argument");
+    if (count <= 0 || step <= 0) return fail(FDKOD_E_ARG, "count and step must be positive");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f && lr >= 0.0f))
+        return fail(FDKOD_E_ARG, "invalid AdamW hyper-parameters");
+    AdamArgs a;
+    a.master = master;
+    a.m1 = m1;
+    a.m2 = m2;
+    a.grad = grad;
+    a.w_bf16 = w_bf16;
+    a.count = count;
+    a.step = step;
+    a.lr = lr;
+    a.beta1 = beta1;
+    a.beta2 = beta2;
+    a.eps = eps;
+    a.weight_decay = weight_decay;
+    HIP_TRY(launch_adamw(a, (hipStream_t)stream), "AdamW kernel launch");
+    return FDKOD_OK;
+}
+
+}  // extern "C"

@@ -136,6 +136,56 @@ int backproject_batch_occupancy(const BpVariant& var, int store);
 bool backproject_variant_exists(const BpVariant& var);
 hipError_t launch_reset_counter(unsigned* counter, hipStream_t st);
 
+// Learned decimation (conv net over angle x column added to the triangle
+// decimation): 817 BF16 parameters W1 [16][5][5], b1 [16], W2 [16][5][5], b2.
+constexpr int kLearnedParams = 817;
+constexpr int kLearnedMaxWidth = 512;   // widest square (local columns) it takes
+
+struct LearnedArgs {
+    const void* filt;        // [P][N][N] store type
+    void* ws;                // decimated data, store type (forward adds R)
+    const float* dws;        // dL/dY, FP32, workspace layout (backward)
+    const SquareDesc* squares;
+    const int2* grid;        // u0, W per square
+    const float* ac_p;       // [nsq][P] a_c(beta_p)
+    const uint16_t* w;       // BF16 parameters
+    float* grad;             // [817] FP32 (backward, overwritten)
+    int n, p, pd, nsq;
+    int d;                   // angle dilation max(1, D / 4)
+    int ntasks;              // nsq * n
+};
+
+// Transpose of the per-square backprojection (training).
+struct AdjArgs {
+    const float* resid;      // [nz][n][n]
+    float* dws;              // FP32, workspace layout, overwritten
+    const SquareDesc* squares;
+    const int2* grid;
+    const float2* trig;      // cos, sin of beta'_m, [pd]
+    int n, nz, pd;
+    int sq_side;             // 2^s
+    float r, cu, cv, cz;
+    float scale;             // pi / P'
+    int64_t ws_elems;
+};
+
+struct AdamArgs {
+    float* master;           // FP32 parameters
+    float* m1;
+    float* m2;
+    const float* grad;
+    uint16_t* w_bf16;        // BF16 copy used by the kernels
+    int count, step;
+    float lr, beta1, beta2, eps, weight_decay;
+};
+
+hipError_t launch_learned_fwd(const LearnedArgs& a, int store, hipStream_t st);
+hipError_t launch_learned_bwd(const LearnedArgs& a, int store, hipStream_t st);
+hipError_t launch_bp_adjoint(const AdjArgs& a, hipStream_t st);
+hipError_t launch_residual(const float* f, const float* ref, float* r, double* loss, int64_t count,
+                           hipStream_t st);
+hipError_t launch_adamw(const AdamArgs& a, hipStream_t st);
+
 // Limits the host checks before choosing a backprojection variant.
 constexpr int kTileXY = 16;      // voxels per tile side in x and y
 constexpr int kDecimUnroll = 4;  // schedule steps the decimation kernel loads at once

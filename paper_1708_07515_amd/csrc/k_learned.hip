@@ -1,0 +1,446 @@
+// Learned angular decimation and its training kernels (gfx950).
+//
+// The paper leaves the low-pass filter of the angular decimation open (Sec. 2.1:
+// quality depends on "the low-pass filter implementation").  The learned filter
+// adds a correction R to the plain triangle decimation T of every square q and
+// detector row v:
+//
+//   Y_q[m][v][j] = T[m][j] + R[m][j],   R = conv2(ReLU(conv1(S)))
+//   conv1: H_k(p, j) = b1_k + sum_{a,b} W1[k][a][b] S((p + (a-2) d) mod P, j + b - 2)
+//   R(m, j) = b2 + sum_{k,a,b} W2[k][a][b] A_k((c(m) + (a-2) d) mod P, j + b - 2)
+//
+// with S the cropped, shifted full-rate sub-sinogram (Sec. 2.1), A = ReLU(H)
+// on the columns [0, W) and zero outside, c(m) the original angle nearest to
+// the decimated angle m, d = max(1, D / 4), 16 channels, 5 x 5 taps.
+//
+// Matrix cores: conv1 is an MFMA 16x16x16 BF16 product per 16 columns,
+//   H^T[16 ch][16 col] = W1[16 ch][32 taps] x X^T[32 taps][16 col]
+// (two K steps; X^T gathers S at the taps), FP32 accumulation.  Its output
+// layout (lane l holds channels 4(l/16)..+3 of column l%16) is exactly the
+// B-operand layout of a second MFMA, which contracts the channels of conv2:
+//   Q[b][col] += W2_a[16 (b, 5 used)][16 ch] x A^T[16 ch][16 col]
+// accumulated over the five dilated angles a; then R[j] = b2 + sum_b Q[b][j+b-2].
+// The weight gradient of conv1 is an MFMA reduction over positions:
+//   dW1^T[32 taps][16 ch] += X[taps][16 pos] x dH[16 pos][16 ch].
+// Weights are BF16 (817 values: W1 [16][5][5], b1 [16], W2 [16][5][5], b2).
+#include "internal.h"
+#include "dtype.h"
+#include "geom.h"
+
+namespace fdkod {
+
+typedef short s4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+constexpr int kLearnedWMax = kLearnedMaxWidth;
+constexpr int kSP = kLearnedWMax + 4;  // LDS pitch of S and Q rows (two zero columns each side)
+constexpr int kOffW1 = 0, kOffB1 = 400, kOffW2 = 416, kOffB2 = 816;
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+__device__ __forceinline__ short f2bf(float v) {
+    uint32_t b = __float_as_uint(v);
+    b += 0x7FFFu + ((b >> 16) & 1u);   // round to nearest even (inputs are finite)
+    return (short)(b >> 16);
+}
+
+__device__ __forceinline__ int centre_angle(int m, int p, int pd) {
+    return (int)(((2ll * m * p + pd) / (2ll * pd)) % p);
+}
+
+// S tile for decimated angle m: rows t = 0..8 hold the original angles
+// c(m) + (t - 4) d; column jj in [-2, 16 ntile + 2) sits at index jj + 2 (every
+// column the 16-column tiles read), zero outside [0, W).  S(p, j) = linear
+// interpolation of the filtered row at the square's local column j (the crop
+// and shift of FDK-OD).
+template <int STORE>
+__device__ __forceinline__ void build_s_tile(const LearnedArgs& a, int q, int v, int m, int width,
+                                             int ntile, int u0, float* s_tile) {
+    using S = Store<STORE>;
+    using T = typename S::T;
+    const int c = centre_angle(m, a.p, a.pd);
+    const int n = a.n;
+    const T* filt = (const T*)a.filt;
+    const int cols = 16 * ntile + 4;
+    for (int e = threadIdx.x; e < 9 * cols; e += blockDim.x) {
+        const int t = e / cols;
+        const int jj = e - t * cols - 2;
+        float val = 0.0f;
+        if (jj >= 0 && jj < width) {
+            int p = (c + (t - 4) * a.d) % a.p;
+            if (p < 0) p += a.p;
+            const float o = a.ac_p[(size_t)q * a.p + p] + (float)u0;
+            const float of = floorf(o);
+            const float phi = o - of;
+            const int i0 = (int)of + jj;
+            const T* row = filt + ((size_t)p * n + v) * n;
+            const float x0 = ((unsigned)i0 < (unsigned)n) ? S::load(row, i0) : 0.0f;
+            const float x1 = ((unsigned)(i0 + 1) < (unsigned)n) ? S::load(row, i0 + 1) : 0.0f;
+            val = fmaf(phi, x1 - x0, x0);
+        }
+        s_tile[t * kSP + jj + 2] = val;
+    }
+}
+
+// conv1 for one dilated angle a2 of decimated angle m and one 16-column tile:
+// returns H^T in the MFMA output layout (lane l: channels 4(l/16)+i, column
+// col0 + l%16), without the bias.
+__device__ __forceinline__ f4v conv1_tile(const float* s_tile, int a2, int col0, const s4v w1op[2]) {
+    const int lane = threadIdx.x & 63;
+    const int lr = lane & 15, lg = lane >> 4;
+    f4v h = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+        s4v x;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int tap = 16 * ks + 4 * lg + i;
+            float sv = 0.0f;
+            if (tap < 25) {
+                const int a1 = tap / 5, b1 = tap - 5 * (tap / 5);
+                sv = s_tile[(a2 + a1) * kSP + col0 + lr + b1];   // column col0+lr+b1-2, index +2
+            }
+            x[i] = f2bf(sv);
+        }
+        h = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1op[ks], x, h, 0, 0, 0);
+    }
+    return h;
+}
+
+// Weight operands held in registers for the whole kernel.
+__device__ __forceinline__ void load_weight_operands(const uint16_t* w, s4v w1op[2], s4v w2op[5],
+                                                     float b1v[4]) {
+    const int lane = threadIdx.x & 63;
+    const int lr = lane & 15, lg = lane >> 4;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int tap = 16 * ks + 4 * lg + i;               // A[row = channel lr][k = tap]
+            w1op[ks][i] = tap < 25 ? (short)w[kOffW1 + lr * 25 + tap] : (short)0;
+        }
+#pragma unroll
+    for (int a2 = 0; a2 < 5; ++a2)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int ch = 4 * lg + i;                          // A[row = b2 = lr][k = channel]
+            w2op[a2][i] = lr < 5 ? (short)w[kOffW2 + ch * 25 + a2 * 5 + lr] : (short)0;
+        }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b1v[i] = bf2f(w[kOffB1 + 4 * lg + i]);
+}
+
+// Forward (inference): adds R to the plain decimation already in the workspace.
+template <int STORE>
+__global__ __launch_bounds__(256) void k_learned_fwd(LearnedArgs a) {
+    using S = Store<STORE>;
+    using T = typename S::T;
+    __shared__ float s_tile[9 * kSP];
+    __shared__ float q_tile[5 * kSP];
+    const int task = blockIdx.x;
+    if (task >= a.ntasks) return;
+    const int q = task % a.nsq, v = task / a.nsq;
+    const int2 gd = a.grid[q];
+    const int u0 = gd.x, width = gd.y;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lg = lane >> 4;
+    s4v w1op[2], w2op[5];
+    float b1v[4];
+    load_weight_operands(a.w, w1op, w2op, b1v);
+    const float b2 = bf2f(a.w[kOffB2]);
+    for (int e = threadIdx.x; e < 5 * kSP; e += blockDim.x) q_tile[e] = 0.0f;
+    const int ntile = (width + 15) >> 4;
+    T* ws = (T*)a.ws;
+    const int64_t yoff = a.squares[q].y_off;
+    for (int m = 0; m < a.pd; ++m) {
+        build_s_tile<STORE>(a, q, v, m, width, ntile, u0, s_tile);
+        __syncthreads();
+        for (int tile = wave; tile < ntile; tile += 4) {
+            const int col0 = tile * 16;
+            const bool cin = col0 + lr < width;
+            f4v qacc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int a2 = 0; a2 < 5; ++a2) {
+                const f4v h = conv1_tile(s_tile, a2, col0, w1op);
+                s4v act;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) act[i] = f2bf(cin ? fmaxf(h[i] + b1v[i], 0.0f) : 0.0f);
+                qacc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w2op[a2], act, qacc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int bb = 4 * lg + i;
+                if (bb < 5) q_tile[bb * kSP + col0 + lr + 2] = qacc[i];
+            }
+        }
+        __syncthreads();
+        const size_t base = (size_t)yoff + ((size_t)m * a.n + v) * width;
+        for (int j = threadIdx.x; j < width; j += blockDim.x) {
+            float r = b2;
+#pragma unroll
+            for (int bb = 0; bb < 5; ++bb) r += q_tile[bb * kSP + j + bb];
+            S::put(ws, base + j, S::load(ws, base + j) + r);
+        }
+        __syncthreads();
+    }
+}
+
+// 16-lane (column) sum within each group of a wavefront.
+__device__ __forceinline__ float sum16(float x) {
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Backward: gradients of sum_{m,v,j} R[m][v][j] dY[m][v][j] with respect to
+// the weights (dY = dL/dY in FP32, workspace layout), accumulated into grad.
+template <int STORE>
+__global__ __launch_bounds__(256) void k_learned_bwd(LearnedArgs a) {
+    __shared__ float s_tile[9 * kSP];
+    __shared__ float dr[kSP];
+    __shared__ float w2f[16 * 25];
+    __shared__ float gw2[16 * 25];
+    __shared__ float gb1[16];
+    __shared__ float tr[4][16 * 17];
+    __shared__ float gb2;
+    const int task = blockIdx.x;
+    if (task >= a.ntasks) return;
+    const int q = task % a.nsq, v = task / a.nsq;
+    const int2 gd = a.grid[q];
+    const int u0 = gd.x, width = gd.y;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lg = lane >> 4;
+    s4v w1op[2], w2op[5];
+    float b1v[4];
+    load_weight_operands(a.w, w1op, w2op, b1v);
+    for (int e = threadIdx.x; e < 400; e += blockDim.x) {
+        w2f[e] = bf2f(a.w[kOffW2 + e]);
+        gw2[e] = 0.0f;
+    }
+    if (threadIdx.x < 16) gb1[threadIdx.x] = 0.0f;
+    if (threadIdx.x == 0) gb2 = 0.0f;
+    for (int e = threadIdx.x; e < kSP; e += blockDim.x) dr[e] = 0.0f;
+    f4v gw1[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
+    float db2 = 0.0f;
+    const int ntile = (width + 15) >> 4;
+    const int64_t yoff = a.squares[q].y_off;
+    float* trw = tr[wave];
+    __syncthreads();
+    for (int m = 0; m < a.pd; ++m) {
+        build_s_tile<STORE>(a, q, v, m, width, ntile, u0, s_tile);
+        const size_t base = (size_t)yoff + ((size_t)m * a.n + v) * width;
+        for (int j = threadIdx.x; j < width; j += blockDim.x) {
+            const float g = a.dws[base + j];
+            dr[j + 2] = g;
+            db2 += g;
+        }
+        __syncthreads();
+        for (int tile = wave; tile < ntile; tile += 4) {
+            const int col0 = tile * 16;
+            const int col = col0 + lr;
+            const bool cin = col < width;
+#pragma unroll 1
+            for (int a2 = 0; a2 < 5; ++a2) {
+                const f4v h = conv1_tile(s_tile, a2, col0, w1op);
+                float dh[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int ch = 4 * lg + i;
+                    const float hv = h[i] + b1v[i];
+                    // the BF16 activation conv2 multiplied in the forward pass
+                    const float av = cin ? bf2f((uint16_t)f2bf(fmaxf(hv, 0.0f))) : 0.0f;
+                    // A(col) feeds R(col - b + 2): dA = sum_b W2[ch][a2][b] dR(col - b + 2)
+                    float da = 0.0f;
+#pragma unroll
+                    for (int bb = 0; bb < 5; ++bb) {
+                        const float g = dr[col - bb + 4];
+                        da = fmaf(w2f[ch * 25 + a2 * 5 + bb], g, da);
+                        const float s = sum16(av * g);        // dW2[ch][a2][bb] over the 16 columns
+                        if (lr == 0) atomicAdd(&gw2[ch * 25 + a2 * 5 + bb], s);
+                    }
+                    dh[i] = (cin && hv > 0.0f) ? da : 0.0f;
+                    const float sb = sum16(dh[i]);
+                    if (lr == 0) atomicAdd(&gb1[ch], sb);
+                    trw[ch * 17 + lr] = dh[i];               // dH[ch][col] for the transpose
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                // B operand: lane holds dH[pos = 4 lg + i][ch = lr]
+                s4v dhop;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) dhop[i] = f2bf(trw[lr * 17 + 4 * lg + i]);
+#pragma unroll
+                for (int tt = 0; tt < 2; ++tt) {
+                    // A operand: lane holds X[tap = 16 tt + lr][pos = 4 lg + i]
+                    s4v xop;
+                    const int tap = 16 * tt + lr;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        float sv = 0.0f;
+                        if (tap < 25) {
+                            const int a1 = tap / 5, b1 = tap - 5 * (tap / 5);
+                            sv = s_tile[(a2 + a1) * kSP + col0 + 4 * lg + i + b1];
+                        }
+                        xop[i] = f2bf(sv);
+                    }
+                    gw1[tt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xop, dhop, gw1[tt], 0, 0, 0);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        __syncthreads();
+    }
+    // flush: dW1^T tiles (lane holds taps 16 tt + 4 lg + i of channel lr)
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int tap = 16 * tt + 4 * lg + i;
+            if (tap < 25) atomicAdd(&a.grad[kOffW1 + lr * 25 + tap], gw1[tt][i]);
+        }
+    // db2: wave sums, then one atomic per wave
+    float s = db2;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) atomicAdd(&gb2, s);
+    __syncthreads();
+    for (int e = threadIdx.x; e < 400; e += blockDim.x) atomicAdd(&a.grad[kOffW2 + e], gw2[e]);
+    if (threadIdx.x < 16) atomicAdd(&a.grad[kOffB1 + threadIdx.x], gb1[threadIdx.x]);
+    if (threadIdx.x == 0) atomicAdd(&a.grad[kOffB2], gb2);
+}
+
+// Transpose of the backprojection of decimated data (training): for every
+// voxel and decimated angle, scatter the residual with the bilinear weights
+// and (pi / P') U^-2 into dY (FP32, workspace layout).
+__global__ __launch_bounds__(256) void k_bp_adjoint(AdjArgs a) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nvox = (int64_t)a.n * a.n * a.nz;
+    if (idx >= nvox) return;
+    const int i = (int)(idx % a.n);
+    const int j = (int)((idx / a.n) % a.n);
+    const int l = (int)(idx / ((int64_t)a.n * a.n));
+    const float res = a.resid[idx];
+    if (res == 0.0f) return;
+    // square of column i / row j: near-equal blocks, larger first
+    const int parts = a.sq_side;
+    const int base = a.n / parts, extra = a.n % parts;
+    const int cut = extra * (base + 1);
+    const int bx = i < cut ? i / (base + 1) : extra + (i - cut) / base;
+    const int by = j < cut ? j / (base + 1) : extra + (j - cut) / base;
+    const int q = by * parts + bx;
+    const SquareDesc sq = a.squares[q];
+    const int2 gd = a.grid[q];
+    const int u0 = gd.x, width = gd.y;
+    const float dx = (float)i - a.cu - sq.xc, dy = (float)j - a.cu - sq.yc;
+    const float z = (float)l - a.cz;
+    for (int m = 0; m < a.pd; ++m) {
+        const float2 t = a.trig[m];
+        const float dc = a.r + sq.xc * t.x + sq.yc * t.y;
+        const float lc = sq.yc * t.x - sq.xc * t.y;
+        const float rdc = 1.0f / dc;
+        const float tau = rel_column(dx, dy, t.x, t.y, a.r, dc, lc, rdc) + a.cu - (float)u0;
+        const float d = dc + dx * t.x + dy * t.y;
+        const float invu = a.r / d;
+        const float w = a.scale * invu * invu * res;
+        const float vv = fmaf(z, invu, a.cv);
+        const float vf = floorf(vv), fv = vv - vf;
+        const float tf = floorf(tau), fu = tau - tf;
+        const int iu = min(max((int)tf, 0), width - 2);
+        const int iv = (int)vf;
+        const size_t plane = (size_t)sq.y_off + (size_t)m * a.n * width;
+#pragma unroll
+        for (int dv = 0; dv < 2; ++dv) {
+            const int row = iv + dv;
+            if ((unsigned)row >= (unsigned)a.n) continue;
+            const float wv = dv ? fv : 1.0f - fv;
+            float* p = a.dws + plane + (size_t)row * width + iu;
+            atomicAdd(p, w * wv * (1.0f - fu));
+            atomicAdd(p + 1, w * wv * fu);
+        }
+    }
+}
+
+// r = 2 (f - ref), loss += sum (f - ref)^2 (FP64).
+__global__ __launch_bounds__(256) void k_residual(const float* f, const float* ref, float* r, double* loss,
+                                                   int64_t count) {
+    __shared__ double part[4];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float dlt = f[i] - ref[i];
+        r[i] = 2.0f * dlt;
+        acc += (double)dlt * (double)dlt;
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(loss, part[0] + part[1] + part[2] + part[3]);
+}
+
+__global__ void k_fill(float* p, int64_t count, float v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_d(double* p, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0.0;
+}
+
+// AdamW on the FP32 master weights; writes their BF16 copy.
+__global__ void k_adamw(AdamArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.count) return;
+    const float g = a.grad[i];
+    float m1 = a.m1[i] = a.beta1 * a.m1[i] + (1.0f - a.beta1) * g;
+    float m2 = a.m2[i] = a.beta2 * a.m2[i] + (1.0f - a.beta2) * g * g;
+    const float mh = m1 / (1.0f - powf(a.beta1, (float)a.step));
+    const float vh = m2 / (1.0f - powf(a.beta2, (float)a.step));
+    float w = a.master[i];
+    w -= a.lr * (mh / (sqrtf(vh) + a.eps) + a.weight_decay * w);
+    a.master[i] = w;
+    a.w_bf16[i] = (uint16_t)f2bf(w);
+}
+
+hipError_t launch_learned_fwd(const LearnedArgs& a, int store, hipStream_t st) {
+    switch (store) {
+        case 0: hipLaunchKernelGGL(k_learned_fwd<0>, dim3(a.ntasks), dim3(256), 0, st, a); break;
+        case 1: hipLaunchKernelGGL(k_learned_fwd<1>, dim3(a.ntasks), dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL(k_learned_fwd<2>, dim3(a.ntasks), dim3(256), 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_learned_bwd(const LearnedArgs& a, int store, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill, dim3(4), dim3(256), 0, st, a.grad, (int64_t)kLearnedParams, 0.0f);
+    switch (store) {
+        case 0: hipLaunchKernelGGL(k_learned_bwd<0>, dim3(a.ntasks), dim3(256), 0, st, a); break;
+        case 1: hipLaunchKernelGGL(k_learned_bwd<1>, dim3(a.ntasks), dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL(k_learned_bwd<2>, dim3(a.ntasks), dim3(256), 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bp_adjoint(const AdjArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, st, a.dws, a.ws_elems, 0.0f);
+    const int64_t nvox = (int64_t)a.n * a.n * a.nz;
+    hipLaunchKernelGGL(k_bp_adjoint, dim3((unsigned)((nvox + 255) / 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const float* f, const float* ref, float* r, double* loss, int64_t count,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_d, dim3(1), dim3(64), 0, st, loss, (int64_t)1);
+    hipLaunchKernelGGL(k_residual, dim3(1024), dim3(256), 0, st, f, ref, r, loss, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_adamw(const AdamArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_adamw, dim3((a.count + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace fdkod
