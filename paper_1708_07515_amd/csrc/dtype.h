@@ -52,4 +52,20 @@ template <> struct Store<2> {
 
 inline int store_bytes(int s) { return s == 0 ? 4 : 2; }
 
+// A pointer that is the same in every lane, held in scalar registers.
+template <class T>
+__device__ __forceinline__ void* uniform_ptr(const T* p) {
+    const uint64_t v = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (void*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Buffer resource over n elements of ES bytes at a lane-uniform address; raw
+// loads through it return zero outside [0, n * ES).
+template <class T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const T* p, int n) {
+    return __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(p), (short)0, n * (int)sizeof(T), 0x00020000);
+}
+
 }  // namespace fdkod

@@ -13,7 +13,8 @@ namespace {
 fdkod_status learned_check(const fdkod_plan_s* pl) {
     if (pl->s == 0) return fail(FDKOD_E_UNSUPPORTED, "the learned decimation needs s > 0");
     if (pl->wmax > kLearnedMaxWidth)
-        return fail(FDKOD_E_UNSUPPORTED, "a square is wider than 512 local columns");
+        return fail(FDKOD_E_UNSUPPORTED, "a square is wider than 252 local columns");
+    if (pl->p > kLearnedMaxP) return fail(FDKOD_E_UNSUPPORTED, "more than 2048 projections");
     return FDKOD_OK;
 }
 
@@ -48,7 +49,7 @@ fdkod_status fdkod_learned_decompose(fdkod_plan_t pl, const void* filt, void* ws
     if (st != FDKOD_OK) return st;
     if ((st = fdkod_decompose(pl, filt, ws, stream)) != FDKOD_OK) return st;
     const LearnedArgs a = learned_args(pl, filt, ws, nullptr, weights, nullptr);
-    HIP_TRY(launch_learned_fwd(a, pl->store, (hipStream_t)stream), "learned decimation kernel launch");
+    HIP_TRY(launch_learned_fwd(a, pl->wmax, pl->store, (hipStream_t)stream), "learned decimation kernel launch");
     return FDKOD_OK;
 }
 

@@ -139,7 +139,8 @@ hipError_t launch_reset_counter(unsigned* counter, hipStream_t st);
 // Learned decimation (conv net over angle x column added to the triangle
 // decimation): 817 BF16 parameters W1 [16][5][5], b1 [16], W2 [16][5][5], b2.
 constexpr int kLearnedParams = 817;
-constexpr int kLearnedMaxWidth = 512;   // widest square (local columns) it takes
+constexpr int kLearnedMaxWidth = 252;   // widest square (local columns) it takes
+constexpr int kLearnedMaxP = 2048;      // most projections it takes
 
 struct LearnedArgs {
     const void* filt;        // [P][N][N] store type
@@ -179,7 +180,7 @@ struct AdamArgs {
     float lr, beta1, beta2, eps, weight_decay;
 };
 
-hipError_t launch_learned_fwd(const LearnedArgs& a, int store, hipStream_t st);
+hipError_t launch_learned_fwd(const LearnedArgs& a, int max_width, int store, hipStream_t st);
 hipError_t launch_learned_bwd(const LearnedArgs& a, int store, hipStream_t st);
 hipError_t launch_bp_adjoint(const AdjArgs& a, hipStream_t st);
 hipError_t launch_residual(const float* f, const float* ref, float* r, double* loss, int64_t count,

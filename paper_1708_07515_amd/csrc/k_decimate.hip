@@ -19,15 +19,6 @@
 
 namespace fdkod {
 
-// A pointer that is the same in every lane, held in scalar registers.
-template <class T>
-__device__ __forceinline__ void* uniform_ptr(const T* p) {
-    const uint64_t v = (uint64_t)(uintptr_t)p;
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return (void*)(uintptr_t)(((uint64_t)hi << 32) | lo);
-}
-
 // One task: square q, detector row v, column group g of 64*CH columns, run by
 // one wavefront (lane = 0..63).
 template <int CH, int STORE>

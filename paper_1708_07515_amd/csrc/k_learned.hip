@@ -1,7 +1,7 @@
 // Learned angular decimation and its training kernels (gfx950).
 //
 // The paper leaves the low-pass filter of the angular decimation open (Sec. 2.1:
-// quality depends on "the low-pass filter implementation").  The learned filter
+// quality depends on the low-pass filter's implementation).  The learned filter
 // adds a correction R to the plain triangle decimation T of every square q and
 // detector row v:
 //
@@ -23,6 +23,13 @@
 // The weight gradient of conv1 is an MFMA reduction over positions:
 //   dW1^T[32 taps][16 ch] += X[taps][16 pos] x dH[16 pos][16 ch].
 // Weights are BF16 (817 values: W1 [16][5][5], b1 [16], W2 [16][5][5], b2).
+//
+// One workgroup per (square, row) walks the decimated angles m.  The S values
+// of the nine original angles c(m) + (t - 4) d, t = 0..8, are kept in LDS as
+// BF16 (the precision conv1 multiplies them in).  The forward kernel loads the
+// next angle's S values and the next output row into registers before it runs
+// the current angle's matrix products, so the global-memory latency of one
+// angle overlaps the arithmetic of the previous one.
 #include "internal.h"
 #include "dtype.h"
 #include "geom.h"
@@ -32,84 +39,116 @@ namespace fdkod {
 typedef short s4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-constexpr int kLearnedWMax = kLearnedMaxWidth;
-constexpr int kSP = kLearnedWMax + 4;  // LDS pitch of S and Q rows (two zero columns each side)
+constexpr int kSP = 16 * ((kLearnedMaxWidth + 15) / 16) + 4;  // LDS pitch of S and Q rows
 constexpr int kOffW1 = 0, kOffB1 = 400, kOffW2 = 416, kOffB2 = 816;
+constexpr int kThreads = 256;
+static_assert(kLearnedMaxWidth + 4 <= kThreads, "one thread per staged column");
+
+typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
-__device__ __forceinline__ short f2bf(float v) {
-    uint32_t b = __float_as_uint(v);
-    b += 0x7FFFu + ((b >> 16) & 1u);   // round to nearest even (inputs are finite)
-    return (short)(b >> 16);
+// FP32 -> BF16, round to nearest even (hardware conversion)
+__device__ __forceinline__ uint16_t f2bf(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
+
+__device__ __forceinline__ s4v f2bf4(f4v v) { return __builtin_bit_cast(s4v, __builtin_convertvector(v, bf4v)); }
+
+// c(m) = floor(m P / P' + 1/2) = floor((2 m P + P') / (2 P')), walked in m
+// with an integer quotient and remainder (c(m) < P for m < P').
+struct CentreWalk {
+    int c, rem, dq, dr, den;
+    __device__ CentreWalk(int p, int pd) {
+        den = 2 * pd;
+        dq = (2 * p) / den;
+        dr = (2 * p) % den;
+        c = pd / den;      // m = 0: floor(P' / 2P') = 0
+        rem = pd % den;
+    }
+    __device__ void next() {
+        c += dq;
+        rem += dr;
+        if (rem >= den) {
+            rem -= den;
+            ++c;
+        }
+    }
+};
+
+// Shared set-up of both kernels: the crop origin a_c(beta_p) + u0 of every
+// original angle, the angle offset (t - 4) d mod P of every tile row, and the
+// BF16 S tile (row t, column j at index j + 2; zero outside [0, W)).
+struct LearnedSmem {
+    float o_tab[kLearnedMaxP];
+    int off_tab[9];
+    uint16_t s_tile[9 * kSP];
+};
+
+__device__ __forceinline__ void learned_setup(const LearnedArgs& a, int q, int u0, LearnedSmem& sm) {
+    for (int p = threadIdx.x; p < a.p; p += blockDim.x) sm.o_tab[p] = a.ac_p[(size_t)q * a.p + p] + (float)u0;
+    if (threadIdx.x < 9) {
+        int off = ((int)threadIdx.x - 4) * a.d % a.p;
+        sm.off_tab[threadIdx.x] = off < 0 ? off + a.p : off;
+    }
+    for (int e = threadIdx.x; e < 9 * kSP; e += blockDim.x) sm.s_tile[e] = 0;
 }
 
-__device__ __forceinline__ int centre_angle(int m, int p, int pd) {
-    return (int)(((2ll * m * p + pd) / (2ll * pd)) % p);
-}
-
-// S tile for decimated angle m: rows t = 0..8 hold the original angles
-// c(m) + (t - 4) d; column jj in [-2, 16 ntile + 2) sits at index jj + 2 (every
-// column the 16-column tiles read), zero outside [0, W).  S(p, j) = linear
-// interpolation of the filtered row at the square's local column j (the crop
-// and shift of FDK-OD).
+// The nine rows of S for centre angle c at the thread's column jj: detector
+// samples x0, x1 and the (row-uniform) interpolation fraction.  offr[t]: the
+// row offsets (t - 4) d mod P.  Rows are read through buffer resources that
+// span exactly one detector row, so samples outside the detector, and every
+// sample of a column outside [0, W) (given a negative offset), read zero.
 template <int STORE>
-__device__ __forceinline__ void build_s_tile(const LearnedArgs& a, int q, int v, int m, int width,
-                                             int ntile, int u0, float* s_tile) {
+__device__ __forceinline__ void s_fetch_rows(const LearnedArgs& a, const LearnedSmem& sm, int v, int c, int jj,
+                                             bool valid, const int offr[9], float x0[9], float x1[9],
+                                             float ph[9]) {
     using S = Store<STORE>;
     using T = typename S::T;
-    const int c = centre_angle(m, a.p, a.pd);
-    const int n = a.n;
-    const T* filt = (const T*)a.filt;
-    const int cols = 16 * ntile + 4;
-    for (int e = threadIdx.x; e < 9 * cols; e += blockDim.x) {
-        const int t = e / cols;
-        const int jj = e - t * cols - 2;
-        float val = 0.0f;
-        if (jj >= 0 && jj < width) {
-            int p = (c + (t - 4) * a.d) % a.p;
-            if (p < 0) p += a.p;
-            const float o = a.ac_p[(size_t)q * a.p + p] + (float)u0;
-            const float of = floorf(o);
-            const float phi = o - of;
-            const int i0 = (int)of + jj;
-            const T* row = filt + ((size_t)p * n + v) * n;
-            const float x0 = ((unsigned)i0 < (unsigned)n) ? S::load(row, i0) : 0.0f;
-            const float x1 = ((unsigned)(i0 + 1) < (unsigned)n) ? S::load(row, i0 + 1) : 0.0f;
-            val = fmaf(phi, x1 - x0, x0);
-        }
-        s_tile[t * kSP + jj + 2] = val;
+    constexpr int ES = (int)sizeof(T);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        int p = c + offr[t];
+        if (p >= a.p) p -= a.p;
+        const float o = sm.o_tab[p];
+        const float of = floorf(o);
+        ph[t] = o - of;
+        const __amdgpu_buffer_rsrc_t rs = row_rsrc((const T*)a.filt + ((size_t)p * a.n + v) * a.n, a.n);
+        const int off0 = valid ? ((int)of + jj) * ES : -4 * ES;
+        int off1 = off0 + ES;
+        asm volatile("" : "+v"(off1));   // two separately range-checked loads, never one wider load
+        x0[t] = S::raw(rs, off0);
+        x1[t] = S::raw(rs, off1);
     }
 }
 
-// conv1 for one dilated angle a2 of decimated angle m and one 16-column tile:
-// returns H^T in the MFMA output layout (lane l: channels 4(l/16)+i, column
-// col0 + l%16), without the bias.
-__device__ __forceinline__ f4v conv1_tile(const float* s_tile, int a2, int col0, const s4v w1op[2]) {
-    const int lane = threadIdx.x & 63;
-    const int lr = lane & 15, lg = lane >> 4;
+__device__ __forceinline__ void s_stage_rows(LearnedSmem& sm, int col, const float x0[9], const float x1[9],
+                                             const float ph[9]) {
+#pragma unroll
+    for (int t = 0; t < 9; ++t) sm.s_tile[t * kSP + col] = f2bf(fmaf(ph[t], x1[t] - x0[t], x0[t]));
+}
+
+// conv1 for one dilated angle a2 and one 16-column tile: H^T in the MFMA
+// output layout (lane l: channels 4(l/16)+i, column col0 + l%16), no bias.
+// toff[8]: per-lane LDS offsets of the lane's eight taps (0 for the padding
+// taps 25..31, whose weights are zero).
+__device__ __forceinline__ f4v conv1_tile(const uint16_t* s_tile, int a2, int col0, const int toff[8],
+                                          const s4v w1op[2]) {
+    const int lr = threadIdx.x & 15;
+    const uint16_t* base = s_tile + a2 * kSP + col0 + lr;
     f4v h = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
         s4v x;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int tap = 16 * ks + 4 * lg + i;
-            float sv = 0.0f;
-            if (tap < 25) {
-                const int a1 = tap / 5, b1 = tap - 5 * (tap / 5);
-                sv = s_tile[(a2 + a1) * kSP + col0 + lr + b1];   // column col0+lr+b1-2, index +2
-            }
-            x[i] = f2bf(sv);
-        }
+        for (int i = 0; i < 4; ++i) x[i] = (short)base[toff[4 * ks + i]];
         h = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1op[ks], x, h, 0, 0, 0);
     }
     return h;
 }
 
-// Weight operands held in registers for the whole kernel.
+// Weight operands held in registers for the whole kernel, and the lane's
+// tap offsets into the S tile.
 __device__ __forceinline__ void load_weight_operands(const uint16_t* w, s4v w1op[2], s4v w2op[5],
-                                                     float b1v[4]) {
+                                                     float b1v[4], int toff[8]) {
     const int lane = threadIdx.x & 63;
     const int lr = lane & 15, lg = lane >> 4;
 #pragma unroll
@@ -118,6 +157,7 @@ __device__ __forceinline__ void load_weight_operands(const uint16_t* w, s4v w1op
         for (int i = 0; i < 4; ++i) {
             const int tap = 16 * ks + 4 * lg + i;               // A[row = channel lr][k = tap]
             w1op[ks][i] = tap < 25 ? (short)w[kOffW1 + lr * 25 + tap] : (short)0;
+            toff[4 * ks + i] = tap < 25 ? (tap / 5) * kSP + tap % 5 : 0;
         }
 #pragma unroll
     for (int a2 = 0; a2 < 5; ++a2)
@@ -130,12 +170,14 @@ __device__ __forceinline__ void load_weight_operands(const uint16_t* w, s4v w1op
     for (int i = 0; i < 4; ++i) b1v[i] = bf2f(w[kOffB1 + 4 * lg + i]);
 }
 
-// Forward (inference): adds R to the plain decimation already in the workspace.
+// Forward (inference): Y(m) += R(m) for every decimated angle of one
+// (square, row).  Thread t stages column t - 2 of the tile and owns output
+// column t.
 template <int STORE>
-__global__ __launch_bounds__(256) void k_learned_fwd(LearnedArgs a) {
+__global__ __launch_bounds__(kThreads) void k_learned_fwd(LearnedArgs a) {
     using S = Store<STORE>;
     using T = typename S::T;
-    __shared__ float s_tile[9 * kSP];
+    __shared__ LearnedSmem sm;
     __shared__ float q_tile[5 * kSP];
     const int task = blockIdx.x;
     if (task >= a.ntasks) return;
@@ -146,26 +188,50 @@ __global__ __launch_bounds__(256) void k_learned_fwd(LearnedArgs a) {
     const int lr = lane & 15, lg = lane >> 4;
     s4v w1op[2], w2op[5];
     float b1v[4];
-    load_weight_operands(a.w, w1op, w2op, b1v);
+    int toff[8];
+    load_weight_operands(a.w, w1op, w2op, b1v, toff);
     const float b2 = bf2f(a.w[kOffB2]);
-    for (int e = threadIdx.x; e < 5 * kSP; e += blockDim.x) q_tile[e] = 0.0f;
     const int ntile = (width + 15) >> 4;
+    learned_setup(a, q, u0, sm);
+    for (int e = threadIdx.x; e < 5 * kSP; e += kThreads) q_tile[e] = 0.0f;
+    const int col = threadIdx.x;               // staged column index (local column col - 2)
+    const int jj = col - 2;
+    const bool stager = col < width + 4;
+    const bool valid = jj >= 0 && jj < width;
     T* ws = (T*)a.ws;
-    const int64_t yoff = a.squares[q].y_off;
+    const size_t yrow = (size_t)a.squares[q].y_off + (size_t)v * width;   // + m n W + j
+    const size_t yplane = (size_t)a.n * width;
+    const int j = threadIdx.x;                                           // output column
+    CentreWalk cw(a.p, a.pd);
+    __syncthreads();
+    int offr[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) offr[t] = __builtin_amdgcn_readfirstlane(sm.off_tab[t]);
+
+    float x0[9], x1[9], ph[9];
+    s_fetch_rows<STORE>(a, sm, v, cw.c, jj, valid, offr, x0, x1, ph);
+    float y_cur = j < width ? S::load(ws, yrow + j) : 0.0f;
+    if (stager) s_stage_rows(sm, col, x0, x1, ph);
+    __syncthreads();
     for (int m = 0; m < a.pd; ++m) {
-        build_s_tile<STORE>(a, q, v, m, width, ntile, u0, s_tile);
-        __syncthreads();
-        for (int tile = wave; tile < ntile; tile += 4) {
+        const bool more = m + 1 < a.pd;
+        float y_next = 0.0f;
+        if (more) {
+            cw.next();
+            s_fetch_rows<STORE>(a, sm, v, cw.c, jj, valid, offr, x0, x1, ph);
+            if (j < width) y_next = S::load(ws, yrow + (size_t)(m + 1) * yplane + j);
+        }
+        for (int tile = wave; tile < ntile; tile += kThreads / 64) {
             const int col0 = tile * 16;
             const bool cin = col0 + lr < width;
             f4v qacc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int a2 = 0; a2 < 5; ++a2) {
-                const f4v h = conv1_tile(s_tile, a2, col0, w1op);
-                s4v act;
+                const f4v h = conv1_tile(sm.s_tile, a2, col0, toff, w1op);
+                f4v act;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) act[i] = f2bf(cin ? fmaxf(h[i] + b1v[i], 0.0f) : 0.0f);
-                qacc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w2op[a2], act, qacc, 0, 0, 0);
+                for (int i = 0; i < 4; ++i) act[i] = cin ? fmaxf(h[i] + b1v[i], 0.0f) : 0.0f;
+                qacc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w2op[a2], f2bf4(act), qacc, 0, 0, 0);
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -174,13 +240,14 @@ __global__ __launch_bounds__(256) void k_learned_fwd(LearnedArgs a) {
             }
         }
         __syncthreads();
-        const size_t base = (size_t)yoff + ((size_t)m * a.n + v) * width;
-        for (int j = threadIdx.x; j < width; j += blockDim.x) {
+        if (j < width) {
             float r = b2;
 #pragma unroll
             for (int bb = 0; bb < 5; ++bb) r += q_tile[bb * kSP + j + bb];
-            S::put(ws, base + j, S::load(ws, base + j) + r);
+            S::put(ws, yrow + (size_t)m * yplane + j, y_cur + r);
         }
+        if (more && stager) s_stage_rows(sm, col, x0, x1, ph);
+        y_cur = y_next;
         __syncthreads();
     }
 }
@@ -195,13 +262,13 @@ __device__ __forceinline__ float sum16(float x) {
 // Backward: gradients of sum_{m,v,j} R[m][v][j] dY[m][v][j] with respect to
 // the weights (dY = dL/dY in FP32, workspace layout), accumulated into grad.
 template <int STORE>
-__global__ __launch_bounds__(256) void k_learned_bwd(LearnedArgs a) {
-    __shared__ float s_tile[9 * kSP];
+__global__ __launch_bounds__(kThreads) void k_learned_bwd(LearnedArgs a) {
+    __shared__ LearnedSmem sm;
     __shared__ float dr[kSP];
     __shared__ float w2f[16 * 25];
     __shared__ float gw2[16 * 25];
     __shared__ float gb1[16];
-    __shared__ float tr[4][16 * 17];
+    __shared__ float tr[kThreads / 64][16 * 17];
     __shared__ float gb2;
     const int task = blockIdx.x;
     if (task >= a.ntasks) return;
@@ -212,7 +279,9 @@ __global__ __launch_bounds__(256) void k_learned_bwd(LearnedArgs a) {
     const int lr = lane & 15, lg = lane >> 4;
     s4v w1op[2], w2op[5];
     float b1v[4];
-    load_weight_operands(a.w, w1op, w2op, b1v);
+    int toff[8];
+    load_weight_operands(a.w, w1op, w2op, b1v, toff);
+    learned_setup(a, q, u0, sm);
     for (int e = threadIdx.x; e < 400; e += blockDim.x) {
         w2f[e] = bf2f(a.w[kOffW2 + e]);
         gw2[e] = 0.0f;
@@ -220,14 +289,33 @@ __global__ __launch_bounds__(256) void k_learned_bwd(LearnedArgs a) {
     if (threadIdx.x < 16) gb1[threadIdx.x] = 0.0f;
     if (threadIdx.x == 0) gb2 = 0.0f;
     for (int e = threadIdx.x; e < kSP; e += blockDim.x) dr[e] = 0.0f;
+    // A-operand offsets of the dW1 product: lane holds tap 16 tt + lr
+    int xoff[2];
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+        const int tap = 16 * tt + lr;
+        xoff[tt] = tap < 25 ? (tap / 5) * kSP + tap % 5 : 0;   // taps >= 25 give discarded rows
+    }
     f4v gw1[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
     float db2 = 0.0f;
     const int ntile = (width + 15) >> 4;
     const int64_t yoff = a.squares[q].y_off;
     float* trw = tr[wave];
+    const int col_s = threadIdx.x, jj = col_s - 2;
+    const bool stager = col_s < width + 4;
+    const bool valid = jj >= 0 && jj < width;
+    CentreWalk cw(a.p, a.pd);
     __syncthreads();
+    int offr[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) offr[t] = __builtin_amdgcn_readfirstlane(sm.off_tab[t]);
     for (int m = 0; m < a.pd; ++m) {
-        build_s_tile<STORE>(a, q, v, m, width, ntile, u0, s_tile);
+        {
+            float x0[9], x1[9], ph[9];
+            s_fetch_rows<STORE>(a, sm, v, cw.c, jj, valid, offr, x0, x1, ph);
+            if (stager) s_stage_rows(sm, col_s, x0, x1, ph);
+            cw.next();
+        }
         const size_t base = (size_t)yoff + ((size_t)m * a.n + v) * width;
         for (int j = threadIdx.x; j < width; j += blockDim.x) {
             const float g = a.dws[base + j];
@@ -235,20 +323,20 @@ __global__ __launch_bounds__(256) void k_learned_bwd(LearnedArgs a) {
             db2 += g;
         }
         __syncthreads();
-        for (int tile = wave; tile < ntile; tile += 4) {
+        for (int tile = wave; tile < ntile; tile += kThreads / 64) {
             const int col0 = tile * 16;
             const int col = col0 + lr;
             const bool cin = col < width;
 #pragma unroll 1
             for (int a2 = 0; a2 < 5; ++a2) {
-                const f4v h = conv1_tile(s_tile, a2, col0, w1op);
+                const f4v h = conv1_tile(sm.s_tile, a2, col0, toff, w1op);
                 float dh[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int ch = 4 * lg + i;
                     const float hv = h[i] + b1v[i];
                     // the BF16 activation conv2 multiplied in the forward pass
-                    const float av = cin ? bf2f((uint16_t)f2bf(fmaxf(hv, 0.0f))) : 0.0f;
+                    const float av = cin ? bf2f(f2bf(fmaxf(hv, 0.0f))) : 0.0f;
                     // A(col) feeds R(col - b + 2): dA = sum_b W2[ch][a2][b] dR(col - b + 2)
                     float da = 0.0f;
 #pragma unroll
@@ -268,21 +356,14 @@ __global__ __launch_bounds__(256) void k_learned_bwd(LearnedArgs a) {
                 // B operand: lane holds dH[pos = 4 lg + i][ch = lr]
                 s4v dhop;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) dhop[i] = f2bf(trw[lr * 17 + 4 * lg + i]);
+                for (int i = 0; i < 4; ++i) dhop[i] = (short)f2bf(trw[lr * 17 + 4 * lg + i]);
+                const uint16_t* xb = sm.s_tile + a2 * kSP + col0 + 4 * lg;
 #pragma unroll
                 for (int tt = 0; tt < 2; ++tt) {
                     // A operand: lane holds X[tap = 16 tt + lr][pos = 4 lg + i]
                     s4v xop;
-                    const int tap = 16 * tt + lr;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        float sv = 0.0f;
-                        if (tap < 25) {
-                            const int a1 = tap / 5, b1 = tap - 5 * (tap / 5);
-                            sv = s_tile[(a2 + a1) * kSP + col0 + 4 * lg + i + b1];
-                        }
-                        xop[i] = f2bf(sv);
-                    }
+                    for (int i = 0; i < 4; ++i) xop[i] = (short)xb[xoff[tt] + i];
                     gw1[tt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xop, dhop, gw1[tt], 0, 0, 0);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -405,11 +486,12 @@ __global__ void k_adamw(AdamArgs a) {
     a.w_bf16[i] = (uint16_t)f2bf(w);
 }
 
-hipError_t launch_learned_fwd(const LearnedArgs& a, int store, hipStream_t st) {
+hipError_t launch_learned_fwd(const LearnedArgs& a, int max_width, int store, hipStream_t st) {
+    if (max_width > kLearnedMaxWidth || a.p > kLearnedMaxP) return hipErrorInvalidValue;
     switch (store) {
-        case 0: hipLaunchKernelGGL(k_learned_fwd<0>, dim3(a.ntasks), dim3(256), 0, st, a); break;
-        case 1: hipLaunchKernelGGL(k_learned_fwd<1>, dim3(a.ntasks), dim3(256), 0, st, a); break;
-        default: hipLaunchKernelGGL(k_learned_fwd<2>, dim3(a.ntasks), dim3(256), 0, st, a); break;
+        case 0: hipLaunchKernelGGL(k_learned_fwd<0>, dim3(a.ntasks), dim3(kThreads), 0, st, a); break;
+        case 1: hipLaunchKernelGGL(k_learned_fwd<1>, dim3(a.ntasks), dim3(kThreads), 0, st, a); break;
+        default: hipLaunchKernelGGL(k_learned_fwd<2>, dim3(a.ntasks), dim3(kThreads), 0, st, a); break;
     }
     return hipGetLastError();
 }
@@ -417,9 +499,9 @@ hipError_t launch_learned_fwd(const LearnedArgs& a, int store, hipStream_t st) {
 hipError_t launch_learned_bwd(const LearnedArgs& a, int store, hipStream_t st) {
     hipLaunchKernelGGL(k_fill, dim3(4), dim3(256), 0, st, a.grad, (int64_t)kLearnedParams, 0.0f);
     switch (store) {
-        case 0: hipLaunchKernelGGL(k_learned_bwd<0>, dim3(a.ntasks), dim3(256), 0, st, a); break;
-        case 1: hipLaunchKernelGGL(k_learned_bwd<1>, dim3(a.ntasks), dim3(256), 0, st, a); break;
-        default: hipLaunchKernelGGL(k_learned_bwd<2>, dim3(a.ntasks), dim3(256), 0, st, a); break;
+        case 0: hipLaunchKernelGGL(k_learned_bwd<0>, dim3(a.ntasks), dim3(kThreads), 0, st, a); break;
+        case 1: hipLaunchKernelGGL(k_learned_bwd<1>, dim3(a.ntasks), dim3(kThreads), 0, st, a); break;
+        default: hipLaunchKernelGGL(k_learned_bwd<2>, dim3(a.ntasks), dim3(kThreads), 0, st, a); break;
     }
     return hipGetLastError();
 }
