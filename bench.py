@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--no-direct", action="store_true", help="skip timing direct FDK")
     ap.add_argument("--no-large", action="store_true", help="skip the N=2000 workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-filter step")
     ap.add_argument("--cpu-slices", type=int, default=12)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy (for HBM counter calibration)")
@@ -104,7 +105,8 @@ def run_workload(torch, pkg, wl, s, k, store, steps, warmup, direct=True, proj=N
         f"squares={plan.squares}, workspace {plan.workspace_bytes / 1e9:.2f} GB")
     per, step_ms, wall = timed_steps(torch, stages, steps, warmup)
     log(f"[bench] FDK-OD per stage (ms): " + ", ".join(f"{a}={b:.3f}" for a, b in per.items()))
-    out = dict(plan=plan, proj=proj, vol=vol, per=per, step_ms=step_ms, wall=wall, direct=None)
+    out = dict(plan=plan, proj=proj, vol=vol, filt=filt, ws=ws, per=per, step_ms=step_ms, wall=wall,
+               direct=None)
     if direct:
         dplan = pkg.Plan(n, p, r, s=0, nz=nz, store=store)
         dvol = dplan.empty_volume()
@@ -145,6 +147,31 @@ def summarise(wl, s, k, store, res):
         "speedup_vs_direct_paper_scope": None if d is None else
             round(d["stage_ms"]["reconstruct"] / paper_ms, 3),
     }
+
+
+def run_learned(torch, pkg, wl, res, steps):
+    """The FDK-OD step with the learned decimation filter on the main workload
+    (seeded random weights: the cost does not depend on their values), timed
+    like the triangle step; None where the learned kernels do not apply."""
+    plan = res["plan"]
+    if plan.s == 0 or plan.info.max_width > 252 or plan.p > 2048:
+        return None
+    proj, filt, ws, vol = res["proj"], res["filt"], res["ws"], res["vol"]
+    net = pkg.LearnedDecimation("cuda:0", seed=0)
+    net.load(torch.randn(pkg.LEARNED_PARAMS, generator=torch.Generator().manual_seed(1)) * 0.05)
+    stages = [("bounds", lambda: plan.bounds()),
+              ("filter", lambda: plan.filter(proj, filt)),
+              ("decompose_learned", lambda: plan.learned_decompose(filt, ws, net.weights)),
+              ("reconstruct", lambda: plan.reconstruct(filt, ws, vol))]
+    per, step_ms, _ = timed_steps(torch, stages, steps, 1)
+    log("[bench] FDK-OD with the learned filter, per stage (ms): "
+        + ", ".join(f"{a}={b:.3f}" for a, b in per.items()))
+    updates_eq = wl.n * wl.n * wl.nzv * wl.p
+    return {"ms_per_step": round(step_ms, 4),
+            "gvups": round(updates_eq / (step_ms * 1e-3) / 1e9, 3),
+            "stage_ms": {a: round(b, 4) for a, b in per.items()},
+            "decompose_triangle_ms": round(res["per"]["decompose"], 4),
+            "weights": "817 BF16 parameters, seeded random"}
 
 
 def batch_volumes(bw):
@@ -259,8 +286,8 @@ def cpu_baseline(proj_cpu, wl, s, k, gpu_vol, count):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the path would "
-              "shard by z-slab across GPUs, which this build does not include", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has "
+              "no multi-GPU path (it would shard the volume by z-slab across GPUs)", file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -296,6 +323,7 @@ def main():
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a bounded sample")
         cpu, parity = cpu_baseline(res["proj"].cpu(), wl, s, k, res["vol"], args.cpu_slices)
+    learned = None if args.no_learned else run_learned(torch, pkg, wl, res, max(1, min(args.steps, 5)))
     del res
 
     large = None
@@ -342,6 +370,7 @@ def main():
         "cpu_baseline": cpu,
         "large_workload": large,
         "batch_workload": batch,
+        "learned_decimation": learned,
     }
     print(json.dumps(out), flush=True)
 

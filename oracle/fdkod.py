@@ -14,7 +14,7 @@ Steps, in the paper's order:
    to detector positions is folded into the sample coordinate (Sec. 2.1 and
    Sec. 2.2, "only one interpolation").
 
-Readings where the paper is silent (each is listed in the design doc):
+Readings where the paper is silent:
 
 * squares: near-equal contiguous blocks, larger first, when 2^s does not
   divide N; vertices are the four corner voxel centres and (x_c, y_c) their
