@@ -61,6 +61,19 @@ __device__ __forceinline__ void* uniform_ptr(const T* p) {
     return (void*)(uintptr_t)(((uint64_t)hi << 32) | lo);
 }
 
+// A structure read from global memory at a lane-uniform address, returned in
+// scalar registers (every 32-bit word through readfirstlane).
+template <class T>
+__device__ __forceinline__ T uniform_load(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "whole 32-bit words");
+    T out;
+    const int* src = (const int*)uniform_ptr(p);
+    int* dst = (int*)&out;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return out;
+}
+
 // Buffer resource over n elements of ES bytes at a lane-uniform address; raw
 // loads through it return zero outside [0, n * ES).
 template <class T>

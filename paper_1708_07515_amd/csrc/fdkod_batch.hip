@@ -21,13 +21,15 @@ struct fdkod_batch_s {
     int dec_chunks = 1;
     int bp_blocks = 0;
     int nitems = 0;
+    int xstart[kXcds + 1] = {};
     int64_t updates_eq = 0;
     // device tables
     BatchItem* d_items = nullptr;
     int items_cap = 0;
     BpVol* d_vols = nullptr;
     DecimVol* d_dvols = nullptr;
-    int* d_task_start = nullptr;
+    int2* d_block_vol = nullptr;
+    int block_vol_cap = 0;
     unsigned* d_counter = nullptr;
     std::vector<void*> allocs;
     // bound buffers
@@ -70,29 +72,47 @@ bool holds_all(const fdkod_batch_t b, const BpVariant& v) {
     return true;
 }
 
-// Work items of the persistent backprojection for the current z run, ordered
-// by decreasing work (tile voxels x decimated angles), ties by volume.
+// Work items of the persistent backprojection for the current z run: volumes
+// by decreasing work, each volume's items by square, slab and tile (tiles
+// that share footprints are adjacent), then cut into one range per XCD of
+// about equal work (tile voxels x slab depth x decimated angles).
 fdkod_status build_items(fdkod_batch_t b) {
-    std::vector<std::pair<int64_t, BatchItem>> w;
-    for (int vb = 0; vb < b->count; ++vb) {
+    std::vector<int> order(b->count);
+    std::iota(order.begin(), order.end(), 0);
+    auto vol_work = [&](int vb) {
+        const fdkod_plan_s* pl = b->plans[vb];
+        return (int64_t)pl->n * pl->n * pl->nz * pl->pd;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return vol_work(x) > vol_work(y); });
+    std::vector<BatchItem> items;
+    std::vector<int64_t> work;
+    for (int vb : order) {
         const fdkod_plan_s* pl = b->plans[vb];
         const int nzt = bp_zslabs(pl->nz, b->bpv.zrun);
         for (int q = 0; q < pl->nsq; ++q) {
             const SquareDesc& d = pl->sq[q];
-            for (int y = d.y0; y < d.y1; y += kTileXY)
-                for (int x = d.x0; x < d.x1; x += kTileXY) {
-                    const int64_t vox = (int64_t)std::min(kTileXY, d.x1 - x) * std::min(kTileXY, d.y1 - y);
-                    for (int zt = 0; zt < nzt; ++zt) {
-                        const int zc = std::min(b->bpv.zrun, pl->nz - zt * b->bpv.zrun);
-                        w.push_back({vox * zc * pl->pd, BatchItem{vb, q, x, y, zt, 0, 0, 0}});
+            for (int zt = 0; zt < nzt; ++zt) {
+                const int zc = std::min(b->bpv.zrun, pl->nz - zt * b->bpv.zrun);
+                for (int y = d.y0; y < d.y1; y += kTileXY)
+                    for (int x = d.x0; x < d.x1; x += kTileXY) {
+                        const int64_t vox = (int64_t)std::min(kTileXY, d.x1 - x) * std::min(kTileXY, d.y1 - y);
+                        items.push_back(BatchItem{vb, q, x, y, zt, 0, 0, 0});
+                        work.push_back(vox * zc * pl->pd);
                     }
-                }
+            }
         }
+        if ((int64_t)items.size() > (int64_t)1 << 30) return fail(FDKOD_E_UNSUPPORTED, "too many work items");
     }
-    std::stable_sort(w.begin(), w.end(), [](const auto& a, const auto& c) { return a.first > c.first; });
-    if ((int64_t)w.size() > (int64_t)1 << 30) return fail(FDKOD_E_UNSUPPORTED, "too many work items");
-    std::vector<BatchItem> items(w.size());
-    for (size_t i = 0; i < w.size(); ++i) items[i] = w[i].second;
+    const int64_t total = std::accumulate(work.begin(), work.end(), (int64_t)0);
+    b->xstart[0] = 0;
+    int64_t acc = 0;
+    size_t i = 0;
+    for (int x = 1; x < kXcds; ++x) {
+        const int64_t target = total * x / kXcds;
+        while (i < items.size() && acc + work[i] <= target) acc += work[i++];
+        b->xstart[x] = (int)i;
+    }
+    b->xstart[kXcds] = (int)items.size();
     if ((int)items.size() > b->items_cap) {
         fdkod_status st = dev_alloc(b->allocs, (void**)&b->d_items, sizeof(BatchItem) * items.size());
         if (st != FDKOD_OK) return st;
@@ -105,6 +125,7 @@ fdkod_status build_items(fdkod_batch_t b) {
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, b->device), "hipGetDeviceProperties");
     b->bp_blocks = std::max(1, occ) * prop.multiProcessorCount;
+    b->bp_blocks = (b->bp_blocks + kXcds - 1) / kXcds * kXcds;
     return FDKOD_OK;
 }
 
@@ -112,38 +133,54 @@ fdkod_status build_items(fdkod_batch_t b) {
 fdkod_status upload_tables(fdkod_batch_t b) {
     std::vector<BpVol> vols(b->count);
     std::vector<DecimVol> dvols;
-    std::vector<int> start{0};
+    std::vector<int2> block_vol;
+    int start = 0;
     for (int vb = 0; vb < b->count; ++vb) {
         const fdkod_plan_s* pl = b->plans[vb];
         vols[vb] = bp_vol(pl, b->filt[vb], b->ws[vb], b->vol[vb]);
         if (pl->s > 0) {
-            dvols.push_back(decim_args(pl, b->filt[vb], b->ws[vb], b->dec_chunks));
-            start.push_back(start.back() + dvols.back().ntasks);
+            // the batch's chunk count is an upper bound: narrow volumes use fewer
+            int c = 1;
+            while (c < b->dec_chunks && 64 * c < pl->wmax) c <<= 1;
+            dvols.push_back(decim_args(pl, b->filt[vb], b->ws[vb], c));
+            const int nblk = (dvols.back().ntasks + 3) / 4;     // padded to whole workgroups
+            for (int g = 0; g < nblk; ++g) block_vol.push_back(make_int2((int)dvols.size() - 1, start));
+            start += 4 * nblk;
         }
     }
     b->ndec = (int)dvols.size();
-    b->dec_ntasks = start.back();
+    b->dec_ntasks = start;
     HIP_TRY(hipMemcpy(b->d_vols, vols.data(), sizeof(BpVol) * vols.size(), hipMemcpyHostToDevice),
             "hipMemcpy volumes");
     if (!dvols.empty()) {
         HIP_TRY(hipMemcpy(b->d_dvols, dvols.data(), sizeof(DecimVol) * dvols.size(), hipMemcpyHostToDevice),
                 "hipMemcpy decimation volumes");
-        HIP_TRY(hipMemcpy(b->d_task_start, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice),
-                "hipMemcpy task offsets");
+        if ((int)block_vol.size() > b->block_vol_cap) {
+            fdkod_status st = dev_alloc(b->allocs, (void**)&b->d_block_vol, sizeof(int2) * block_vol.size());
+            if (st != FDKOD_OK) return st;
+            b->block_vol_cap = (int)block_vol.size();
+        }
+        HIP_TRY(hipMemcpy(b->d_block_vol, block_vol.data(), sizeof(int2) * block_vol.size(), hipMemcpyHostToDevice),
+                "hipMemcpy workgroup table");
     }
     return FDKOD_OK;
 }
 
 fdkod_status run_decimate(fdkod_batch_t b, hipStream_t st) {
     if (b->ndec == 0) return FDKOD_OK;
-    DecimBatchArgs a{b->d_dvols, b->d_task_start, b->ndec, b->dec_ntasks};
+    DecimBatchArgs a{b->d_dvols, b->d_block_vol, b->ndec, b->dec_ntasks};
     HIP_TRY(launch_decimate_batch(a, b->dec_chunks, b->store, st), "batched decimation launch");
     return FDKOD_OK;
 }
 
 fdkod_status run_backproject(fdkod_batch_t b, hipStream_t st) {
     HIP_TRY(launch_reset_counter(b->d_counter, st), "counter reset launch");
-    BpBatchArgs a{b->d_vols, b->d_items, b->nitems, b->d_counter};
+    BpBatchArgs a;
+    a.vols = b->d_vols;
+    a.items = b->d_items;
+    a.nitems = b->nitems;
+    for (int x = 0; x <= kXcds; ++x) a.xstart[x] = b->xstart[x];
+    a.counter = b->d_counter;
     HIP_TRY(launch_backproject_batch(a, b->bpv, b->store, b->bp_blocks, st), "persistent backprojection launch");
     return FDKOD_OK;
 }
@@ -234,9 +271,8 @@ fdkod_status fdkod_batch_create(const fdkod_params* prms, int32_t count, int dev
     fdkod_status st;
     if ((st = dev_alloc(b->allocs, (void**)&b->d_vols, sizeof(BpVol) * count)) != FDKOD_OK) return bail(st);
     if ((st = dev_alloc(b->allocs, (void**)&b->d_dvols, sizeof(DecimVol) * count)) != FDKOD_OK) return bail(st);
-    if ((st = dev_alloc(b->allocs, (void**)&b->d_task_start, sizeof(int) * (count + 1))) != FDKOD_OK)
+    if ((st = dev_alloc(b->allocs, (void**)&b->d_counter, sizeof(unsigned) * kXcds * kCounterStride)) != FDKOD_OK)
         return bail(st);
-    if ((st = dev_alloc(b->allocs, (void**)&b->d_counter, 256)) != FDKOD_OK) return bail(st);
     if ((st = build_items(b)) != FDKOD_OK) return bail(st);
     (void)hipSetDevice(prev);
     *out = b;

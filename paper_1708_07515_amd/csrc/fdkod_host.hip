@@ -235,6 +235,7 @@ DecimVol decim_args(const fdkod_plan_s* pl, const void* filt, void* ws, int chun
     a.nsq = pl->nsq;
     a.tasks_per_sq = dec_tasks_per_sq(pl->wmax, chunks);
     a.ntasks = pl->nsq * pl->n * a.tasks_per_sq;
+    a.chunks = chunks;
     return a;
 }
 

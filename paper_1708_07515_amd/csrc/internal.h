@@ -73,14 +73,17 @@ struct DecimVol {
     int n, p, pd, nsq;
     int tasks_per_sq;       // column groups per square
     int ntasks;             // nsq * n * tasks_per_sq
+    int chunks;             // 64-column chunks per wave (1, 2, 4 or 8)
 };
 
-// Many volumes in one launch: volume b owns tasks [task_start[b], task_start[b+1]).
+// Many volumes in one launch: volume b owns tasks [start_b, start_b + ntasks_b)
+// with start_b a multiple of 4, so a workgroup (4 waves) never spans two
+// volumes; block_vol[g] = (volume, start) of workgroup g's volume.
 struct DecimBatchArgs {
     const DecimVol* vols;
-    const int* task_start;  // [nvols + 1]
+    const int2* block_vol;  // [ntasks / 4]
     int nvols;
-    int ntasks;
+    int ntasks;             // sum of the padded task ranges
 };
 
 // Per-volume parameters of the backprojection.
@@ -111,11 +114,18 @@ struct BatchItem {
     int vol, sq, x0, y0, zt, pad0, pad1, pad2;
 };
 
+// Work items are split into one contiguous range per XCD (items
+// [xstart[x], xstart[x+1]) with about equal work); each range has its own
+// ticket counter, counter[x * kCounterStride], zeroed before each launch.
+constexpr int kXcds = 8;
+constexpr int kCounterStride = 32;   // 128 bytes between counters
+
 struct BpBatchArgs {
     const BpVol* vols;
-    const BatchItem* items;  // largest first
+    const BatchItem* items;  // per XCD range: larger volumes first, then square, slab, tile
     int nitems;
-    unsigned* counter;       // ticket counter, zeroed before each launch
+    int xstart[kXcds + 1];
+    unsigned* counter;       // kXcds ticket counters, kCounterStride apart
 };
 
 // A backprojection kernel variant: slices per thread, LDS footprint

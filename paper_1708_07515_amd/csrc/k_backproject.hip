@@ -201,28 +201,39 @@ __global__ __launch_bounds__(256) void k_backproject(BpArgs a) {
     bp_block<ZR, TW, TH, G, STORE>(a.v, zt, tl, sm);
 }
 
-// Persistent backprojection over the work items of many volumes: each
-// workgroup takes the next item from a ticket counter (items are ordered
-// largest first) until the tickets run past the end; every workgroup reaches
-// that exit.  The counter must be zero at launch (launch_reset_counter).
+// Persistent backprojection over the work items of many volumes.  Workgroup
+// b runs on XCD b mod 8 (round-robin dispatch) and first takes tickets from
+// that XCD's range of items, so the tiles that share footprints (same volume,
+// square and slab) meet in one L2; when its range is exhausted it takes
+// tickets from the other XCDs' ranges in turn.  Every workgroup leaves after
+// all eight ranges are exhausted.  The counters must be zero at launch
+// (launch_reset_counter).
 template <int ZR, int TW, int TH, int G, int STORE>
 __global__ __launch_bounds__(256) void k_backproject_batch(BpBatchArgs a) {
     __shared__ BpSmem<TW, TH, G> sm;
     __shared__ int ticket;
-    for (;;) {
-        if (threadIdx.x == 0) ticket = (int)atomicAdd(a.counter, 1u);
-        __syncthreads();
-        const int it = ticket;
-        __syncthreads();          // all threads read the ticket before it is replaced
-        if (it >= a.nitems) break;
-        const BatchItem bi = a.items[it];
-        const BpVol v = a.vols[bi.vol];
-        bp_block<ZR, TW, TH, G, STORE>(v, bi.zt, BpTile{bi.sq, bi.x0, bi.y0, 0}, sm);
+    const int home = blockIdx.x & (kXcds - 1);
+    for (int k = 0; k < kXcds; ++k) {
+        const int x = (home + k) & (kXcds - 1);
+        const int beg = a.xstart[x];
+        const int count = a.xstart[x + 1] - beg;
+        for (;;) {
+            if (threadIdx.x == 0) ticket = (int)atomicAdd(a.counter + x * kCounterStride, 1u);
+            __syncthreads();
+            const int it = __builtin_amdgcn_readfirstlane(ticket);
+            __syncthreads();      // all threads read the ticket before it is replaced
+            if (it >= count) break;
+            // item and volume parameters are workgroup-uniform: keep them in
+            // scalar registers, as the single-volume kernel's arguments are
+            const BatchItem bi = uniform_load(a.items + beg + it);
+            const BpVol v = uniform_load(a.vols + bi.vol);
+            bp_block<ZR, TW, TH, G, STORE>(v, bi.zt, BpTile{bi.sq, bi.x0, bi.y0, 0}, sm);
+        }
     }
 }
 
 __global__ void k_reset_counter(unsigned* c) {
-    if (threadIdx.x == 0) *c = 0u;
+    if (threadIdx.x < kXcds) c[threadIdx.x * kCounterStride] = 0u;
 }
 
 hipError_t launch_reset_counter(unsigned* counter, hipStream_t st) {

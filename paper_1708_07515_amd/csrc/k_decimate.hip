@@ -127,8 +127,10 @@ __global__ __launch_bounds__(256) void k_decimate(DecimVol a) {
     decimate_task<CH, STORE>(a, task, threadIdx.x & 63);
 }
 
-// Many volumes in one launch (tasks concatenated volume after volume).
-template <int CH, int STORE>
+// Many volumes in one launch (tasks concatenated volume after volume).  Each
+// volume uses its own chunk count (at most CHMAX), so the waves of a small
+// volume do not carry idle columns.
+template <int CHMAX, int STORE>
 __global__ __launch_bounds__(256) void k_decimate_batch(DecimBatchArgs a) {
     const int nblk = gridDim.x;
     const int chunk = nblk / 8;
@@ -137,16 +139,15 @@ __global__ __launch_bounds__(256) void k_decimate_batch(DecimBatchArgs a) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int task = lblk * 4 + wave;
     if (task >= a.ntasks) return;
-    // the volume holding this task: last vb with task_start[vb] <= task
-    int lo = 0, hi = a.nvols - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (a.task_start[mid] <= task) lo = mid;
-        else hi = mid - 1;
-    }
-    const int vb = lo;
-    const DecimVol dv = a.vols[vb];
-    decimate_task<CH, STORE>(dv, task - a.task_start[vb], threadIdx.x & 63);
+    const int2 bv = uniform_load(a.block_vol + lblk);   // (volume, first task of the volume)
+    const DecimVol dv = uniform_load(a.vols + bv.x);    // wave-uniform: scalar registers
+    const int t = task - bv.y;
+    if (t >= dv.ntasks) return;                         // padding of the volume's range
+    const int lane = threadIdx.x & 63;
+    if (CHMAX >= 8 && dv.chunks >= 8) decimate_task<(CHMAX >= 8 ? 8 : 1), STORE>(dv, t, lane);
+    else if (CHMAX >= 4 && dv.chunks >= 4) decimate_task<(CHMAX >= 4 ? 4 : 1), STORE>(dv, t, lane);
+    else if (CHMAX >= 2 && dv.chunks >= 2) decimate_task<(CHMAX >= 2 ? 2 : 1), STORE>(dv, t, lane);
+    else decimate_task<1, STORE>(dv, t, lane);
 }
 
 template <int CH>
