@@ -12,6 +12,7 @@ template <int S> struct Store;
 
 template <> struct Store<0> {
     using T = float;
+    static __device__ __forceinline__ float cvt(T x) { return x; }
     static __device__ __forceinline__ float load(const T* p, size_t i) { return p[i]; }
     static __device__ __forceinline__ void put(T* p, size_t i, float v) { p[i] = v; }
     // load through a raw buffer resource at a byte offset (zero when out of range)
@@ -22,6 +23,7 @@ template <> struct Store<0> {
 
 template <> struct Store<1> {
     using T = _Float16;
+    static __device__ __forceinline__ float cvt(T x) { return (float)x; }
     static __device__ __forceinline__ float load(const T* p, size_t i) { return (float)p[i]; }
     static __device__ __forceinline__ void put(T* p, size_t i, float v) { p[i] = (_Float16)v; }
     static __device__ __forceinline__ float raw(__amdgpu_buffer_rsrc_t r, int off) {
@@ -32,6 +34,7 @@ template <> struct Store<1> {
 
 template <> struct Store<2> {
     using T = uint16_t;  // bfloat16 bit pattern
+    static __device__ __forceinline__ float cvt(T x) { return __uint_as_float(((uint32_t)x) << 16); }
     static __device__ __forceinline__ float load(const T* p, size_t i) {
         return __uint_as_float(((uint32_t)p[i]) << 16);
     }

@@ -17,7 +17,7 @@ using namespace fdkod;
 struct fdkod_batch_s {
     int device = 0, count = 0, store = 0;
     std::vector<fdkod_plan_t> plans;
-    BpVariant bpv{32, 32, 48, 2};
+    BpVariant bpv{32, 32, 48, 1};
     int dec_chunks = 1;
     int bp_blocks = 0;
     int nitems = 0;
@@ -256,8 +256,7 @@ fdkod_status fdkod_batch_create(const fdkod_params* prms, int32_t count, int dev
             th = std::max(th, h);
         }
         if (!all) continue;
-        b->bpv = BpVariant{zr, tw, th, 2};
-        if (!backproject_variant_exists(b->bpv)) b->bpv.g = 1;
+        b->bpv = BpVariant{zr, tw, th, 1};
         ok = holds_all(b, b->bpv);
         if (ok) break;
     }

@@ -500,9 +500,8 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
     for (int zr : {32, 16}) {
         int tw = 0, th = 0;
         if (bp_tiles_for(pl->n, pl->nz, pl->r, zr, &tw, &th)) {
-            pl->bpv = BpVariant{zr, tw, th, 2};
-            if (!backproject_variant_exists(pl->bpv)) pl->bpv.g = 1;
-            pl->bp_ok = true;
+            pl->bpv = BpVariant{zr, tw, th, 1};   // one angle per stage: smallest LDS, highest occupancy
+            pl->bp_ok = backproject_variant_exists(pl->bpv);
             break;
         }
     }

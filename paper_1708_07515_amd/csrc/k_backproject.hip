@@ -20,25 +20,36 @@
 // (b = z / U), so an update costs a row index, one LDS read and five FMAs.
 #include "internal.h"
 #include "dtype.h"
-#include "geom.h"
 
 namespace fdkod {
 
 typedef float f2v __attribute__((ext_vector_type(2)));
+
 typedef __attribute__((address_space(3))) const char* lds_cptr;
 typedef __attribute__((address_space(3))) const f2v* lds_f2ptr;
 
-// LDS of one workgroup: G staged footprints and their per-angle constants.
+// LDS of one workgroup: G staged footprints and, in a ring of three angle
+// batches, their per-angle constants.
 template <int TW, int TH, int G>
 struct BpSmem {
     float2 tile[G][TH * (TW + 1)];
-    int4 meta[G];      // c0, r0 (first column / row of the footprint), rows, -
-    float4 mgeo[G];    // cos, sin, Dc, Lc
-    float2 mgeo2[G];   // R / Dc, c_u - u0 - c0
+    int4 meta[3][G];      // c0, r0 (first column / row of the footprint), rows, -
+    float4 mgeo[3][G];    // cos, sin, Dc, Lc
+    float2 mgeo2[3][G];   // R / Dc, c_u - u0 - c0
 };
+
+// Lane l receives lane l + 1's value (a DPP wave shift; lane 63 receives 0).
+__device__ __forceinline__ float from_next_lane(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130 /* wave_shl:1 */, 0xf, 0xf, false));
+}
 
 // Backprojection of one 16 x 16 x ZR voxel block (tile tl, slab zt) of one
 // volume.  Every thread of the workgroup calls it (it contains barriers).
+//
+// Angles go in batches of G.  While batch b is accumulated from LDS, the
+// detector samples of batch b + 1 are already being loaded into registers
+// (their footprints were bounded one batch earlier), so global-memory latency
+// overlaps the arithmetic; two barriers per batch separate the LDS phases.
 template <int ZR, int TW, int TH, int G, int STORE>
 __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& tl,
                                          BpSmem<TW, TH, G>& sm) {
@@ -47,9 +58,6 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
     constexpr int TWP = TW + 1;   // LDS row pitch in pairs (odd: spreads banks)
     static_assert(TWP <= 255, "ds_read2_b64 offset range");
     auto& tile = sm.tile;
-    auto& meta = sm.meta;
-    auto& mgeo = sm.mgeo;
-    auto& mgeo2 = sm.mgeo2;
     const SquareDesc sq = v.squares[tl.sq];
     const int2 gd = v.grid[tl.sq];
     const int u0 = gd.x, width = gd.y;
@@ -82,31 +90,33 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
     // staging map: a lane keeps one footprint column, rows strided by 256 / TW
     constexpr int RSTEP = 256 / TW;
     static_assert(TH % RSTEP == 0, "uniform staging trip count");
+    constexpr int NR = TH / RSTEP;
     const int scol = threadIdx.x % TW;
     const int srow = threadIdx.x / TW;
 
-    float acc[ZR];
-#pragma unroll
-    for (int k = 0; k < ZR; ++k) acc[k] = 0.0f;
-
-    for (int m0 = 0; m0 < v.pd; m0 += G) {
-        const int gcount = min(G, v.pd - m0);
-        // footprint of the block at each angle of the batch
-        if (threadIdx.x < gcount) {
+    // footprint of the block at angles [m0, m0 + G) into ring slot `slot`:
+    // eq. (1) at the block's corners bounds the columns, eq. (9) at its corner
+    // depths and end slices the rows; one sample of margin on every side
+    // covers the rounding of the reciprocals
+    auto footprint = [&](int slot, int m0) {
+        if (threadIdx.x < G && m0 + (int)threadIdx.x < v.pd) {
             const int m = m0 + threadIdx.x;
             const float2 t = v.trig[m];
             const float dc = v.r + sq.xc * t.x + sq.yc * t.y;
             const float lc = sq.yc * t.x - sq.xc * t.y;
-            const float rdc = 1.0f / dc;
+            const float rdc = __builtin_amdgcn_rcpf(dc);
             float tlo = INFINITY, thi = -INFINITY, vlo = INFINITY, vhi = -INFINITY;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const float cx = (k & 1) ? bx1 : bx0;
                 const float cy = (k & 2) ? by1 : by0;
-                const float tau = rel_column(cx, cy, t.x, t.y, v.r, dc, lc, rdc) + kq;
+                const float dl = cy * t.x - cx * t.y;
+                const float dd = cx * t.x + cy * t.y;
+                const float rd = __builtin_amdgcn_rcpf(dc + dd);
+                const float tau = v.r * (dl * dc - lc * dd) * rdc * rd + kq;
                 tlo = fminf(tlo, tau);
                 thi = fmaxf(thi, tau);
-                const float iu = v.r / (dc + cx * t.x + cy * t.y);
+                const float iu = v.r * rd;
                 const float va = z0 * iu + v.cv, vb = zlast * iu + v.cv;
                 vlo = fminf(vlo, fminf(va, vb));
                 vhi = fmaxf(vhi, fmaxf(va, vb));
@@ -114,33 +124,84 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
             const int c0 = (int)floorf(tlo) - 1;
             const int r0 = (int)floorf(vlo) - 1;
             const int rows = min((int)floorf(vhi) + 3 - r0, TH);
-            meta[threadIdx.x] = make_int4(c0, r0, rows, 0);
-            mgeo[threadIdx.x] = make_float4(t.x, t.y, dc, lc);
-            mgeo2[threadIdx.x] = make_float2(v.r * rdc, kq - (float)c0);
+            sm.meta[slot][threadIdx.x] = make_int4(c0, r0, rows, 0);
+            sm.mgeo[slot][threadIdx.x] = make_float4(t.x, t.y, dc, lc);
+            sm.mgeo2[slot][threadIdx.x] = make_float2(v.r * rdc, kq - (float)c0);
         }
-        __syncthreads();
-        // stage the footprints as (Y[c], Y[c+1] - Y[c]); columns outside
-        // [0, width) and rows outside the detector are zero (zero extension)
-        for (int g = 0; g < gcount; ++g) {
-            const int4 mt = meta[g];
-            const T* pl = data + (size_t)(m0 + g) * plane;
+    };
+    // detector samples of the footprints of [m0, m0 + G) into registers, in
+    // the storage type (converted when staged, so no load is waited for
+    // early); columns outside [0, width) and rows outside the detector are
+    // zero.  Footprints of more than 16 samples per thread are loaded after
+    // the arithmetic instead (their registers would cost occupancy).
+    constexpr bool kPrefetch = G * NR <= 16;
+    T pre[G][NR];
+    auto fetch_one = [&](int slot, int m0, int g) {
+        {
+            const bool gok = m0 + g < v.pd;
+            const int4 mt = gok ? sm.meta[slot][g] : make_int4(0, 0, 0, 0);
+            const T* pl = data + (size_t)(gok ? m0 + g : 0) * plane;
             const int col = mt.x + scol;
             const bool cok = (unsigned)col < (unsigned)width;
-            for (int rr = srow; rr < TH; rr += RSTEP) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int rr = srow + r * RSTEP;
                 const int row = mt.y + rr;
-                float y0 = 0.0f;
-                if (rr < mt.z && cok && (unsigned)row < (unsigned)n)
-                    y0 = S::load(pl, (size_t)row * row_stride + col);
-                // the last column's pair is never read (column index <= TW - 2)
-                const float y1 = __shfl_down(y0, 1, TW);
-                if (rr < mt.z) tile[g][rr * TWP + scol] = make_float2(y0, y1 - y0);
+                pre[g][r] = (rr < mt.z && cok && (unsigned)row < (unsigned)n)
+                                ? pl[(size_t)row * row_stride + col] : (T)0;
             }
         }
-        __syncthreads();
+    };
+    // pairs (Y[c], Y[c+1] - Y[c]) into LDS; the last column's pair is never
+    // read (the column index is at most TW - 2), so the lane that receives
+    // the next footprint row's first sample writes an unused pair
+    auto stage_one = [&](int slot, int m0, int g) {
+        {
+            const int rows = m0 + g < v.pd ? sm.meta[slot][g].z : 0;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int rr = srow + r * RSTEP;
+                const float y0 = S::cvt(pre[g][r]);
+                const float y1 = from_next_lane(y0);
+                if (rr < rows) tile[g][rr * TWP + scol] = make_float2(y0, y1 - y0);
+            }
+        }
+    };
+
+    float acc[ZR];
+#pragma unroll
+    for (int k = 0; k < ZR; ++k) acc[k] = 0.0f;
+
+    auto fetch_stage = [&](int slot, int m0) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            fetch_one(slot, m0, g);
+            stage_one(slot, m0, g);
+        }
+    };
+
+    footprint(0, 0);
+    footprint(1, G);
+    __syncthreads();
+    fetch_stage(0, 0);
+    __syncthreads();
+    int cur = 0;
+#pragma unroll 1
+    for (int m0 = 0; m0 < v.pd; m0 += G) {
+        const int nxt = cur == 2 ? 0 : cur + 1;
+        const int nn = nxt == 2 ? 0 : nxt + 1;
+        const int gcount = min(G, v.pd - m0);
+        const bool more = m0 + G < v.pd;
+        if (kPrefetch && more) {             // in flight during the arithmetic below
+#pragma unroll
+            for (int g = 0; g < G; ++g) fetch_one(nxt, m0 + G, g);
+        }
+        footprint(nn, m0 + 2 * G);
+#pragma unroll 1
         for (int g = 0; g < gcount; ++g) {
-            const float4 mg = mgeo[g];
-            const float2 mg2 = mgeo2[g];
-            const int4 mt = meta[g];
+            const float4 mg = sm.mgeo[cur][g];
+            const float2 mg2 = sm.mgeo2[cur][g];
+            const int4 mt = sm.meta[cur][g];
             const float dl = dy * mg.x - dx * mg.y;
             const float dd = dx * mg.x + dy * mg.y;
             const float d = mg.z + dd;
@@ -165,17 +226,34 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
             asm volatile("" : "+v"(tga));   // keep it one register: address = mad24(row, pitch, tga)
 #pragma unroll
             for (int k = 0; k < ZR; ++k) {
-                const float v = fmaf((float)k, invu, v0);
-                const float fv = __builtin_amdgcn_fractf(v);
-                const uint32_t ri = (uint32_t)(int)v;
+                const float vv = fmaf((float)k, invu, v0);
+                const float fv = __builtin_amdgcn_fractf(vv);
+                const uint32_t ri = (uint32_t)(int)vv;
                 const lds_f2ptr p = (lds_f2ptr)(uintptr_t)(tga + __umul24(ri, (uint32_t)(TWP * sizeof(float2))));
                 const f2v A = p[0], B = p[TWP];
                 const float top = fmaf(fu, A.y, A.x);
                 const float bot = fmaf(fu, B.y, B.x);
                 acc[k] = fmaf(w, fmaf(fv, bot - top, top), acc[k]);
+                // four slices per group: their accumulators are complete before
+                // the next group's reads are issued (without this fence the
+                // compiler may issue all ZR reads first and trade occupancy
+                // for the registers that holds them)
+                if ((k & 3) == 3)
+                    asm volatile("" : "+v"(acc[k - 3]), "+v"(acc[k - 2]), "+v"(acc[k - 1]), "+v"(acc[k])
+                                 :: "memory");
             }
         }
         __syncthreads();
+        if (more) {
+            if (kPrefetch) {
+#pragma unroll
+                for (int g = 0; g < G; ++g) stage_one(nxt, m0 + G, g);
+            } else {
+                fetch_stage(nxt, m0 + G);
+            }
+        }
+        __syncthreads();
+        cur = nxt;
     }
     if (own) {
         const size_t slice = (size_t)n * n;

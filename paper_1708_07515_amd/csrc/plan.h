@@ -19,7 +19,7 @@ struct fdkod_plan_s {
     // decomposition kernel shape
     int dec_chunks = 1;
     // backprojection kernel shape
-    fdkod::BpVariant bpv{32, 32, 48, 2};
+    fdkod::BpVariant bpv{32, 32, 48, 1};
     bool bp_ok = false;     // some variant's LDS footprint holds a block's footprint
     int ntiles = 0;
     int64_t ws_elems = 0;
