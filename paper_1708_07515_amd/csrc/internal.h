@@ -199,6 +199,6 @@ hipError_t launch_adamw(const AdamArgs& a, hipStream_t st);
 
 // Limits the host checks before choosing a backprojection variant.
 constexpr int kTileXY = 16;      // voxels per tile side in x and y
-constexpr int kDecimUnroll = 4;  // schedule steps the decimation kernel loads at once
+constexpr int kDecimUnroll = 8;  // the decimation schedule is padded to a multiple of this
 
 }  // namespace fdkod

@@ -19,12 +19,27 @@
 
 namespace fdkod {
 
+// Read-only tables of the decimation (schedule, crop offsets), read word by
+// word through the constant address space so that their lane-uniform loads
+// are scalar.
+typedef __attribute__((address_space(4))) const int* cword_ptr;
+static_assert(sizeof(DecimStep) == 16 && sizeof(int2) == 8, "table layouts");
+
+// Steps whose samples one group loads; two groups are in flight (the next
+// group's loads are issued before the current group's arithmetic).
+template <int CH>
+struct DecimGroup {
+    static constexpr int U = CH >= 8 ? 1 : 8 / CH;
+};
+
 // One task: square q, detector row v, column group g of 64*CH columns, run by
 // one wavefront (lane = 0..63).
 template <int CH, int STORE>
 __device__ __forceinline__ void decimate_task(const DecimVol& a, int task, int lane) {
     using S = Store<STORE>;
     using T = typename S::T;
+    constexpr int U = DecimGroup<CH>::U;
+    static_assert(kDecimUnroll % U == 0, "the schedule is padded to whole groups");
     // task = (v * nsq + q) * tasks_per_sq + g
     const int g = task % a.tasks_per_sq;
     const int vq = task / a.tasks_per_sq;
@@ -35,12 +50,15 @@ __device__ __forceinline__ void decimate_task(const DecimVol& a, int task, int l
     const int u0 = gd.x, width = gd.y;
     const int jbase = g * 64 * CH + lane;
     if (g * 64 * CH >= width) return;
+    (void)u0;
 
-    const T* filt = (const T*)a.filt;
+    const T* frow = (const T*)uniform_ptr((const T*)a.filt + (size_t)v * n);   // row v of projection 0
     T* ws = (T*)a.ws;
-    const int2* crop = a.crop + (size_t)q * a.nsched;
+    const cword_ptr sched = (cword_ptr)a.sched;                       // 4 words per step
+    const cword_ptr crop = (cword_ptr)(a.crop + (size_t)q * a.nsched);  // 2 words per step
     const int64_t yoff = a.squares[q].y_off;
     const size_t plane = (size_t)n * width;   // elements per decimated angle
+    const size_t pstride = (size_t)n * n;     // elements per projection
     constexpr int ES = (int)sizeof(T);
     // per-lane byte offset of each chunk's column within the cropped run
     int lane_off[CH];
@@ -54,40 +72,39 @@ __device__ __forceinline__ void decimate_task(const DecimVol& a, int task, int l
         acc1[c] = 0.0f;
     }
     int m = 0;
-    // The schedule is padded to a multiple of U with zero-weight steps, so the
-    // loads of U steps are issued together before their arithmetic.  Each
-    // detector row is read through a buffer resource spanning exactly that
-    // row: the hardware range check returns zero outside [0, N), which is the
-    // zero extension of the crop (offsets below the row wrap to huge unsigned
-    // values and are out of range too).
-    constexpr int U = kDecimUnroll;
-    for (int t = 0; t < a.nsched; t += U) {
-        DecimStep st[U];
-        int2 cr[U];
-        __amdgpu_buffer_rsrc_t rs[U];
+    // Each detector row is read through a buffer resource spanning exactly
+    // that row: the hardware range check returns zero outside [0, N), which is
+    // the zero extension of the crop (offsets below the row wrap to huge
+    // unsigned values and are out of range too).  Two separately
+    // range-checked loads per sample: the empty asm hides that off1 = off0 +
+    // ES, so the loads are not merged into one wider load (whose range check
+    // would zero both elements at the detector's left edge).
+    auto issue = [&](int t, DecimStep (&st)[U], int2 (&cr)[U], float (&x0)[U][CH], float (&x1)[U][CH]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            st[u] = a.sched[t + u];
-            cr[u] = crop[t + u];
-            rs[u] = __builtin_amdgcn_make_buffer_rsrc(
-                uniform_ptr(filt + ((size_t)st[u].p * n + v) * n), (short)0, n * ES, 0x00020000);
+            const int e = t + u;
+            st[u].p = sched[4 * e];
+            st[u].emit = sched[4 * e + 1];
+            st[u].w0 = __int_as_float(sched[4 * e + 2]);
+            st[u].w1 = __int_as_float(sched[4 * e + 3]);
+            cr[u] = make_int2(crop[2 * e], crop[2 * e + 1]);
         }
-        float x0[U][CH], x1[U][CH];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < U; ++u) {
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(frow + (size_t)st[u].p * pstride), (short)0, n * ES, 0x00020000);
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
-                // two separately range-checked loads: a negative offset is out of
-                // range as a huge unsigned value, and no in-range access relies on
-                // a wrap.  The empty asm hides that off1 = off0 + ES, so the two
-                // loads are not merged into one wider load (whose range check
-                // would zero both elements at the detector's left edge).
                 const int off0 = cr[u].x * ES + lane_off[c];
                 int off1 = off0 + ES;
                 asm volatile("" : "+v"(off1));
-                x0[u][c] = S::raw(rs[u], off0);
-                x1[u][c] = S::raw(rs[u], off1);
+                x0[u][c] = S::raw(rs, off0);
+                x1[u][c] = S::raw(rs, off1);
             }
+        }
+    };
+    auto consume = [&](const DecimStep (&st)[U], const int2 (&cr)[U], const float (&x0)[U][CH],
+                       const float (&x1)[U][CH]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const float phi = __int_as_float(cr[u].y);
@@ -109,6 +126,18 @@ __device__ __forceinline__ void decimate_task(const DecimVol& a, int task, int l
                 ++m;
             }
         }
+    };
+    // two groups (ping, pong) per iteration; the schedule holds whole groups
+    DecimStep sa[U], sb[U];
+    int2 ca[U], cb[U];
+    float xa0[U][CH], xa1[U][CH], xb0[U][CH], xb1[U][CH];
+    issue(0, sa, ca, xa0, xa1);
+    for (int t = 0; t < a.nsched; t += 2 * U) {
+        const bool b_ok = t + U < a.nsched;
+        if (b_ok) issue(t + U, sb, cb, xb0, xb1);
+        consume(sa, ca, xa0, xa1);
+        if (t + 2 * U < a.nsched) issue(t + 2 * U, sa, ca, xa0, xa1);
+        if (b_ok) consume(sb, cb, xb0, xb1);
     }
 }
 
