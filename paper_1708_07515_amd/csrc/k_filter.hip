@@ -14,7 +14,8 @@
 // (summation by parts; the last term is the difference at u' = N, applied
 // directly so that lags stay within +-(N-1)).  The convolution is circular of
 // length M >= 2N - 1 on the zero-padded row, by an FP32 Stockham FFT held in
-// LDS.  Two real rows travel in one complex transform (row0 + i row1); g is
+// LDS (radix-16 stages with the 16-point transforms in registers, so a
+// 4096-point transform takes three passes through LDS).  Two real rows travel in one complex transform (row0 + i row1); g is
 // real, so its transform G is Hermitian and multiplying by it keeps the rows
 // apart.  The inverse transform is conj(FFT(conj(.))); 1/M is folded into G.
 #include "internal.h"
@@ -26,143 +27,195 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// In-place forward DFT of length M (natural order in and out) by Stockham
-// radix-4 stages (one radix-2 stage last when log2 M is odd).  TP threads
-// cooperate on one transform; every thread of the workgroup calls this the
-// same number of times because it contains barriers.
-template <int LOGM, int TP>
-__device__ __forceinline__ void fft_lds(float2* z, int t, const float2* __restrict__ tw) {
-    constexpr int M = 1 << LOGM;
-    constexpr int Q = M / 4;           // radix-4 butterflies per stage
-    constexpr int BPT = (Q + TP - 1) / TP;
-#pragma unroll 1
-    for (int ns = 1; ns * 4 <= M; ns *= 4) {
-        float2 v[BPT][4];
-        const int tstep = M / (4 * ns);
+// LDS position of transform element i: one pad slot after every 16 elements
+// and another after every 256, so that the strided writes of the radix-16
+// stages spread over the banks.
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 4) + (i >> 8); }
+template <int M>
+struct Padded {
+    static constexpr int size = M + M / 16 + M / 256 + 1;
+};
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// 4-point DFT in place: X1 = a - i b - c + i d, X3 = a + i b - c - i d
+__device__ __forceinline__ void dft4(float2& a, float2& b, float2& c, float2& d) {
+    const float2 s02 = cadd(a, c), d02 = csub(a, c);
+    const float2 s13 = cadd(b, d), d13 = csub(b, d);
+    a = cadd(s02, s13);
+    c = csub(s02, s13);
+    b = make_float2(d02.x + d13.y, d02.y - d13.x);   // d02 - i d13
+    d = make_float2(d02.x - d13.y, d02.y + d13.x);   // d02 + i d13
+}
+
+// 16-point DFT in place (natural order in and out) as 4 x 4:
+// X[k1 + 4 k2] = sum_n2 w16^(n2 k2 4) w16^(n2 k1) sum_n1 x[4 n1 + n2] w4^(n1 k1)
+__device__ __forceinline__ void dft16(float2 (&v)[16]) {
+    // cos and sin of pi/8 and pi/4
+    constexpr float C1 = 0.923879532511286756f, S1 = 0.382683432365089772f, R2 = 0.707106781186547524f;
 #pragma unroll
-        for (int b = 0; b < BPT; ++b) {
-            const int j = t + b * TP;
-            if (j < Q) {
-                const int k = j & (ns - 1);
+    for (int n2 = 0; n2 < 4; ++n2) dft4(v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]);
+    // v[n2 + 4 k1] now holds y[n2][k1]; multiply by w16^(n2 k1)
+    v[5] = cmul(v[5], make_float2(C1, -S1));     // w^1
+    v[9] = cmul(v[9], make_float2(R2, -R2));     // w^2
+    v[13] = cmul(v[13], make_float2(S1, -C1));   // w^3
+    v[6] = cmul(v[6], make_float2(R2, -R2));     // w^2
+    v[10] = make_float2(v[10].y, -v[10].x);      // w^4 = -i
+    v[14] = cmul(v[14], make_float2(-R2, -R2));  // w^6
+    v[7] = cmul(v[7], make_float2(S1, -C1));     // w^3
+    v[11] = cmul(v[11], make_float2(-R2, -R2));  // w^6
+    v[15] = cmul(v[15], make_float2(-C1, S1));   // w^9
+    // 4-point DFTs over n2 for each k1: inputs v[4 k1 + n2]
 #pragma unroll
-                for (int r = 0; r < 4; ++r) v[b][r] = z[j + r * Q];
-                v[b][1] = cmul(v[b][1], tw[(1 * k * tstep) & (M - 1)]);
-                v[b][2] = cmul(v[b][2], tw[(2 * k * tstep) & (M - 1)]);
-                v[b][3] = cmul(v[b][3], tw[(3 * k * tstep) & (M - 1)]);
-                // 4-point DFT: X1 = a - i b - c + i d, X3 = a + i b - c - i d
-                const float2 s02 = make_float2(v[b][0].x + v[b][2].x, v[b][0].y + v[b][2].y);
-                const float2 d02 = make_float2(v[b][0].x - v[b][2].x, v[b][0].y - v[b][2].y);
-                const float2 s13 = make_float2(v[b][1].x + v[b][3].x, v[b][1].y + v[b][3].y);
-                const float2 d13 = make_float2(v[b][1].x - v[b][3].x, v[b][1].y - v[b][3].y);
-                v[b][0] = make_float2(s02.x + s13.x, s02.y + s13.y);
-                v[b][2] = make_float2(s02.x - s13.x, s02.y - s13.y);
-                v[b][1] = make_float2(d02.x + d13.y, d02.y - d13.x);   // d02 - i d13
-                v[b][3] = make_float2(d02.x - d13.y, d02.y + d13.x);   // d02 + i d13
+    for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    // v[4 k1 + k2] holds X[k1 + 4 k2]: transpose the 4 x 4 index
+    float2 t[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) t[i] = v[i];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[4 * k1 + k2];
+}
+
+// One Stockham stage of radix R (16, 4 or 2) at stride NS, TP threads.  The
+// first stage (NS = 1) needs no twiddles.
+template <int R, int M, int TP, int NS>
+__device__ __forceinline__ void fft_stage(float2* z, int t, const float2* __restrict__ tw) {
+    constexpr int NB = M / R;                       // butterflies of this stage
+    constexpr int BPT = (NB + TP - 1) / TP;
+    constexpr int ns = NS;
+    float2 v[BPT][R];
+    constexpr int tstep = M / (R * ns);
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+        const int j = t + b * TP;
+        if (j < NB) {
+            const int k = j & (ns - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b][r] = z[pidx(j + r * NB)];
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[(r * k * tstep) & (M - 1)]);
+            }
+            if constexpr (R == 16) {
+                dft16(v[b]);
+            } else if constexpr (R == 4) {
+                dft4(v[b][0], v[b][1], v[b][2], v[b][3]);
+            } else {
+                const float2 x0 = v[b][0];
+                v[b][0] = cadd(x0, v[b][1]);
+                v[b][1] = csub(x0, v[b][1]);
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int b = 0; b < BPT; ++b) {
-            const int j = t + b * TP;
-            if (j < Q) {
-                const int k = j & (ns - 1);
-                const int dst = (j / ns) * ns * 4 + k;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) z[dst + r * ns] = v[b][r];
-            }
-        }
-        __syncthreads();
     }
-    if (LOGM & 1) {
-        // last stage, radix 2, ns = M / 2: X0 = a + w^j b, X1 = a - w^j b
-        constexpr int H = M / 2;
-        constexpr int B2 = (H + TP - 1) / TP;
-        float2 v0[B2], v1[B2];
+    __syncthreads();
 #pragma unroll
-        for (int b = 0; b < B2; ++b) {
-            const int j = t + b * TP;
-            if (j < H) {
-                v0[b] = z[j];
-                v1[b] = cmul(z[j + H], tw[j]);
-            }
-        }
-        __syncthreads();
+    for (int b = 0; b < BPT; ++b) {
+        const int j = t + b * TP;
+        if (j < NB) {
+            const int k = j & (ns - 1);
+            const int dst = (j / ns) * ns * R + k;
 #pragma unroll
-        for (int b = 0; b < B2; ++b) {
-            const int j = t + b * TP;
-            if (j < H) {
-                z[j] = make_float2(v0[b].x + v1[b].x, v0[b].y + v1[b].y);
-                z[j + H] = make_float2(v0[b].x - v1[b].x, v0[b].y - v1[b].y);
-            }
+            for (int r = 0; r < R; ++r) z[pidx(dst + r * ns)] = v[b][r];
         }
-        __syncthreads();
+    }
+    __syncthreads();
+}
+
+// The stages from stride NS on: radix 16 while at least four bits remain,
+// then 4, then 2.
+template <int M, int TP, int NS>
+__device__ __forceinline__ void fft_stages(float2* z, int t, const float2* __restrict__ tw) {
+    if constexpr (NS * 16 <= M) {
+        fft_stage<16, M, TP, NS>(z, t, tw);
+        fft_stages<M, TP, NS * 16>(z, t, tw);
+    } else if constexpr (NS * 4 <= M) {
+        fft_stage<4, M, TP, NS>(z, t, tw);
+        fft_stages<M, TP, NS * 4>(z, t, tw);
+    } else if constexpr (NS * 2 <= M) {
+        fft_stage<2, M, TP, NS>(z, t, tw);
     }
 }
 
+// In-place forward DFT of length M = 2^LOGM (natural order in and out, LDS
+// positions through pidx) by Stockham stages.  TP threads cooperate on one
+// transform; every thread of the workgroup calls this the same number of
+// times because it contains barriers.
+template <int LOGM, int TP>
+__device__ __forceinline__ void fft_lds(float2* z, int t, const float2* __restrict__ tw) {
+    fft_stages<1 << LOGM, TP, 1>(z, t, tw);
+}
+
+// Threads per transform: one radix-16 butterfly per thread and stage (at
+// most 256 threads, one workgroup).
+// WAVES: waves per SIMD the register allocation is held to (the LDS of one
+// 4096-point transform allows four workgroups per CU).
+template <int LOGM>
+struct FilterShape {
+    static constexpr int M = 1 << LOGM;
+    static constexpr int TP = M / 16 < 1 ? 1 : (M / 16 > 256 ? 256 : M / 16);
+    static constexpr int WAVES = LOGM >= 13 ? 2 : (LOGM == 11 ? 3 : 4);
+};
+
 template <int LOGM, int STORE>
-__global__ __launch_bounds__(256) void k_filter(FilterArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FilterShape<LOGM>::WAVES)))
+void k_filter(FilterArgs a) {
     using S = Store<STORE>;
     constexpr int M = 1 << LOGM;
-    constexpr int TP = (M / 4 < 256) ? M / 4 : 256;   // threads per row pair
-    constexpr int PAIRS = 256 / TP;                   // row pairs per workgroup
-    __shared__ float2 buf[PAIRS * M];
+    constexpr int TP = FilterShape<LOGM>::TP;          // threads per row pair
+    constexpr int PAIRS = 256 / TP;                    // row pairs per workgroup
+    constexpr int MP = Padded<M>::size;
+    __shared__ float2 buf[PAIRS * MP];
 
     const int grp = threadIdx.x / TP;
     const int t = threadIdx.x % TP;
     const int pair = blockIdx.x * PAIRS + grp;
     const int r0 = 2 * pair, r1 = 2 * pair + 1;
     const bool has0 = r0 < a.rows, has1 = r1 < a.rows;
-    float2* z = buf + grp * M;
+    float2* z = buf + grp * MP;
     const int n = a.n;
     const float rr = a.r * a.r;
 
-    // load and pre-weight (zero-padded), then take the first difference in LDS
+    // pre-weighted first difference d[u] = p~[u] - p~[u-1] (zero-padded);
+    // p~[u-1] is recomputed from the row rather than read back from LDS
     const float b0 = has0 ? (float)(r0 % n) - a.c : 0.0f;
     const float b1 = has1 ? (float)(r1 % n) - a.c : 0.0f;
     const float rb0 = rr + b0 * b0, rb1 = rr + b1 * b1;
     const float* p0 = a.proj + (size_t)r0 * n;
     const float* p1 = a.proj + (size_t)r1 * n;
+    auto weighted = [&](int u, float& x0, float& x1) {
+        const float au = (float)u - a.c;
+        x0 = has0 ? p0[u] * (a.r * rsqrtf(rb0 + au * au)) : 0.0f;
+        x1 = has1 ? p1[u] * (a.r * rsqrtf(rb1 + au * au)) : 0.0f;
+    };
     for (int u = t; u < M; u += TP) {
-        float x0 = 0.0f, x1 = 0.0f;
+        float d0 = 0.0f, d1 = 0.0f;      // the difference at u = N is applied after the FFT
         if (u < n) {
-            const float au = (float)u - a.c;
-            if (has0) x0 = p0[u] * (a.r * rsqrtf(rb0 + au * au));
-            if (has1) x1 = p1[u] * (a.r * rsqrtf(rb1 + au * au));
+            weighted(u, d0, d1);
+            if (u > 0) {
+                float e0, e1;
+                weighted(u - 1, e0, e1);
+                d0 -= e0;
+                d1 -= e1;
+            }
         }
-        z[u] = make_float2(x0, x1);
+        z[pidx(u)] = make_float2(d0, d1);
     }
-    __syncthreads();
-    constexpr int EPT = (M + TP - 1) / TP;
-    float2 dv[EPT];
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-        const int u = t + e * TP;
-        dv[e] = make_float2(0.0f, 0.0f);     // the difference at u = N is applied after the FFT
-        if (u < n) {
-            const float2 cur = z[u];
-            const float2 prev = u > 0 ? z[u - 1] : make_float2(0.0f, 0.0f);
-            dv[e] = make_float2(cur.x - prev.x, cur.y - prev.y);
-        }
-    }
-    const float2 last = z[n - 1];
-    const float last0 = last.x, last1 = last.y;
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-        const int u = t + e * TP;
-        if (u < M) z[u] = dv[e];
-    }
+    float last0, last1;
+    weighted(n - 1, last0, last1);
     __syncthreads();
     fft_lds<LOGM, TP>(z, t, a.twiddle);
     for (int k = t; k < M; k += TP) {
-        const float2 v = cmul(z[k], a.resp[k]);
-        z[k] = make_float2(v.x, -v.y);                // conj(Z G)
+        const float2 v = cmul(z[pidx(k)], a.resp[k]);
+        z[pidx(k)] = make_float2(v.x, -v.y);          // conj(Z G)
     }
     __syncthreads();
     fft_lds<LOGM, TP>(z, t, a.twiddle);
     typename S::T* out = (typename S::T*)a.out;
     for (int u = t; u < n; u += TP) {
-        const float2 v = z[u];                        // conj of the result
+        const float2 v = z[pidx(u)];                  // conj of the result
         const float gt = a.gtail[u];                  // g[u - N]
         if (has0) S::put(out, (size_t)r0 * n + u, v.x - last0 * gt);
         if (has1) S::put(out, (size_t)r1 * n + u, -v.y - last1 * gt);
@@ -171,8 +224,7 @@ __global__ __launch_bounds__(256) void k_filter(FilterArgs a) {
 
 template <int LOGM>
 static hipError_t launch_filter_m(const FilterArgs& a, int store, hipStream_t st) {
-    constexpr int M = 1 << LOGM;
-    constexpr int TP = (M / 4 < 256) ? M / 4 : 256;
+    constexpr int TP = FilterShape<LOGM>::TP;
     constexpr int PAIRS = 256 / TP;
     const int pairs = (a.rows + 1) / 2;
     const dim3 grid((pairs + PAIRS - 1) / PAIRS);
