@@ -27,7 +27,7 @@
  *                fdkod_plan_info().workspace_bytes bytes (unused when s = 0):
  *                square q (q = by 2^s + bx) holds Y_q as [P'][N][W_q]
  *                (m, v, j), j fastest, from element offset
- *                sum_{q' < q} roundup(P' N W_q', 64)
+ *                N P' sum_{q' < q} W_q' 
  *   volume       float32 [N_z][N][N]     (l, j, i), x fastest
  *
  * Ownership and streams
@@ -288,6 +288,64 @@ fdkod_status fdkod_sq_residual(const float* f, const float* ref, float* resid, d
 fdkod_status fdkod_adamw_step(float* master, float* m1, float* m2, const float* grad,
                               uint16_t* w_bf16, int32_t count, int32_t step, float lr, float beta1,
                               float beta2, float eps, float weight_decay, fdkod_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Low-memory reconstruction by slabs.  Sec. 2.2: eq. (9) gives the detector
+ * rows a slice uses, so only a band of rows of every projection has to be
+ * resident, and the decomposition and reconstruction of a part of the volume
+ * need only the matching part of the data.
+ *
+ * A slab is the output slices [z0, z0 + nzs).  Its band is the detector rows
+ * [v0, v0 + nrows) that eq. (9) maps the slab's voxels to at any angle (depth
+ * between R - (N-1)/sqrt(2) and R + (N-1)/sqrt(2)), the two rows of each
+ * bilinear sample and one row of margin on each side, widened to even row
+ * boundaries and clipped to the detector.  Band buffers hold only those rows:
+ *   projection band  float32 [P][nrows][N]
+ *   filtered band    store type [P][nrows][N]
+ *   workspace band   store type, square q's block [P'][nrows][W_q] from
+ *                    element offset nrows P' sum_{q' < q} W_q'
+ *   volume slab      float32 [nzs][N][N]
+ * The band calls compute for those rows and slices exactly what the
+ * whole-volume calls compute (bit for bit when v0 is even, as
+ * fdkod_band_rows returns it, and z0 is a multiple of the plan's z_run; the
+ * filter transforms detector rows 2k and 2k + 1 together).  Asynchronous on
+ * `stream`; they allocate nothing.
+ * ------------------------------------------------------------------------- */
+
+/* The band of slab [z0, z0 + nzs) (host arithmetic, FP64). */
+fdkod_status fdkod_band_rows(fdkod_plan_t plan, int32_t z0, int32_t nzs, int32_t* v0, int32_t* nrows);
+
+/* fdkod_filter on the rows [v0, v0 + nrows) held by proj_band. */
+fdkod_status fdkod_filter_band(fdkod_plan_t plan, const float* proj_band, int32_t v0, int32_t nrows,
+                               void* filt_band, fdkod_stream_t stream);
+
+/* fdkod_decompose of the rows [v0, v0 + nrows); no-op when s = 0. */
+fdkod_status fdkod_decompose_band(fdkod_plan_t plan, const void* filt_band, int32_t v0, int32_t nrows,
+                                  void* ws_band, fdkod_stream_t stream);
+
+/* fdkod_reconstruct of slices [z0, z0 + nzs) from a band (ws_band when s > 0,
+ * filt_band when s = 0).  FDKOD_E_ARG when the band misses a row the slab
+ * samples. */
+fdkod_status fdkod_reconstruct_slab(fdkod_plan_t plan, const void* filt_band, const void* ws_band,
+                                    int32_t v0, int32_t nrows, int32_t z0, int32_t nzs, float* vol_slab,
+                                    fdkod_stream_t stream);
+
+/* Device bytes of the work buffer fdkod_reconstruct_streamed needs for slabs
+ * of nzs slices (rounded up to a multiple of z_run): two projection bands,
+ * one filtered and one workspace band, two volume slabs. */
+fdkod_status fdkod_streamed_bytes(fdkod_plan_t plan, int32_t nzs, int64_t* bytes);
+
+/* The whole reconstruction from host memory, slab by slab: host_proj float32
+ * [P][N][N] and host_vol float32 [N_z][N][N] are host buffers (page-locked
+ * for overlap).  Each slab's band is copied in on copy_stream while the
+ * previous slab is filtered, decomposed and reconstructed on `stream`, and
+ * each finished slab is copied out on copy_stream.  copy_stream may be NULL
+ * (everything on `stream`).  work: device buffer of fdkod_streamed_bytes.
+ * Synchronous: returns when host_vol is complete.  Creates and destroys its
+ * own events; allocates no device memory. */
+fdkod_status fdkod_reconstruct_streamed(fdkod_plan_t plan, const float* host_proj, float* host_vol,
+                                        int32_t nzs, void* work, int64_t work_bytes, fdkod_stream_t stream,
+                                        fdkod_stream_t copy_stream);
 
 /* Static text for a status code. */
 const char* fdkod_status_str(fdkod_status st);

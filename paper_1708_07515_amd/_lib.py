@@ -87,6 +87,14 @@ EXPORTS = {
     "fdkod_sq_residual": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int64, _VP]),
     "fdkod_adamw_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32]
                          + [ctypes.c_float] * 5 + [_VP]),
+    "fdkod_band_rows": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]),
+    "fdkod_filter_band": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32, _VP, _VP]),
+    "fdkod_decompose_band": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32, _VP, _VP]),
+    "fdkod_reconstruct_slab": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_int32, _VP, _VP]),
+    "fdkod_streamed_bytes": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "fdkod_reconstruct_streamed": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, _VP, ctypes.c_int64, _VP, _VP]),
     "fdkod_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "fdkod_last_error": (ctypes.c_char_p, []),
     "fdkod_version": (ctypes.c_int32, []),
@@ -360,6 +368,70 @@ class Plan:
         _check(self._lib.fdkod_reconstruct_adjoint(
             self._h, ctypes.c_void_p(resid.data_ptr()), ctypes.c_void_p(dws.data_ptr()),
             _stream_ptr(stream)))
+
+    # low-memory slabs -----------------------------------------------------
+    def band_rows(self, z0, nzs):
+        """Detector rows (v0, nrows) that slices [z0, z0 + nzs) sample."""
+        v0, nr = ctypes.c_int32(), ctypes.c_int32()
+        _check(self._lib.fdkod_band_rows(self._h, int(z0), int(nzs), ctypes.byref(v0), ctypes.byref(nr)))
+        return v0.value, nr.value
+
+    def band_workspace_elems(self, nrows):
+        return (int(self.workspace_bytes) // _STORE_BYTES[self.store]) // self.n * int(nrows)
+
+    def empty_band(self, nrows):
+        """(projection band, filtered band, workspace band) for nrows rows."""
+        import torch
+        dev = f"cuda:{self.device}"
+        proj = torch.empty((self.p, nrows, self.n), dtype=torch.float32, device=dev)
+        filt = torch.empty((self.p, nrows, self.n), dtype=self.store_torch_dtype(), device=dev)
+        ws = torch.empty(max(self.band_workspace_elems(nrows), 1), dtype=self.store_torch_dtype(), device=dev)
+        return proj, filt, ws
+
+    def filter_band(self, proj_band, v0, filt_band, stream=None):
+        import torch
+        nr = proj_band.shape[1]
+        self._chk(proj_band, (self.p, nr, self.n), torch.float32, "proj_band")
+        self._chk(filt_band, (self.p, nr, self.n), self.store_torch_dtype(), "filt_band")
+        _check(self._lib.fdkod_filter_band(self._h, ctypes.c_void_p(proj_band.data_ptr()), int(v0), nr,
+                                           ctypes.c_void_p(filt_band.data_ptr()), _stream_ptr(stream)))
+
+    def decompose_band(self, filt_band, v0, ws_band, stream=None):
+        nr = filt_band.shape[1]
+        self._chk(filt_band, (self.p, nr, self.n), self.store_torch_dtype(), "filt_band")
+        if self.s > 0 and (ws_band is None or ws_band.numel() < self.band_workspace_elems(nr)):
+            raise ValueError("workspace band too small")
+        _check(self._lib.fdkod_decompose_band(
+            self._h, ctypes.c_void_p(filt_band.data_ptr()), int(v0), nr,
+            ctypes.c_void_p(ws_band.data_ptr() if ws_band is not None else 0), _stream_ptr(stream)))
+
+    def reconstruct_slab(self, filt_band, ws_band, v0, nrows, z0, vol_slab, stream=None):
+        import torch
+        nzs = vol_slab.shape[0]
+        self._chk(vol_slab, (nzs, self.n, self.n), torch.float32, "vol_slab")
+        _check(self._lib.fdkod_reconstruct_slab(
+            self._h, ctypes.c_void_p(filt_band.data_ptr() if filt_band is not None else 0),
+            ctypes.c_void_p(ws_band.data_ptr() if ws_band is not None else 0), int(v0), int(nrows), int(z0),
+            nzs, ctypes.c_void_p(vol_slab.data_ptr()), _stream_ptr(stream)))
+
+    def streamed_bytes(self, nzs):
+        b = ctypes.c_int64()
+        _check(self._lib.fdkod_streamed_bytes(self._h, int(nzs), ctypes.byref(b)))
+        return b.value
+
+    def reconstruct_streamed(self, host_proj, host_vol, nzs, work, stream=None, copy_stream=None):
+        """Whole reconstruction from host tensors, slab by slab (synchronous)."""
+        import torch
+        for t, shape, nm in ((host_proj, (self.p, self.n, self.n), "host_proj"),
+                             (host_vol, (self.nz, self.n, self.n), "host_vol")):
+            if t.is_cuda or tuple(t.shape) != shape or t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError(f"{nm} must be a contiguous float32 host tensor of shape {shape}")
+        if not work.is_cuda or not work.is_contiguous():
+            raise ValueError("work must be a contiguous device tensor")
+        _check(self._lib.fdkod_reconstruct_streamed(
+            self._h, ctypes.c_void_p(host_proj.data_ptr()), ctypes.c_void_p(host_vol.data_ptr()), int(nzs),
+            ctypes.c_void_p(work.data_ptr()), work.numel() * work.element_size(), _stream_ptr(stream),
+            _stream_ptr(copy_stream)))
 
     def get_bounds(self):
         """Bounds tables as numpy arrays (synchronises)."""

@@ -374,9 +374,9 @@ fdkod_status fdkod_batch_tune(fdkod_batch_t b, fdkod_stream_t stream, fdkod_tuni
     }
     float best = 1e30f;
     BpVariant bestv = b->bpv;
-    for (int zr : {32, 16})
+    for (int zr : {64, 32, 16})
         for (int tw : {32, 64})
-            for (int th : {48, 64})
+            for (int th : {48, 64, 96})
                 for (int g : {1, 2, 4}) {
                     const BpVariant v{zr, tw, th, g};
                     if (!holds_all(b, v)) continue;

@@ -215,12 +215,16 @@ bool bp_tiles_for(int n, int nz, double r, int zrun, int* tw, int* th) {
     const int need_c = (int)std::ceil(span_c + 1e-6) + 4;
     const int need_r = (int)std::ceil(span_r + 1e-6) + 4;
     *tw = need_c <= 32 ? 32 : (need_c <= 64 ? 64 : 0);
-    *th = need_r <= 48 ? 48 : (need_r <= 64 ? 64 : 0);
+    *th = need_r <= 48 ? 48 : (need_r <= 64 ? 64 : (need_r <= 96 ? 96 : 0));
     return *tw && *th;
 }
 
 
 DecimVol decim_args(const fdkod_plan_s* pl, const void* filt, void* ws, int chunks) {
+    return decim_args_band(pl, filt, ws, chunks, 0, pl->n);
+}
+
+DecimVol decim_args_band(const fdkod_plan_s* pl, const void* filt, void* ws, int chunks, int v0, int nv) {
     DecimVol a;
     a.filt = filt;
     a.ws = ws;
@@ -233,9 +237,27 @@ DecimVol decim_args(const fdkod_plan_s* pl, const void* filt, void* ws, int chun
     a.p = pl->p;
     a.pd = pl->pd;
     a.nsq = pl->nsq;
+    a.v0 = v0;
+    a.nv = nv;
     a.tasks_per_sq = dec_tasks_per_sq(pl->wmax, chunks);
-    a.ntasks = pl->nsq * pl->n * a.tasks_per_sq;
+    a.ntasks = pl->nsq * nv * a.tasks_per_sq;
     a.chunks = chunks;
+    return a;
+}
+
+FilterArgs filter_args(const fdkod_plan_s* pl, const float* proj, void* filt, int v0, int nv) {
+    FilterArgs a;
+    a.proj = proj;
+    a.out = filt;
+    a.resp = pl->d_resp;
+    a.gtail = pl->d_gtail;
+    a.twiddle = pl->d_tw;
+    a.n = pl->n;
+    a.rows = pl->p * nv;
+    a.v0 = v0;
+    a.nv = nv;
+    a.r = (float)pl->r;
+    a.c = (float)((pl->n - 1) / 2.0);
     return a;
 }
 
@@ -249,6 +271,11 @@ bool variant_holds(const fdkod_plan_s* pl, const BpVariant& v) {
 }
 
 BpVol bp_vol(const fdkod_plan_s* pl, const void* filt, const void* ws, float* vol) {
+    return bp_vol_band(pl, filt, ws, vol, 0, pl->n, 0, pl->nz);
+}
+
+BpVol bp_vol_band(const fdkod_plan_s* pl, const void* filt, const void* ws, float* vol, int v0, int nv,
+                  int zbase, int nzs) {
     const bool direct = pl->s == 0;
     BpVol v;
     v.data = direct ? filt : ws;
@@ -257,8 +284,11 @@ BpVol bp_vol(const fdkod_plan_s* pl, const void* filt, const void* ws, float* vo
     v.grid = direct ? pl->d_grid_direct : pl->d_grid;
     v.trig = pl->d_trig_m;
     v.n = pl->n;
-    v.nz = pl->nz;
+    v.nz = nzs;
     v.pd = pl->pd;
+    v.v0 = v0;
+    v.nv = nv;
+    v.zbase = zbase;
     v.row_stride_direct = direct ? pl->n : 0;
     v.r = (float)pl->r;
     v.cu = (float)((pl->n - 1) / 2.0);
@@ -425,7 +455,7 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
             d.x0 = bx.first; d.x1 = bx.second; d.y0 = by.first; d.y1 = by.second;
             d.xc = (float)(0.5 * ((bx.first - c) + (bx.second - 1 - c)));
             d.yc = (float)(0.5 * ((by.first - c) + (by.second - 1 - c)));
-            d.y_off = 0;
+            d.y_off_row = 0;
             pl->sq.push_back(d);
         }
 
@@ -479,11 +509,11 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
         const int w = pl->grid[q].y;
         if (w < 2 || w > 4 * pl->n + 8) return bail(fail(FDKOD_E_HIP, "bounds kernel produced an invalid width"));
         pl->wmax = std::max(pl->wmax, w);
-        pl->sq[q].y_off = off;
-        off += (int64_t)w * pl->pd * pl->n;
-        off = (off + 63) & ~(int64_t)63;     // 256-byte aligned planes for FP32
+        pl->sq[q].y_off_row = off;
+        off += (int64_t)w * pl->pd;
     }
-    pl->ws_elems = pl->s > 0 ? off : 0;
+    pl->ws_row_elems = pl->s > 0 ? off : 0;
+    pl->ws_elems = pl->ws_row_elems * pl->n;
     {
         hipError_t e = hipMemcpy(pl->d_sq, pl->sq.data(), sizeof(SquareDesc) * pl->nsq, hipMemcpyHostToDevice);
         if (e != hipSuccess) return bail(hip_fail(e, "hipMemcpy squares"));
@@ -497,11 +527,13 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
     while (ch < 8 && 64 * ch < pl->wmax) ch <<= 1;
     pl->dec_chunks = ch;
     pl->bp_ok = false;
-    for (int zr : {32, 16}) {
+    for (int zr : {32, 16, 64}) {
         int tw = 0, th = 0;
-        if (bp_tiles_for(pl->n, pl->nz, pl->r, zr, &tw, &th)) {
-            pl->bpv = BpVariant{zr, tw, th, 1};   // one angle per stage: smallest LDS, highest occupancy
-            pl->bp_ok = backproject_variant_exists(pl->bpv);
+        // one angle per stage: the smallest LDS footprint, the highest occupancy
+        if (bp_tiles_for(pl->n, pl->nz, pl->r, zr, &tw, &th) &&
+            backproject_variant_exists(BpVariant{zr, tw, th, 1})) {
+            pl->bpv = BpVariant{zr, tw, th, 1};
+            pl->bp_ok = true;
             break;
         }
     }
@@ -574,16 +606,7 @@ fdkod_status fdkod_bounds(fdkod_plan_t pl, fdkod_stream_t stream) {
 
 fdkod_status fdkod_filter(fdkod_plan_t pl, const float* proj, void* filt, fdkod_stream_t stream) {
     if (!pl || !proj || !filt) return fail(FDKOD_E_ARG, "NULL argument");
-    FilterArgs a;
-    a.proj = proj;
-    a.out = filt;
-    a.resp = pl->d_resp;
-    a.gtail = pl->d_gtail;
-    a.twiddle = pl->d_tw;
-    a.n = pl->n;
-    a.rows = pl->p * pl->n;
-    a.r = (float)pl->r;
-    a.c = (float)((pl->n - 1) / 2.0);
+    const FilterArgs a = filter_args(pl, proj, filt, 0, pl->n);
     HIP_TRY(launch_filter(a, pl->logm, pl->store, (hipStream_t)stream), "filter kernel launch");
     return FDKOD_OK;
 }
@@ -711,9 +734,9 @@ fdkod_status fdkod_tune(fdkod_plan_t pl, const void* filt, void* ws, float* vol,
     }
     float best = 1e30f;
     BpVariant bestv = pl->bpv;
-    for (int zr : {32, 16})
+    for (int zr : {64, 32, 16})
         for (int tw : {32, 64})
-            for (int th : {48, 64})
+            for (int th : {48, 64, 96})
                 for (int g : {1, 2, 4}) {
                     const BpVariant v{zr, tw, th, g};
                     if (!variant_holds(pl, v)) continue;

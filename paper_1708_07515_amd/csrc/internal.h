@@ -9,12 +9,13 @@
 namespace fdkod {
 
 // One square of the decomposition (Sec. 2.1): voxel index ranges, centre
-// (vertex mean, voxel coordinates), local grid and the offset of its
-// decimated data in the workspace (elements).
+// (vertex mean, voxel coordinates) and where its decimated data starts in a
+// workspace: the squares' blocks [P'][rows][W_q] are concatenated, so square
+// q starts at y_off_row * rows elements, y_off_row = P' * sum_{q'<q} W_q'.
 struct SquareDesc {
     int x0, x1, y0, y1;
     float xc, yc;
-    int64_t y_off;
+    int64_t y_off_row;
 };
 
 // One step of the decimation schedule: the extended angle index p_ext
@@ -56,7 +57,8 @@ struct FilterArgs {
     const float* gtail;     // g[u - N], u in [0, N)
     const float2* twiddle;  // exp(-2 pi i k / M), [M]
     int n;                  // detector width
-    int rows;               // P * N
+    int rows;               // P * nv
+    int v0, nv;             // detector rows [v0, v0 + nv) of every projection
     float r;                // R
     float c;                // (N-1)/2
 };
@@ -71,8 +73,9 @@ struct DecimVol {
     const DecimStep* sched;
     int nsched;
     int n, p, pd, nsq;
+    int v0, nv;             // detector rows [v0, v0 + nv): filt is [P][nv][N], ws blocks [P'][nv][W_q]
     int tasks_per_sq;       // column groups per square
-    int ntasks;             // nsq * n * tasks_per_sq
+    int ntasks;             // nsq * nv * tasks_per_sq
     int chunks;             // 64-column chunks per wave (1, 2, 4 or 8)
 };
 
@@ -93,7 +96,9 @@ struct BpVol {
     const SquareDesc* squares;
     const int2* grid;       // u0, W per square (direct: 0, N)
     const float2* trig;     // cos, sin of the reconstruction angles, [pd]
-    int n, nz, pd;
+    int n, nz, pd;          // nz: slices in the output buffer
+    int v0, nv;             // detector rows [v0, v0 + nv) held by data (rows outside read zero)
+    int zbase;              // volume slice of output slice 0
     int row_stride_direct;  // 0 for per-square layout [m][v][W_q]
     float r, cu, cv, cz;
     float scale;            // pi / P'

@@ -77,14 +77,14 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
 
     // the run covers ZR slices even past the volume's end (those voxels are
     // computed and discarded), so the staged rows always hold the whole run
-    const int l0 = zt * ZR;
-    const float z0 = (float)l0 - v.cz;
-    const float zlast = (float)(l0 + ZR - 1) - v.cz;
+    const int l0 = zt * ZR;                       // output slice (volume slice zbase + l0)
+    const float z0 = (float)(v.zbase + l0) - v.cz;
+    const float zlast = (float)(v.zbase + l0 + ZR - 1) - v.cz;
 
     const bool direct = v.row_stride_direct != 0;
     const int row_stride = direct ? v.row_stride_direct : width;
-    const size_t plane = (size_t)n * row_stride;
-    const T* data = (const T*)v.data + (direct ? 0 : sq.y_off);
+    const size_t plane = (size_t)v.nv * row_stride;
+    const T* data = (const T*)v.data + (direct ? 0 : sq.y_off_row * v.nv);
     const float kq = v.cu - (float)u0;            // tau = rel + kq
 
     // staging map: a lane keeps one footprint column, rows strided by 256 / TW
@@ -146,8 +146,8 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 const int rr = srow + r * RSTEP;
-                const int row = mt.y + rr;
-                pre[g][r] = (rr < mt.z && cok && (unsigned)row < (unsigned)n)
+                const int row = mt.y + rr - v.v0;        // row within the buffer
+                pre[g][r] = (rr < mt.z && cok && (unsigned)row < (unsigned)v.nv)
                                 ? pl[(size_t)row * row_stride + col] : (T)0;
             }
         }
@@ -322,6 +322,7 @@ hipError_t launch_reset_counter(unsigned* counter, hipStream_t st) {
 // Variant table: (zrun, TW, TH, G).  G is limited so that the LDS of one
 // workgroup stays within 64 KB.
 #define FDKOD_BP_VARIANTS(X)  \
+    X(64, 32, 96, 1) \
     X(32, 32, 48, 1) X(32, 32, 48, 2) X(32, 32, 48, 4) \
     X(32, 32, 64, 1) X(32, 32, 64, 2) \
     X(32, 64, 48, 1) X(32, 64, 48, 2) \

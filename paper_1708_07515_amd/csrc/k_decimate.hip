@@ -44,7 +44,7 @@ __device__ __forceinline__ void decimate_task(const DecimVol& a, int task, int l
     const int g = task % a.tasks_per_sq;
     const int vq = task / a.tasks_per_sq;
     const int q = vq % a.nsq;
-    const int v = vq / a.nsq;
+    const int v = vq / a.nsq;                 // row within the buffer (detector row v0 + v)
     const int n = a.n;
     const int2 gd = a.grid[q];
     const int u0 = gd.x, width = gd.y;
@@ -56,9 +56,9 @@ __device__ __forceinline__ void decimate_task(const DecimVol& a, int task, int l
     T* ws = (T*)a.ws;
     const cword_ptr sched = (cword_ptr)a.sched;                       // 4 words per step
     const cword_ptr crop = (cword_ptr)(a.crop + (size_t)q * a.nsched);  // 2 words per step
-    const int64_t yoff = a.squares[q].y_off;
-    const size_t plane = (size_t)n * width;   // elements per decimated angle
-    const size_t pstride = (size_t)n * n;     // elements per projection
+    const int64_t yoff = a.squares[q].y_off_row * a.nv;
+    const size_t plane = (size_t)a.nv * width;   // elements per decimated angle
+    const size_t pstride = (size_t)a.nv * n;     // elements per projection
     constexpr int ES = (int)sizeof(T);
     // per-lane byte offset of each chunk's column within the cropped run
     int lane_off[CH];

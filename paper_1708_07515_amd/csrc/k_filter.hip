@@ -171,17 +171,22 @@ void k_filter(FilterArgs a) {
 
     const int grp = threadIdx.x / TP;
     const int t = threadIdx.x % TP;
+    // rows 2k and 2k + 1 of one projection share a transform (a projection
+    // with an odd number of rows leaves its last row alone), so a band that
+    // starts at an even row pairs its rows as the whole detector does
+    const int hp = (a.nv + 1) >> 1;                   // row pairs per projection
     const int pair = blockIdx.x * PAIRS + grp;
-    const int r0 = 2 * pair, r1 = 2 * pair + 1;
-    const bool has0 = r0 < a.rows, has1 = r1 < a.rows;
+    const int pp = pair / hp, kk = pair - pp * hp;
+    const int r0 = pp * a.nv + 2 * kk, r1 = r0 + 1;
+    const bool has0 = r0 < a.rows, has1 = has0 && 2 * kk + 1 < a.nv;
     float2* z = buf + grp * MP;
     const int n = a.n;
     const float rr = a.r * a.r;
 
     // pre-weighted first difference d[u] = p~[u] - p~[u-1] (zero-padded);
     // p~[u-1] is recomputed from the row rather than read back from LDS
-    const float b0 = has0 ? (float)(r0 % n) - a.c : 0.0f;
-    const float b1 = has1 ? (float)(r1 % n) - a.c : 0.0f;
+    const float b0 = has0 ? (float)(a.v0 + r0 % a.nv) - a.c : 0.0f;
+    const float b1 = has1 ? (float)(a.v0 + r1 % a.nv) - a.c : 0.0f;
     const float rb0 = rr + b0 * b0, rb1 = rr + b1 * b1;
     const float* p0 = a.proj + (size_t)r0 * n;
     const float* p1 = a.proj + (size_t)r1 * n;
@@ -226,7 +231,7 @@ template <int LOGM>
 static hipError_t launch_filter_m(const FilterArgs& a, int store, hipStream_t st) {
     constexpr int TP = FilterShape<LOGM>::TP;
     constexpr int PAIRS = 256 / TP;
-    const int pairs = (a.rows + 1) / 2;
+    const int pairs = (a.rows / a.nv) * ((a.nv + 1) / 2);
     const dim3 grid((pairs + PAIRS - 1) / PAIRS);
     switch (store) {
         case 0: hipLaunchKernelGGL((k_filter<LOGM, 0>), grid, dim3(256), 0, st, a); break;

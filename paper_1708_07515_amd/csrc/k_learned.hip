@@ -199,7 +199,7 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd(LearnedArgs a) {
     const bool stager = col < width + 4;
     const bool valid = jj >= 0 && jj < width;
     T* ws = (T*)a.ws;
-    const size_t yrow = (size_t)a.squares[q].y_off + (size_t)v * width;   // + m n W + j
+    const size_t yrow = (size_t)a.squares[q].y_off_row * a.n + (size_t)v * width;   // + m n W + j
     const size_t yplane = (size_t)a.n * width;
     const int j = threadIdx.x;                                           // output column
     CentreWalk cw(a.p, a.pd);
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kThreads) void k_learned_bwd(LearnedArgs a) {
     f4v gw1[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
     float db2 = 0.0f;
     const int ntile = (width + 15) >> 4;
-    const int64_t yoff = a.squares[q].y_off;
+    const int64_t yoff = a.squares[q].y_off_row * a.n;
     float* trw = tr[wave];
     const int col_s = threadIdx.x, jj = col_s - 2;
     const bool stager = col_s < width + 4;
@@ -429,7 +429,7 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(AdjArgs a) {
         const float tf = floorf(tau), fu = tau - tf;
         const int iu = min(max((int)tf, 0), width - 2);
         const int iv = (int)vf;
-        const size_t plane = (size_t)sq.y_off + (size_t)m * a.n * width;
+        const size_t plane = (size_t)sq.y_off_row * a.n + (size_t)m * a.n * width;
 #pragma unroll
         for (int dv = 0; dv < 2; ++dv) {
             const int row = iv + dv;

@@ -22,7 +22,8 @@ struct fdkod_plan_s {
     fdkod::BpVariant bpv{32, 32, 48, 1};
     bool bp_ok = false;     // some variant's LDS footprint holds a block's footprint
     int ntiles = 0;
-    int64_t ws_elems = 0;
+    int64_t ws_row_elems = 0;  // workspace elements per detector row: P' * sum_q W_q
+    int64_t ws_elems = 0;      // ws_row_elems * N
     float tuned_bp_ms = 0.0f, tuned_dec_ms = 0.0f;
     // device tables
     fdkod::SquareDesc* d_sq = nullptr;
@@ -59,9 +60,15 @@ inline int dec_tasks_per_sq(int wmax, int chunks) { return (wmax + 64 * chunks -
 // z slabs of the backprojection for a variant
 inline int bp_zslabs(int nz, int zrun) { return (nz + zrun - 1) / zrun; }
 
-// argument blocks for one plan (data pointers supplied by the caller)
+// argument blocks for one plan (data pointers supplied by the caller); the
+// _band forms cover detector rows [v0, v0 + nv) and output slices
+// [zbase, zbase + nzs)
 DecimVol decim_args(const fdkod_plan_s* pl, const void* filt, void* ws, int chunks);
+DecimVol decim_args_band(const fdkod_plan_s* pl, const void* filt, void* ws, int chunks, int v0, int nv);
 BpVol bp_vol(const fdkod_plan_s* pl, const void* filt, const void* ws, float* vol);
+BpVol bp_vol_band(const fdkod_plan_s* pl, const void* filt, const void* ws, float* vol, int v0, int nv,
+                  int zbase, int nzs);
+FilterArgs filter_args(const fdkod_plan_s* pl, const float* proj, void* filt, int v0, int nv);
 
 }  // namespace fdkod
 

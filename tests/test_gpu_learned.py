@@ -46,13 +46,13 @@ def device_weights(net):
 
 def square_views(plan, buf):
     """Per-square [P', N, W_q] views of a workspace-layout tensor (element
-    offsets: cumulative P' N W_q rounded up to 64 elements)."""
+    offsets: cumulative P' N W_q)."""
     widths = plan.get_bounds()["width"]
     out, off = [], 0
     for w in widths:
         size = plan.p_dec * plan.n * int(w)
         out.append(buf[off:off + size].reshape(plan.p_dec, plan.n, int(w)))
-        off = (off + size + 63) // 64 * 64
+        off += size
     return out
 
 
