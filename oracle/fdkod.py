@@ -265,6 +265,87 @@ def fdkod(proj, r, s, k=0, slices=None, nz=None, store=None):
     return out
 
 
+# ------------------------------------------------ cone-corrected decimation
+#
+# An extension beyond the paper (its Sec. 2.1 crops and shifts every detector
+# row on its own and notes that the bounds stay roughly the same for all
+# slices).  Off the mid-plane a voxel's detector row b = z R / D(beta)
+# (eq. (9)) moves with the angle, so averaging a row over the decimation
+# window blurs it.  The cone-corrected crop also resamples the rows, by the
+# square centre's depth D_c(beta) = R + x_c cos beta + y_c sin beta:
+#
+#   S[p][v'][j] = Bil(q[p], (v' - c_v) R / D_c(beta_p) + c_v, a_c(beta_p) + u0 + j)
+#
+# so that a point above the square's centre keeps one warped row v' = z + c_v
+# at every angle.  The reconstruction samples the warped data at
+# v' = z D_c(beta') / D(beta') + c_v (the same eq. (9) in warped rows).
+
+def cone_row_scale(sq, beta, r):
+    """R / D_c(beta): detector row offset per warped row offset."""
+    return r / g.depth(sq.xc, sq.yc, beta, r)
+
+
+def crop_shift_cone(frows, sq, betas, r, n):
+    """Cone-corrected step 3 for every warped row v' = 0..N-1: S[p, v', j]
+    (frows must hold every detector row)."""
+    if len(frows.rows) != frows.nv:
+        raise ValueError("the cone-corrected crop needs every filtered row")
+    cv = g.centre(n)
+    ac = centre_track(sq, betas, r)
+    j = np.arange(sq.width, dtype=np.float64)
+    vw = np.arange(frows.nv, dtype=np.float64)
+    out = np.zeros((len(betas), frows.nv, sq.width))
+    for p, beta in enumerate(betas):
+        rows = (vw - cv) * cone_row_scale(sq, beta, r) + cv
+        out[p] = fdk_mod.bilinear(frows.data[p], frows.slot, frows.nv, rows[:, None],
+                                  (ac[p] + sq.u0 + j)[None, :])
+    return out
+
+
+def cone_row(sq, x, y, z, beta, r):
+    """Warped row offset v' - c_v = z D_c(beta) / D(beta) of voxel (x, y, z)."""
+    return z * g.depth(sq.xc, sq.yc, beta, r) / g.depth(x, y, beta, r)
+
+
+def backproject_square_cone(y_sub, nv, sq, betas_dec, r, n, x, y, z):
+    """Step 5 on cone-corrected data Y[m, v', j]: as backproject_square, with
+    the row coordinate cone_row + c_v."""
+    cu = cv = g.centre(n)
+    pd = len(betas_dec)
+    ac = centre_track(sq, betas_dec, r)
+    slot = np.arange(nv)
+    f = np.zeros(np.broadcast(x, y, z).shape)
+    for m, beta in enumerate(betas_dec):
+        u_mag = g.depth(x, y, beta, r) / r
+        a = g.pix_pos(x, y, beta, r)
+        tau = a - ac[m] + cu - sq.u0
+        if tau.size and (tau.min() < 0.0 or tau.max() >= sq.width - 1):
+            raise AssertionError("local column outside the square's grid")
+        f += fdk_mod.bilinear(y_sub[m], slot, nv, cone_row(sq, x, y, z, beta, r) + cv, tau) / (u_mag * u_mag)
+    return (np.pi / pd) * f
+
+
+def fdkod_cone(proj, r, s, k=0, slices=None, nz=None, store=None):
+    """FDK-OD with the cone-corrected decimation, listed slices (all by
+    default).  Filters every detector row.  Returns [S, N, N]."""
+    p_count, nv, n = proj.shape
+    nz = n if nz is None else nz
+    slices = np.arange(nz) if slices is None else np.asarray(slices)
+    sqs, betas, betas_dec = plan(n, p_count, r, s, k)
+    weights = triangle_weights(p_count, len(betas_dec))
+    frows = fdk_mod.filter_rows(proj, r, np.arange(nv))
+    if store is not None:
+        frows.data = store(frows.data)
+    out = np.zeros((len(slices), n, n))
+    for sq in sqs:
+        z, y, x = _square_points(sq, n, nz, slices)
+        y_sub = decimate(crop_shift_cone(frows, sq, betas, r, n), weights)
+        if store is not None:
+            y_sub = store(y_sub)
+        out[:, sq.y0:sq.y1, sq.x0:sq.x1] = backproject_square_cone(y_sub, nv, sq, betas_dec, r, n, x, y, z)
+    return out
+
+
 def square_of(n, s, i, j):
     """Index q of the square that holds voxel column i, row j."""
     b = g.blocks(n, 2 ** s)
