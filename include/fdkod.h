@@ -68,7 +68,19 @@ typedef enum {
 
 typedef enum { FDKOD_F32 = 0, FDKOD_F16 = 1, FDKOD_BF16 = 2 } fdkod_dtype;
 
-typedef enum { FDKOD_DECIM_TRIANGLE = 0 } fdkod_decim;
+/* Decomposition of the filtered sinogram (Sec. 2.1, step 3):
+ *  TRIANGLE  crop, shift and triangle decimation of each detector row, as in
+ *            Sec. 2.1; the backprojection reads row z R / D(beta) + c_v (eq. (9)).
+ *  CONE      cone-corrected rows (an extension beyond the paper): before the
+ *            decimation, row v' of square q at angle beta is resampled from
+ *            detector row (v' - c_v) R / D_c(beta) + c_v (bilinear; rows outside
+ *            the detector read zero), D_c the depth of the square's centre, so
+ *            a voxel's row coordinate z D_c / D + c_v varies little with beta
+ *            and the angular decimation averages less of the z direction.
+ *            Needs s > 0 to differ from TRIANGLE (s = 0 gives the same result);
+ *            not available to the learned decimation, the slab mode and
+ *            batches (FDKOD_E_UNSUPPORTED). */
+typedef enum { FDKOD_DECIM_TRIANGLE = 0, FDKOD_DECIM_CONE = 1 } fdkod_decim;
 
 /* Problem statement, after Sec. 2.1: N, P, R, s, and the skipped
  * decimation stages k of Sec. 2.2 (D = 2^(s-k), P' = ceil(P / D)). */

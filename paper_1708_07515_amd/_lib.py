@@ -128,15 +128,20 @@ def _check(status):
         raise FdkodError(status, lib.fdkod_last_error().decode())
 
 
-def _params(n, p, r, s=0, skip=0, nz=0, store="f32"):
+DECIM_TYPES = {"triangle": 0, "cone": 1}
+
+
+def _params(n, p, r, s=0, skip=0, nz=0, store="f32", decim="triangle"):
     if isinstance(store, str):
         store = STORE_TYPES[store]
-    return Params(int(n), int(nz), int(p), float(r), int(s), int(skip), int(store), 0)
+    if isinstance(decim, str):
+        decim = DECIM_TYPES[decim]
+    return Params(int(n), int(nz), int(p), float(r), int(s), int(skip), int(store), int(decim))
 
 
-def validate(n, p, r, s=0, skip=0, nz=0, store="f32"):
+def validate(n, p, r, s=0, skip=0, nz=0, store="f32", decim="triangle"):
     """Host-only parameter check (no device needed)."""
-    prm = _params(n, p, r, s, skip, nz, store)
+    prm = _params(n, p, r, s, skip, nz, store, decim)
     _check(load_library().fdkod_validate(ctypes.byref(prm)))
 
 
@@ -185,9 +190,10 @@ def _stream_ptr(stream):
 class Plan:
     """An FDK-OD plan: geometry tables on one device, sizes of the buffers."""
 
-    def __init__(self, n, p, r, s=0, skip=0, nz=0, store="f32", device=0, _handle=None):
+    def __init__(self, n, p, r, s=0, skip=0, nz=0, store="f32", device=0, decim="triangle", _handle=None):
         self._lib = load_library()
-        self.params = _params(n, p, r, s, skip, nz, store)
+        self.params = _params(n, p, r, s, skip, nz, store, decim)
+        self.decim = self.params.decim
         self.n, self.p, self.r, self.s, self.skip = int(n), int(p), float(r), int(s), int(skip)
         self.nz = int(nz) or int(n)
         self.store = self.params.store
@@ -475,7 +481,8 @@ class Batch:
         """volumes: list of dicts with keys n, p, r and optional s, skip, nz."""
         self._lib = load_library()
         self.device = int(device)
-        prms = [_params(v["n"], v["p"], v["r"], v.get("s", 0), v.get("skip", 0), v.get("nz", 0), store)
+        prms = [_params(v["n"], v["p"], v["r"], v.get("s", 0), v.get("skip", 0), v.get("nz", 0), store,
+                        v.get("decim", "triangle"))
                 for v in volumes]
         arr = (Params * len(prms))(*prms)
         h = ctypes.c_void_p()

@@ -217,6 +217,8 @@ fdkod_status fdkod_batch_create(const fdkod_params* prms, int32_t count, int dev
         fdkod_status st = fdkod_validate(&prms[i]);
         if (st != FDKOD_OK) return st;
         if (prms[i].store != prms[0].store) return fail(FDKOD_E_ARG, "all volumes of a batch share the store type");
+        if (prms[i].decim != FDKOD_DECIM_TRIANGLE && prms[i].s > 0)
+            return fail(FDKOD_E_UNSUPPORTED, "batches use the triangle decimation");
     }
     fdkod_batch_t b = new fdkod_batch_s();
     b->device = device;
@@ -248,7 +250,7 @@ fdkod_status fdkod_batch_create(const fdkod_params* prms, int32_t count, int dev
         bool all = true;
         for (fdkod_plan_t p : b->plans) {
             int w = 0, h = 0;
-            if (!bp_tiles_for(p->n, p->nz, p->r, zr, &w, &h)) {
+            if (!bp_tiles_for(p->n, p->nz, p->r, zr, 0, &w, &h)) {
                 all = false;
                 break;
             }

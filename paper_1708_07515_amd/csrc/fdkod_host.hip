@@ -203,7 +203,7 @@ namespace fdkod {
 // Choose the backprojection LDS footprint (TW x TH samples) that holds the
 // footprint of a 16 x 16 x zrun voxel block at any angle, from the slice's
 // smallest depth Dmin = R - (N-1)/sqrt(2).
-bool bp_tiles_for(int n, int nz, double r, int zrun, int* tw, int* th) {
+bool bp_tiles_for(int n, int nz, double r, int zrun, int cone_side, int* tw, int* th) {
     const double c = (n - 1) / 2.0;
     const double dmin = r - c * std::sqrt(2.0);
     const double mag = r / dmin;
@@ -211,7 +211,12 @@ bool bp_tiles_for(int n, int nz, double r, int zrun, int* tw, int* th) {
     const double diag = (kTileXY - 1) * std::sqrt(2.0);
     const double span_c = diag * mag * std::sqrt(1.0 + lat * lat);
     const double zmax = (nz - 1) / 2.0 + zrun;     // runs may extend past the last slice
-    const double span_r = (zrun - 1) * mag + zmax * r * diag / (dmin * dmin);
+    // rows per slice: R / D (eq. (9)); on cone-corrected rows D_c / D, where
+    // D_c <= D + h with h the square's half diagonal
+    const double hd = cone_side * std::sqrt(0.5);
+    const double rows_per_z = cone_side ? (dmin + hd) / dmin : mag;
+    const double numer = cone_side ? dmin + hd : r;   // bounds R (or D_c) where D = dmin
+    const double span_r = (zrun - 1) * rows_per_z + zmax * numer * diag / (dmin * dmin);
     const int need_c = (int)std::ceil(span_c + 1e-6) + 4;
     const int need_r = (int)std::ceil(span_r + 1e-6) + 4;
     *tw = need_c <= 32 ? 32 : (need_c <= 64 ? 64 : 0);
@@ -232,7 +237,10 @@ DecimVol decim_args_band(const fdkod_plan_s* pl, const void* filt, void* ws, int
     a.grid = pl->d_grid;
     a.crop = pl->d_crop;
     a.sched = pl->d_sched;
+    a.rscale = pl->d_rscale;
     a.nsched = pl->nsched;
+    a.cone = pl->cone;
+    a.cv = (float)((pl->n - 1) / 2.0);
     a.n = pl->n;
     a.p = pl->p;
     a.pd = pl->pd;
@@ -266,7 +274,7 @@ FilterArgs filter_args(const fdkod_plan_s* pl, const float* proj, void* filt, in
 bool variant_holds(const fdkod_plan_s* pl, const BpVariant& v) {
     if (!backproject_variant_exists(v)) return false;
     int tw = 0, th = 0;
-    if (!bp_tiles_for(pl->n, pl->nz, pl->r, v.zrun, &tw, &th)) return false;
+    if (!bp_tiles_for(pl->n, pl->nz, pl->r, v.zrun, cone_side(pl), &tw, &th)) return false;
     return v.tile_w >= tw && v.tile_h >= th;
 }
 
@@ -289,6 +297,7 @@ BpVol bp_vol_band(const fdkod_plan_s* pl, const void* filt, const void* ws, floa
     v.v0 = v0;
     v.nv = nv;
     v.zbase = zbase;
+    v.cone = pl->cone;
     v.row_stride_direct = direct ? pl->n : 0;
     v.r = (float)pl->r;
     v.cu = (float)((pl->n - 1) / 2.0);
@@ -307,6 +316,7 @@ std::string tune_key(const fdkod_plan_s* pl) {
     std::ostringstream k;
     k << "gfx950 n=" << pl->n << " nz=" << pl->nz << " p=" << pl->p << " r=" << pl->r
       << " s=" << pl->s << " k=" << pl->k << " store=" << pl->store;
+    if (pl->cone) k << " decim=cone";
     return k.str();
 }
 
@@ -391,7 +401,8 @@ fdkod_status fdkod_validate(const fdkod_params* prm) {
     if (q.nz < 0 || q.nz > 65536) return fail(FDKOD_E_ARG, "nz must be in [0, 65536]");
     if (q.p < 1 || q.p > 65536) return fail(FDKOD_E_ARG, "p must be in [1, 65536]");
     if (q.store < FDKOD_F32 || q.store > FDKOD_BF16) return fail(FDKOD_E_ARG, "unknown store type");
-    if (q.decim != FDKOD_DECIM_TRIANGLE) return fail(FDKOD_E_ARG, "unknown decimation");
+    if (q.decim != FDKOD_DECIM_TRIANGLE && q.decim != FDKOD_DECIM_CONE)
+        return fail(FDKOD_E_ARG, "unknown decimation");
     if (!std::isfinite(q.r)) return fail(FDKOD_E_GEOMETRY, "R is not finite");
     if (q.s < 0 || q.s > 12) return fail(FDKOD_E_GEOMETRY, "s must be in [0, 12]");
     if ((1 << q.s) > q.n) return fail(FDKOD_E_GEOMETRY, "2^s exceeds N");
@@ -433,6 +444,7 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
     pl->pd = (int)ceildiv(pl->p, pl->d);
     pl->nsq = 1 << (2 * pl->s);
     pl->store = prm->store;
+    pl->cone = prm->decim == FDKOD_DECIM_CONE && prm->s > 0;
     {
         int m = 8;
         while (m < 2 * pl->n - 1) m <<= 1;
@@ -491,6 +503,9 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
         return bail(st);
     if ((st = dev_alloc(pl->allocs, (void**)&pl->d_grid, sizeof(int2) * (size_t)pl->nsq)) != FDKOD_OK)
         return bail(st);
+    if (pl->cone &&
+        (st = dev_alloc(pl->allocs, (void**)&pl->d_rscale, sizeof(float) * (size_t)pl->nsq * pl->nsched)) != FDKOD_OK)
+        return bail(st);
 
     // bounds kernel, then one synchronisation to lay out the workspace
     if ((st = fdkod_bounds(pl, nullptr)) != FDKOD_OK) return bail(st);
@@ -530,7 +545,7 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
     for (int zr : {32, 16, 64}) {
         int tw = 0, th = 0;
         // one angle per stage: the smallest LDS footprint, the highest occupancy
-        if (bp_tiles_for(pl->n, pl->nz, pl->r, zr, &tw, &th) &&
+        if (bp_tiles_for(pl->n, pl->nz, pl->r, zr, cone_side(pl), &tw, &th) &&
             backproject_variant_exists(BpVariant{zr, tw, th, 1})) {
             pl->bpv = BpVariant{zr, tw, th, 1};
             pl->bp_ok = true;
@@ -593,6 +608,7 @@ fdkod_status fdkod_bounds(fdkod_plan_t pl, fdkod_stream_t stream) {
     a.grid = pl->d_grid;
     a.sched = pl->d_sched;
     a.crop = pl->d_crop;
+    a.rscale = pl->d_rscale;
     a.n = pl->n;
     a.p = pl->p;
     a.pd = pl->pd;

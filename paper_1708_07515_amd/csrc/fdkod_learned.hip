@@ -12,6 +12,7 @@ namespace {
 
 fdkod_status learned_check(const fdkod_plan_s* pl) {
     if (pl->s == 0) return fail(FDKOD_E_UNSUPPORTED, "the learned decimation needs s > 0");
+    if (pl->cone) return fail(FDKOD_E_UNSUPPORTED, "the learned decimation corrects the triangle decimation");
     if (pl->wmax > kLearnedMaxWidth)
         return fail(FDKOD_E_UNSUPPORTED, "a square is wider than 252 local columns");
     if (pl->p > kLearnedMaxP) return fail(FDKOD_E_UNSUPPORTED, "more than 2048 projections");

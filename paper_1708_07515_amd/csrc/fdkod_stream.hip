@@ -30,6 +30,13 @@ void band_for(const fdkod_plan_s* pl, int z0, int nzs, int* v0, int* nv) {
     *nv = std::max(0, hi - lo);
 }
 
+// cone-corrected rows are not detector rows: a band of them would need the
+// whole detector height, so the slab mode covers the triangle decimation only
+fdkod_status check_rows_are_detector_rows(const fdkod_plan_s* pl) {
+    if (pl->cone) return fail(FDKOD_E_UNSUPPORTED, "the slab mode needs the triangle decimation");
+    return FDKOD_OK;
+}
+
 fdkod_status check_band(const fdkod_plan_s* pl, int v0, int nv) {
     if (v0 < 0 || nv < 1 || v0 + nv > pl->n) return fail(FDKOD_E_ARG, "band rows outside the detector");
     return FDKOD_OK;
@@ -105,6 +112,7 @@ extern "C" {
 fdkod_status fdkod_band_rows(fdkod_plan_t pl, int32_t z0, int32_t nzs, int32_t* v0, int32_t* nrows) {
     if (!pl || !v0 || !nrows) return fail(FDKOD_E_ARG, "NULL argument");
     if (z0 < 0 || nzs < 1 || z0 + nzs > pl->nz) return fail(FDKOD_E_ARG, "slab slices outside the volume");
+    if (check_rows_are_detector_rows(pl) != FDKOD_OK) return FDKOD_E_UNSUPPORTED;
     int a = 0, b = 0;
     band_for(pl, z0, nzs, &a, &b);
     *v0 = a;
@@ -127,6 +135,7 @@ fdkod_status fdkod_decompose_band(fdkod_plan_t pl, const void* filt_band, int32_
     if (!pl || !filt_band) return fail(FDKOD_E_ARG, "NULL argument");
     fdkod_status st = check_band(pl, v0, nrows);
     if (st != FDKOD_OK) return st;
+    if ((st = check_rows_are_detector_rows(pl)) != FDKOD_OK) return st;
     if (pl->s == 0) return FDKOD_OK;
     if (!ws_band) return fail(FDKOD_E_ARG, "workspace is NULL");
     const DecimVol a = decim_args_band(pl, filt_band, ws_band, pl->dec_chunks, v0, nrows);
@@ -144,6 +153,7 @@ fdkod_status fdkod_reconstruct_slab(fdkod_plan_t pl, const void* filt_band, cons
         return fail(FDKOD_E_UNSUPPORTED, "R too small: a block's detector footprint exceeds the LDS tiles");
     fdkod_status st = check_band(pl, v0, nrows);
     if (st != FDKOD_OK) return st;
+    if ((st = check_rows_are_detector_rows(pl)) != FDKOD_OK) return st;
     if ((st = check_slab(pl, v0, nrows, z0, nzs)) != FDKOD_OK) return st;
     return launch_slab(pl, filt_band, ws_band, v0, nrows, z0, nzs, vol_slab, (hipStream_t)stream);
 }
@@ -160,6 +170,7 @@ fdkod_status fdkod_reconstruct_streamed(fdkod_plan_t pl, const float* host_proj,
                                         fdkod_stream_t copy_stream) {
     if (!pl || !host_proj || !host_vol || !work) return fail(FDKOD_E_ARG, "NULL argument");
     if (nzs < 1) return fail(FDKOD_E_ARG, "slab must hold at least one slice");
+    if (check_rows_are_detector_rows(pl) != FDKOD_OK) return FDKOD_E_UNSUPPORTED;
     if (!pl->bp_ok)
         return fail(FDKOD_E_UNSUPPORTED, "R too small: a block's detector footprint exceeds the LDS tiles");
     const StreamLayout L = stream_layout(pl, nzs);

@@ -45,6 +45,7 @@ struct BoundsArgs {
     int2* grid;             // [nsq] u0, W
     const DecimStep* sched; // decimation schedule (projection of each step)
     int2* crop;             // [nsq][nsched] floor(a_c + u0), bits of the fraction
+    float* rscale;          // [nsq][nsched] R / D_c(beta) (cone-corrected rows), or null
     int n, p, pd, nsq, nsched;
     float r, cu;
 };
@@ -71,7 +72,10 @@ struct DecimVol {
     const int2* grid;       // u0, W per square
     const int2* crop;       // [nsq][nsched] integer shift and fraction per step
     const DecimStep* sched;
+    const float* rscale;    // [nsq][nsched] row scale R / D_c(beta) (cone-corrected rows)
     int nsched;
+    int cone;               // 1: rows resampled by rscale about cv before the decimation
+    float cv;               // (N-1)/2
     int n, p, pd, nsq;
     int v0, nv;             // detector rows [v0, v0 + nv): filt is [P][nv][N], ws blocks [P'][nv][W_q]
     int tasks_per_sq;       // column groups per square
@@ -99,6 +103,7 @@ struct BpVol {
     int n, nz, pd;          // nz: slices in the output buffer
     int v0, nv;             // detector rows [v0, v0 + nv) held by data (rows outside read zero)
     int zbase;              // volume slice of output slice 0
+    int cone;               // 1: data rows are cone-corrected (row offset z D_c / D)
     int row_stride_direct;  // 0 for per-square layout [m][v][W_q]
     float r, cu, cv, cz;
     float scale;            // pi / P'

@@ -116,7 +116,7 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
                 const float tau = v.r * (dl * dc - lc * dd) * rdc * rd + kq;
                 tlo = fminf(tlo, tau);
                 thi = fmaxf(thi, tau);
-                const float iu = v.r * rd;
+                const float iu = (v.cone ? dc : v.r) * rd;   // row offset per unit z
                 const float va = z0 * iu + v.cv, vb = zlast * iu + v.cv;
                 vlo = fminf(vlo, fminf(va, vb));
                 vhi = fmaxf(vhi, fmaxf(va, vb));
@@ -207,26 +207,28 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
             const float d = mg.z + dd;
             const float rd = __builtin_amdgcn_rcpf(d);
             const float tau = (dl * mg.z - mg.w * dd) * mg2.x * rd + mg2.y;
-            float invu = v.r * rd;
+            const float invu = v.r * rd;                 // 1 / U
             float w = v.scale * invu * invu;
+            // row offset per unit z: R / D (eq. (9)), or D_c / D on cone-corrected rows
+            float vstep = (v.cone ? mg.z : v.r) * rd;
             const float tf = floorf(tau);
             const float fu = tau - tf;
             const int ci = min(max((int)tf, 0), TW - 2);
-            float v0 = fmaf(z0, invu, v.cv - (float)mt.y);
+            float v0 = fmaf(z0, vstep, v.cv - (float)mt.y);
             // the row index is monotone in z: check the run's ends once; a
             // run outside the staged rows (never expected) contributes zero
-            const float vend = fmaf((float)(ZR - 1), invu, v0);
+            const float vend = fmaf((float)(ZR - 1), vstep, v0);
             if (!(v0 >= 0.0f && vend < (float)(mt.z - 1))) {
                 w = 0.0f;
                 v0 = 0.5f;
-                invu = 0.0f;
+                vstep = 0.0f;
             }
             // 32-bit LDS byte address of the thread's column in this footprint
             uint32_t tga = (uint32_t)(uintptr_t)(lds_cptr)(tile[g] + ci);
             asm volatile("" : "+v"(tga));   // keep it one register: address = mad24(row, pitch, tga)
 #pragma unroll
             for (int k = 0; k < ZR; ++k) {
-                const float vv = fmaf((float)k, invu, v0);
+                const float vv = fmaf((float)k, vstep, v0);
                 const float fv = __builtin_amdgcn_fractf(vv);
                 const uint32_t ri = (uint32_t)(int)vv;
                 const lds_f2ptr p = (lds_f2ptr)(uintptr_t)(tga + __umul24(ri, (uint32_t)(TWP * sizeof(float2))));

@@ -86,6 +86,7 @@ __global__ __launch_bounds__(256) void k_bounds(BoundsArgs a) {
         const float o = pix_pos(sq.xc, sq.yc, tr.x, tr.y, a.r) + u0f;
         const float of = floorf(o);
         a.crop[(size_t)q * a.nsched + t] = make_int2((int)of, __float_as_int(o - of));
+        if (a.rscale) a.rscale[(size_t)q * a.nsched + t] = a.r / (a.r + sq.xc * tr.x + sq.yc * tr.y);
     }
 }
 

@@ -12,6 +12,7 @@ struct fdkod_plan_s {
     int device = 0;
     int n = 0, nz = 0, p = 0, s = 0, k = 0, d = 1, pd = 0, nsq = 1, store = 0;
     int logm = 0;
+    int cone = 0;           // cone-corrected rows (FDKOD_DECIM_CONE with s > 0)
     double r = 0;
     std::vector<fdkod::SquareDesc> sq;
     std::vector<int2> grid;
@@ -31,6 +32,7 @@ struct fdkod_plan_s {
     float2* d_trig_m = nullptr;
     float* d_ac_p = nullptr;
     int2* d_crop = nullptr;
+    float* d_rscale = nullptr;  // [nsq][nsched] R / D_c (cone-corrected rows only)
     float4* d_geo_m = nullptr;
     int2* d_grid = nullptr;
     int2* d_grid_direct = nullptr;
@@ -51,8 +53,11 @@ fdkod_status hip_fail(hipError_t e, const char* what);
 fdkod_status dev_alloc(std::vector<void*>& owner, void** ptr, size_t bytes);
 
 // minimal LDS footprint (columns, rows) of a 16 x 16 x zrun block for a plan's
-// geometry; false when no tile holds it
-bool bp_tiles_for(int n, int nz, double r, int zrun, int* tw, int* th);
+// geometry; false when no tile holds it.  cone_side > 0: cone-corrected rows
+// of squares at most cone_side voxels wide.
+bool bp_tiles_for(int n, int nz, double r, int zrun, int cone_side, int* tw, int* th);
+// square side bound for bp_tiles_for (0 unless the plan's rows are cone-corrected)
+inline int cone_side(const fdkod_plan_s* pl) { return pl->cone ? (pl->n + (1 << pl->s) - 1) >> pl->s : 0; }
 // a backprojection variant exists and its LDS footprint holds the plan's
 bool variant_holds(const fdkod_plan_s* pl, const BpVariant& v);
 // tasks per square of the decimation for a chunk count

@@ -47,6 +47,7 @@ def test_version_and_status_strings():
     (dict(n=64, p=90, r=512.0, s=2, skip=3), "E_GEOMETRY"),
     (dict(n=64, p=7, r=512.0, s=2), "E_GEOMETRY"),       # P < 2 D
     (dict(n=64, p=90, r=512.0, nz=-1), "E_ARG"),
+    (dict(n=64, p=90, r=512.0, s=2, decim=2), "E_ARG"),
 ])
 def test_validation_codes(args, code):
     with pytest.raises(pkg.FdkodError) as ei:
@@ -55,7 +56,9 @@ def test_validation_codes(args, code):
 
 
 @pytest.mark.parametrize("args", [dict(n=64, p=90, r=512.0, s=2), dict(n=2000, p=720, r=8000.0, s=4),
-                                  dict(n=64, p=8, r=45.0, s=2, skip=0), dict(n=3, p=1, r=2.0)])
+                                  dict(n=64, p=8, r=45.0, s=2, skip=0), dict(n=3, p=1, r=2.0),
+                                  dict(n=64, p=90, r=512.0, s=2, decim="cone"),
+                                  dict(n=64, p=90, r=512.0, s=0, decim="cone")])
 def test_validation_accepts(args):
     pkg.validate(**args)
 
@@ -89,6 +92,9 @@ def test_batch_validation_before_device():
     assert lib.fdkod_batch_create(arr, 2, 0, ctypes.byref(h)) == 2
     arr = (_lib.Params * 2)(good, mixed)
     assert lib.fdkod_batch_create(arr, 2, 0, ctypes.byref(h)) == 1
+    cone = _lib.Params(32, 0, 45, 128.0, 1, 0, 0, 1)       # cone-corrected rows
+    arr = (_lib.Params * 2)(good, cone)
+    assert lib.fdkod_batch_create(arr, 2, 0, ctypes.byref(h)) == 3
     assert lib.fdkod_batch_create(arr, 0, 0, ctypes.byref(h)) == 1
     assert h.value is None
     assert lib.fdkod_batch_run(None, None) == 1
