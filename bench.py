@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-filter step")
     ap.add_argument("--no-streamed", action="store_true", help="skip the low-memory slab mode run")
+    ap.add_argument("--no-cone", action="store_true", help="skip the cone-corrected decimation run")
     ap.add_argument("--slab", type=int, default=64, help="slices per slab in the slab mode")
     ap.add_argument("--cpu-slices", type=int, default=12)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -174,6 +175,69 @@ def run_learned(torch, pkg, wl, res, steps):
             "stage_ms": {a: round(b, 4) for a, b in per.items()},
             "decompose_triangle_ms": round(res["per"]["decompose"], 4),
             "weights": "817 BF16 parameters, seeded random"}
+
+
+def _rel_rmse_regions(torch, vol, ref, regions, chunk=32):
+    """rel-RMSE of vol against ref (device volumes) over slice ranges, in FP64
+    chunks of slices so that no full-volume temporary is made."""
+    out = {}
+    for name, (z0, z1) in regions.items():
+        num = den = 0.0
+        for a in range(z0, z1, chunk):
+            b = min(a + chunk, z1)
+            r = ref[a:b].double()
+            num += float(((vol[a:b].double() - r) ** 2).sum())
+            den += float((r ** 2).sum())
+        out[name] = (num / den) ** 0.5 if den > 0 else None
+    return out
+
+
+def run_cone(torch, pkg, wl, s, k, store, res, steps):
+    """The FDK-OD step with the cone-corrected decimation on the same scan,
+    timed like the triangle step, and the error of both decimations against
+    the HIP direct FDK on the whole volume, on its top and bottom eighths
+    (where the cone angle is largest) and on the central eighth."""
+    if s == 0:
+        return None
+    n, p, r, nz = wl.n, wl.p, wl.r, wl.nzv
+    proj, filt, vol = res["proj"], res["filt"], res["vol"]
+    cplan = pkg.Plan(n, p, r, s=s, skip=k, nz=nz, store=store, decim="cone")
+    cws = cplan.empty_workspace()
+    cvol = cplan.empty_volume()
+    stages = [("bounds", lambda: cplan.bounds()),
+              ("filter", lambda: cplan.filter(proj, filt)),
+              ("decompose", lambda: cplan.decompose(filt, cws)),
+              ("reconstruct", lambda: cplan.reconstruct(filt, cws, cvol))]
+    per, step_ms, _ = timed_steps(torch, stages, steps, 1)
+    log("[bench] FDK-OD with the cone-corrected decimation, per stage (ms): "
+        + ", ".join(f"{a}={b:.3f}" for a, b in per.items()))
+    del cws
+    # the triangle result (vol may hold another decimation's since)
+    plan, ws = res["plan"], res["ws"]
+    plan.decompose(filt, ws)
+    plan.reconstruct(filt, ws, vol)
+    dplan = pkg.Plan(n, p, r, s=0, nz=nz, store=store)
+    dvol = dplan.empty_volume()
+    dplan.filter(proj, filt)
+    dplan.reconstruct(filt, None, dvol)
+    torch.cuda.synchronize()
+    e = max(1, nz // 8)
+    regions = {"whole": (0, nz), "top_eighth": (nz - e, nz), "bottom_eighth": (0, e),
+               "central_eighth": ((nz - e) // 2, (nz - e) // 2 + e)}
+    tri = _rel_rmse_regions(torch, vol, dvol, regions)
+    cone = _rel_rmse_regions(torch, cvol, dvol, regions)
+    log("[bench] rel-RMSE vs direct FDK, triangle / cone: "
+        + ", ".join(f"{a} {tri[a]:.4f} / {cone[a]:.4f}" for a in regions))
+    del dvol, cvol
+    updates_eq = n * n * nz * p
+    paper_ms = per["bounds"] + per["decompose"] + per["reconstruct"]
+    return {"ms_per_step": round(step_ms, 4),
+            "gvups": round(updates_eq / (step_ms * 1e-3) / 1e9, 3),
+            "gvups_paper_scope": round(updates_eq / (paper_ms * 1e-3) / 1e9, 3),
+            "stage_ms": {a: round(b, 4) for a, b in per.items()},
+            "rel_rmse_vs_direct_fdk": {"triangle": {a: round(b, 6) for a, b in tri.items()},
+                                       "cone": {a: round(b, 6) for a, b in cone.items()}},
+            "regions": {a: list(b) for a, b in regions.items()}}
 
 
 def run_streamed(torch, res, slab):
@@ -357,6 +421,7 @@ def main():
         log("[bench] timing the CPU oracle on a bounded sample")
         cpu, parity = cpu_baseline(res["proj"].cpu(), wl, s, k, res["vol"], args.cpu_slices)
     learned = None if args.no_learned else run_learned(torch, pkg, wl, res, max(1, min(args.steps, 5)))
+    cone = None if args.no_cone else run_cone(torch, pkg, wl, s, k, store, res, max(1, min(args.steps, 5)))
     del res
 
     large = None
@@ -366,6 +431,8 @@ def main():
         lres = run_workload(torch, pkg, lw, max(lw.s), lw.k, lw.store[0], 2, 1,
                             direct=not args.no_direct)
         large = summarise(lw, max(lw.s), lw.k, lw.store[0], lres)
+        if not args.no_cone:
+            large["cone_decimation"] = run_cone(torch, pkg, lw, max(lw.s), lw.k, lw.store[0], lres, 2)
         if not args.no_streamed:
             large["streamed"] = run_streamed(torch, lres, args.slab)
         del lres
@@ -406,6 +473,7 @@ def main():
         "large_workload": large,
         "batch_workload": batch,
         "learned_decimation": learned,
+        "cone_decimation": cone,
     }
     print(json.dumps(out), flush=True)
 

@@ -49,11 +49,14 @@ __device__ __forceinline__ void decimate_task(const DecimVol& a, int task, int l
     constexpr int U = DecimGroup<CH>::U;
     constexpr int CC = CONE ? CH : 1;   // second-row samples (CONE only)
     static_assert(kDecimUnroll % U == 0, "the schedule is padded to whole groups");
-    // task = (v * nsq + q) * tasks_per_sq + g
+    // task = (v * nsq + q) * tasks_per_sq + g: the squares of one detector row
+    // run together and share its reads in L2.  CONE: task = (q * nv + v) *
+    // tasks_per_sq + g, since squares read different detector rows for the
+    // same warped row; neighbouring warped rows of one square share theirs.
     const int g = task % a.tasks_per_sq;
     const int vq = task / a.tasks_per_sq;
-    const int q = vq % a.nsq;
-    const int v = vq / a.nsq;                 // row within the buffer (detector row v0 + v)
+    const int q = CONE ? vq / a.nv : vq % a.nsq;
+    const int v = CONE ? vq % a.nv : vq / a.nsq;   // row within the buffer (detector row v0 + v)
     const int n = a.n;
     const int2 gd = a.grid[q];
     const int u0 = gd.x, width = gd.y;
@@ -113,9 +116,14 @@ __device__ __forceinline__ void decimate_task(const DecimVol& a, int task, int l
                 fv[u] = rr - rf;
                 r0 = __builtin_amdgcn_readfirstlane((int)rf);
             }
-            const int rows0 = CONE ? ((unsigned)r0 < (unsigned)n ? n * ES : 0) : n * ES;
-            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                (void*)(pbase + (CONE ? (ptrdiff_t)r0 * n : 0)), (short)0, rows0, 0x00020000);
+            // CONE: the row's address and extent go through readfirstlane so that
+            // the resource is built in scalar registers (a resource the compiler
+            // holds in vector registers costs a loop around every load)
+            const __amdgpu_buffer_rsrc_t rs =
+                CONE ? __builtin_amdgcn_make_buffer_rsrc(
+                           uniform_ptr(pbase + (ptrdiff_t)r0 * n), (short)0,
+                           __builtin_amdgcn_readfirstlane((unsigned)r0 < (unsigned)n ? n * ES : 0), 0x00020000)
+                     : __builtin_amdgcn_make_buffer_rsrc((void*)pbase, (short)0, n * ES, 0x00020000);
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
                 const int off0 = cr[u].x * ES + lane_off[c];
@@ -127,8 +135,8 @@ __device__ __forceinline__ void decimate_task(const DecimVol& a, int task, int l
             if constexpr (CONE) {
                 const int r1 = r0 + 1;
                 const __amdgpu_buffer_rsrc_t rs1 = __builtin_amdgcn_make_buffer_rsrc(
-                    (void*)(pbase + (ptrdiff_t)r1 * n), (short)0, (unsigned)r1 < (unsigned)n ? n * ES : 0,
-                    0x00020000);
+                    uniform_ptr(pbase + (ptrdiff_t)r1 * n), (short)0,
+                    __builtin_amdgcn_readfirstlane((unsigned)r1 < (unsigned)n ? n * ES : 0), 0x00020000);
 #pragma unroll
                 for (int c = 0; c < CH; ++c) {
                     const int off0 = cr[u].x * ES + lane_off[c];
