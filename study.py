@@ -1,0 +1,275 @@
+"""Quality and cost study of FDK-OD on one GPU, after the paper's own
+evaluations (Sec. 2.2 cost model, Sec. 4 quality), on synthetic phantoms:
+
+1. s x k sweep on a noise-free random-ellipsoid phantom (standing in for the
+   Shepp-Logan-3D phantom, whose parameter table the paper does not give):
+   rel-RMSE against direct FDK, and the voxel-wise ratio FDK-OD / FDK on the
+   uniform interiors of the objects (the paper's ratio maps, reduced to their
+   mean and spread where the ratio is meaningful: away from borders and from
+   near-zero densities).
+2. Slanted-edge resolution (Sec. 4) on an analytic box phantom rotated by 5
+   degrees: the edge spread function of one face in the central slice,
+   binned at a quarter voxel by distance to the known face, its derivative
+   (tapered beyond half the reach) and Fourier magnitude; MTF50, MTF10 and the 10-90 % edge
+   width for direct FDK and every (s, k, decimation).
+3. Time split vs s (Sec. 2.2): decomposition and reconstruction kernel times
+   for s = 1..5 at several N, and the constants of the cost model
+   Total = C1 N^3 P / 2^s + C2 N^2 P 2^s fitted by least squares (one
+   constant per term), with the optimum 2^s = sqrt(C1 N / C2) against the
+   measured best s.
+
+Usage: python study.py [--quick] > study.json (progress on stderr).  Every
+reconstruction runs in the HIP library; the analysis is plain NumPy.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------ analysis
+
+def face_coordinates(n, centre, angle, half):
+    """Signed distance to the face x' = +half[0] of a box rotated by ``angle``
+    about z (positive outside) and the coordinate along that face, for every
+    pixel of an N x N slice indexed [j (y), i (x)]; centre and half in voxels."""
+    c = (n - 1) / 2.0
+    j, i = np.mgrid[0:n, 0:n].astype(np.float64)
+    x, y = i - c - centre[0], j - c - centre[1]
+    ca, sa = math.cos(angle), math.sin(angle)
+    lx = x * ca + y * sa
+    ly = -x * sa + y * ca
+    return lx - half[0], ly
+
+
+def edge_spread(img, dist, along, half_len, reach=20.0, bin_w=0.25):
+    """Edge spread function: pixel values averaged in bins of ``bin_w`` voxels
+    of distance to the face, over pixels within ``reach`` of it and within
+    ``half_len`` of the face's middle.  Returns (bin centres, ESF)."""
+    sel = (np.abs(dist) < reach) & (np.abs(along) <= half_len)
+    nb = int(round(2 * reach / bin_w))
+    b = np.clip(np.floor((dist[sel] + reach) / bin_w).astype(np.int64), 0, nb - 1)
+    sums = np.bincount(b, weights=img[sel], minlength=nb)
+    cnt = np.bincount(b, minlength=nb)
+    if np.any(cnt == 0):
+        raise ValueError("empty distance bin: the face is not slanted enough or too short")
+    centres = -reach + (np.arange(nb) + 0.5) * bin_w
+    return centres, sums / cnt
+
+
+def mtf_from_esf(esf, bin_w=0.25):
+    """MTF (frequencies in cycles per voxel, magnitude normalised at 0) of an
+    edge spread function sampled every ``bin_w`` voxels, centred on the edge.
+    The line spread function is kept whole within half the reach and tapered
+    by a raised cosine beyond it (a full Hann window would narrow it)."""
+    lsf = np.gradient(esf, bin_w)
+    u = np.abs(np.arange(len(lsf)) + 0.5 - len(lsf) / 2.0) / (len(lsf) / 2.0)
+    lsf = lsf * np.where(u <= 0.5, 1.0, 0.5 * (1.0 + np.cos(2.0 * np.pi * (u - 0.5))))
+    spec = np.abs(np.fft.rfft(lsf))
+    return np.fft.rfftfreq(len(lsf), d=bin_w), spec / spec[0]
+
+
+def first_crossing(f, m, level):
+    """Frequency where m first falls below ``level`` (linear interpolation)."""
+    k = np.nonzero(m < level)[0]
+    if len(k) == 0:
+        return None
+    k = int(k[0])
+    if k == 0:
+        return float(f[0])
+    t = (m[k - 1] - level) / (m[k - 1] - m[k])
+    return float(f[k - 1] + t * (f[k] - f[k - 1]))
+
+
+def edge_width(centres, esf, reach_frac=0.5):
+    """10-90 % rise distance of a falling edge (inside level at negative
+    distance, outside level at positive distance)."""
+    far = np.abs(centres) >= reach_frac * np.abs(centres).max()
+    hi = esf[far & (centres < 0)].mean()
+    lo = esf[far & (centres > 0)].mean()
+    t = (esf - lo) / (hi - lo)
+    def cross(level):
+        k = np.nonzero(t < level)[0]
+        k = int(k[0])
+        return centres[k - 1] + (t[k - 1] - level) / (t[k - 1] - t[k]) * (centres[k] - centres[k - 1])
+    return float(cross(0.1) - cross(0.9))
+
+
+def slanted_edge(img, centre, angle, half, reach=20.0, bin_w=0.25, along_frac=0.6):
+    dist, along = face_coordinates(img.shape[0], centre, angle, half)
+    d, esf = edge_spread(img, dist, along, along_frac * half[1], reach, bin_w)
+    f, m = mtf_from_esf(esf, bin_w)
+    return {"mtf50": first_crossing(f, m, 0.5), "mtf10": first_crossing(f, m, 0.1),
+            "width_10_90": edge_width(d, esf)}
+
+
+def interior_mask(ell, n, margin=3.0, min_density=0.2, step=2):
+    """Voxels (every ``step``-th in each direction) whose true density is the
+    same at +-margin voxels along x, y and z and at least ``min_density`` in
+    magnitude.  Returns (slice tuple, boolean mask on that grid)."""
+    from synth import phantom
+    c = (n - 1) / 2.0
+    g = np.arange(0, n, step, dtype=np.float64) - c
+    z, y, x = np.meshgrid(g, g, g, indexing="ij")
+    d0 = phantom.density(ell, n, n, x, y, z)
+    same = np.abs(d0) >= min_density
+    for dx, dy, dz in ((margin, 0, 0), (-margin, 0, 0), (0, margin, 0), (0, -margin, 0),
+                       (0, 0, margin), (0, 0, -margin)):
+        same &= phantom.density(ell, n, n, x + dx, y + dy, z + dz) == d0
+    sl = (slice(0, n, step),) * 3
+    return sl, same
+
+
+def rel_rmse(a, b):
+    return float(np.sqrt(np.mean((a - b) ** 2) / np.mean(b ** 2)))
+
+
+def fit_costs(rows):
+    """Least-squares constants of Dec = C2 N^2 P 2^s and Rec = C1 N^3 P / 2^s
+    (each a one-parameter fit through the origin)."""
+    a1 = np.array([r["n"] ** 3 * r["p"] / 2 ** r["s"] for r in rows], dtype=np.float64)
+    a2 = np.array([r["n"] ** 2 * r["p"] * 2 ** r["s"] for r in rows], dtype=np.float64)
+    rec = np.array([r["reconstruct_ms"] for r in rows])
+    dec = np.array([r["decompose_ms"] for r in rows])
+    c1 = float(a1 @ rec / (a1 @ a1))
+    c2 = float(a2 @ dec / (a2 @ a2))
+    return c1, c2
+
+
+# ----------------------------------------------------------------- GPU runs
+
+def reconstruct(torch, pkg, proj, n, p, r, s, k=0, decim="triangle", reps=0):
+    """Volume (device tensor) and, with reps > 0, the median decomposition and
+    reconstruction kernel times (ms) over ``reps`` runs."""
+    with pkg.Plan(n, p, r, s=s, skip=k, decim=decim) as plan:
+        filt, ws, vol = plan.empty_filtered(), plan.empty_workspace(), plan.empty_volume()
+        plan.filter(proj, filt)
+        plan.decompose(filt, ws)
+        plan.reconstruct(filt, ws, vol)
+        times = None
+        if reps:
+            dec, rec = [], []
+            for _ in range(reps):
+                e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+                e[0].record()
+                plan.decompose(filt, ws)
+                e[1].record()
+                plan.reconstruct(filt, ws, vol)
+                e[2].record()
+                torch.cuda.synchronize()
+                dec.append(e[0].elapsed_time(e[1]))
+                rec.append(e[1].elapsed_time(e[2]))
+            times = (float(np.median(dec)), float(np.median(rec)))
+        torch.cuda.synchronize()
+        del filt, ws
+        return vol, times
+
+
+def combos(smax):
+    out = []
+    for s in range(1, smax + 1):
+        for k in range(0, min(2, s) + 1):
+            for decim in ("triangle", "cone"):
+                out.append((s, k, decim))
+    return out
+
+
+def quality_sweep(torch, pkg, n, p, r, smax):
+    from synth import phantom
+    ell = phantom.random_ellipsoids(20, 11)
+    proj = phantom.project(ell, n, p, r, device="cuda:0").contiguous()
+    box_half_norm, box_angle = 0.6, math.radians(5.0)
+    bx = phantom.box((0.0, 0.0, 0.0), (box_half_norm,) * 3, box_angle, 1.0)
+    bproj = phantom.project(bx, n, p, r, device="cuda:0").contiguous()
+    half_vox = (box_half_norm * n / 2.0,) * 2
+    mid = n // 2
+    log(f"[study] quality sweep N={n} P={p} R={r}: interior mask")
+    sl, mask = interior_mask(ell, n)
+    ref, _ = reconstruct(torch, pkg, proj, n, p, r, 0)
+    ref_np = ref.cpu().double().numpy()
+    ref_in = ref_np[sl][mask]
+    bref, _ = reconstruct(torch, pkg, bproj, n, p, r, 0)
+    edge_ref = slanted_edge(bref[mid].cpu().double().numpy(), (0.0, 0.0), box_angle, half_vox)
+    log(f"[study] direct FDK edge: {edge_ref}")
+    rows = []
+    for s, k, decim in combos(smax):
+        vol, _ = reconstruct(torch, pkg, proj, n, p, r, s, k, decim)
+        v = vol.cpu().double().numpy()
+        ratio = v[sl][mask] / ref_in
+        bvol, _ = reconstruct(torch, pkg, bproj, n, p, r, s, k, decim)
+        edge = slanted_edge(bvol[mid].cpu().double().numpy(), (0.0, 0.0), box_angle, half_vox)
+        row = {"s": s, "k": k, "d": 2 ** (s - k), "decim": decim,
+               "rel_rmse_vs_fdk": rel_rmse(v, ref_np),
+               "interior_ratio_mean": float(ratio.mean()), "interior_ratio_std": float(ratio.std()),
+               "interior_ratio_p01": float(np.percentile(ratio, 1)),
+               "interior_ratio_p99": float(np.percentile(ratio, 99)), **edge}
+        log(f"[study] s={s} k={k} {decim}: rel-RMSE {row['rel_rmse_vs_fdk']:.4f}, interior ratio "
+            f"{row['interior_ratio_mean']:.4f} +- {row['interior_ratio_std']:.4f}, MTF50 {edge['mtf50']:.3f} "
+            f"MTF10 {edge['mtf10']:.3f}, 10-90 {edge['width_10_90']:.2f}")
+        rows.append(row)
+        del vol, bvol
+    return {"n": n, "p": p, "r": r, "phantom": "20 random ellipsoids, seed 11, noise-free",
+            "edge_phantom": f"box, half size {box_half_norm} (normalised), rotated 5 degrees, face x' = +half",
+            "interior_voxels": int(mask.sum()), "fdk_edge": edge_ref, "rows": rows}
+
+
+def time_split(torch, pkg, sizes, smax, reps):
+    from synth import phantom
+    out = []
+    for n, p in sizes:
+        r = 4.0 * n
+        ell = phantom.random_ellipsoids(20, 3)
+        proj = phantom.project(ell, n, p, r, device="cuda:0").contiguous()
+        rows = []
+        for s in range(1, smax + 1):
+            _, (dec, rec) = reconstruct(torch, pkg, proj, n, p, r, s, 0, "triangle", reps)
+            rows.append({"n": n, "p": p, "s": s, "decompose_ms": dec, "reconstruct_ms": rec,
+                         "total_ms": dec + rec})
+            log(f"[study] N={n} P={p} s={s}: decompose {dec:.3f} ms, reconstruct {rec:.3f} ms")
+        c1, c2 = fit_costs(rows)
+        best = min(rows, key=lambda x: x["total_ms"])["s"]
+        s_model = 0.5 * math.log2(c1 * n / c2)
+        out.append({"n": n, "p": p, "r": r, "rows": rows, "c1_ms": c1, "c2_ms": c2,
+                    "s_opt_model": s_model, "s_opt_measured": best})
+        log(f"[study] N={n}: C1 {c1:.3e} ms, C2 {c2:.3e} ms, optimum s model {s_model:.2f}, measured {best}")
+        del proj
+        torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--quick", action="store_true", help="smaller sizes (a few seconds)")
+    ap.add_argument("--reps", type=int, default=5)
+    args = ap.parse_args()
+    import torch
+
+    import paper_1708_07515_amd as pkg
+
+    t0 = time.time()
+    if args.quick:
+        sweep = quality_sweep(torch, pkg, 96, 120, 384.0, 3)
+        split = time_split(torch, pkg, [(128, 180)], 3, 2)
+    else:
+        sweep = quality_sweep(torch, pkg, 256, 360, 1024.0, 5)
+        split = time_split(torch, pkg, [(256, 360), (512, 360), (1024, 720)], 5, args.reps)
+    print(json.dumps({"study": "FDK-OD quality and cost on one MI355X", "data": "synthetic",
+                      "quality": sweep, "time_split": split, "seconds": round(time.time() - t0, 1)}),
+          flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,5 +1,5 @@
-"""Seeded synthetic inputs: random-ellipsoid phantoms and their exact cone-beam
-line integrals.
+"""Seeded synthetic inputs: random-ellipsoid and box phantoms and their exact
+cone-beam line integrals.
 
 This module only makes inputs.  It holds none of the reconstruction method's
 arithmetic and is imported by the tests and the benchmark, never by the
@@ -12,9 +12,12 @@ Geometry (the same conventions as the reconstruction): voxel units; source at
 + b (0, 0, 1) on a virtual detector through the axis; pixel (u, v) of
 projection p sits at a = u - (N-1)/2, b = v - (N-1)/2, beta_p = 2 pi p / P.
 Ellipsoids are given in normalised units, 1.0 = N/2 voxels, axis aligned, and
-densities add where they overlap.
+densities add where they overlap.  Boxes (the slanted-edge phantom of the
+resolution study, Sec. 4) are given in the same units and may be rotated about
+the z axis.
 """
 
+import math
 from dataclasses import dataclass
 
 import numpy as np
@@ -43,6 +46,20 @@ def random_ellipsoids(count, seed, centre_range=0.6, axis_range=(0.05, 0.4),
     return Ellipsoids(c, a, d)
 
 
+@dataclass
+class Boxes:
+    centres: np.ndarray     # [M, 3] normalised (x, y, z)
+    half: np.ndarray        # [M, 3] normalised half sizes along the box's own axes
+    angle: np.ndarray       # [M] rotation about z (radians): box axis x is (cos, sin, 0)
+    density: np.ndarray     # [M]
+
+
+def box(centre, half, angle=0.0, density=1.0):
+    """A single box (normalised units) rotated by ``angle`` about z."""
+    return Boxes(np.array([centre], dtype=np.float64), np.array([half], dtype=np.float64),
+                 np.array([angle], dtype=np.float64), np.array([density], dtype=np.float64))
+
+
 def sphere(centre, radius, density=1.0):
     """A single sphere (normalised units), for closed-form checks."""
     return Ellipsoids(np.array([centre], dtype=np.float64),
@@ -65,6 +82,36 @@ def _chords(src, dirn, ell, scale, device):
         disc = b * b - a2 * cc
         chord = 2.0 * torch.sqrt(torch.clamp(disc, min=0.0)) / a2
         out += float(ell.density[e]) * chord
+    return out
+
+
+def _box_chords(src, dirn, boxes, scale, device):
+    """Sum over boxes of density x chord length (slab intersection: the ray
+    is inside the box between the largest entry and the smallest exit of the
+    three pairs of parallel faces)."""
+    out = torch.zeros(dirn.shape[:-1], dtype=torch.float64, device=device)
+    for e in range(len(boxes.density)):
+        c = torch.tensor(boxes.centres[e] * scale, dtype=torch.float64, device=device)
+        h = boxes.half[e] * scale
+        ca, sa = math.cos(boxes.angle[e]), math.sin(boxes.angle[e])
+        axes = ((ca, sa, 0.0), (-sa, ca, 0.0), (0.0, 0.0, 1.0))
+        o = src - c
+        t_in = torch.full(out.shape, -math.inf, dtype=torch.float64, device=device)
+        t_out = torch.full(out.shape, math.inf, dtype=torch.float64, device=device)
+        for k in range(3):
+            ax = torch.tensor(axes[k], dtype=torch.float64, device=device)
+            ok = (o * ax).sum(-1)                 # source coordinate along the axis
+            dk = (dirn * ax).sum(-1)
+            par = dk.abs() < 1e-15                # parallel to the faces: inside or never
+            safe = torch.where(par, torch.ones_like(dk), dk)
+            t1 = (-h[k] - ok) / safe
+            t2 = (h[k] - ok) / safe
+            inside = ok.abs() <= h[k]
+            lo = torch.where(par, torch.where(inside, -math.inf, math.inf), torch.minimum(t1, t2))
+            hi = torch.where(par, torch.where(inside, math.inf, -math.inf), torch.maximum(t1, t2))
+            t_in = torch.maximum(t_in, lo)
+            t_out = torch.minimum(t_out, hi)
+        out += float(boxes.density[e]) * torch.clamp(t_out - t_in, min=0.0)
     return out
 
 
@@ -93,7 +140,8 @@ def project(ell, n, p, r, device="cpu", out_dtype=torch.float32, angles=None,
         q = torch.stack([-aa[None] * sb, aa[None] * cb, bb[None].expand(len(idx), -1, -1)], dim=-1)
         d = q - src
         d = d / torch.linalg.norm(d, dim=-1, keepdim=True)
-        out[t0:t0 + len(idx)] = _chords(src, d, ell, scale, device).to(out_dtype)
+        chords = _box_chords if isinstance(ell, Boxes) else _chords
+        out[t0:t0 + len(idx)] = chords(src, d, ell, scale, device).to(out_dtype)
     return out
 
 
@@ -113,6 +161,16 @@ def density(ell, n, nz, x, y, z):
     """True phantom density at voxel coordinates (x, y, z) (numpy arrays)."""
     scale = n / 2.0
     out = np.zeros(np.broadcast(x, y, z).shape)
+    if isinstance(ell, Boxes):
+        for e in range(len(ell.density)):
+            c = ell.centres[e] * scale
+            h = ell.half[e] * scale
+            ca, sa = np.cos(ell.angle[e]), np.sin(ell.angle[e])
+            lx = (x - c[0]) * ca + (y - c[1]) * sa
+            ly = -(x - c[0]) * sa + (y - c[1]) * ca
+            inside = (np.abs(lx) <= h[0]) & (np.abs(ly) <= h[1]) & (np.abs(z - c[2]) <= h[2])
+            out += ell.density[e] * inside
+        return out
     for e in range(len(ell.density)):
         c = ell.centres[e] * scale
         ax = ell.axes[e] * scale
