@@ -36,7 +36,10 @@ Pinned by (tests/test_oracle_fdkod.py): s = 0 reproduces direct FDK; D = 1 is
 the identity; triangle weights equal the [1,2,1]/4 cascade; brute-force vertex
 containment of every voxel of every square and every bilinear footprint;
 linearity; interior means and centroids of analytic spheres; the update and
-crop counters of eq. (6) and eq. (7).
+crop counters of eq. (6) and eq. (7).  The quality knobs (windowed-sinc
+decimation, cubic shift) are pinned in tests/test_oracle_knobs.py against
+scipy's windowed-sinc design, the identity at D = 1, exact reproduction of
+quadratics and the Catmull-Rom Hermite form.
 """
 
 from dataclasses import dataclass
@@ -142,6 +145,57 @@ def triangle_weights(p, pd):
     return w / w.sum(axis=1, keepdims=True)
 
 
+# ------------------------------------------------------------ quality knobs
+#
+# Two extensions beyond the paper, cheaper than a learned decimation filter:
+# Sec. 2.1 leaves the low-pass kernel open ("filters with small kernel"), and
+# the discussion of interpolation counts in Sec. 2.2 notes that a more precise
+# interpolation reduces smoothing.
+#
+# * windowed-sinc decimation: the ideal low-pass for the decimated rate (cut
+#   off at half a decimated step's frequency) truncated to K decimated steps
+#   by a Hann window, normalised per window like the triangle;
+# * cubic shift: Keys' cubic convolution kernel (a = -1/2, Catmull-Rom) in u
+#   for the crop and shift of step 3.
+
+def sinc_weights(p, pd, taps):
+    """w[m, p] proportional to sinc(t) (1 + cos(2 pi t / K)) / 2 for |t| < K / 2,
+    zero beyond, with t the circular distance between beta_p and beta'_m in
+    decimated steps (|p P' - m P| / P, as in triangle_weights) and K = taps
+    (even); normalised so every row sums to one.  K = 2 has the triangle's
+    support."""
+    if taps < 2 or taps % 2:
+        raise ValueError("taps must be an even number >= 2")
+    pp = np.arange(p, dtype=np.int64)[None, :]
+    mm = np.arange(pd, dtype=np.int64)[:, None]
+    period = p * pd
+    e = np.abs(pp * pd - mm * p) % period
+    e = np.minimum(e, period - e)
+    t = e / p
+    inside = e * 2 < taps * p                      # |t| < K / 2, decided in integers
+    w = np.where(inside, np.sinc(t) * 0.5 * (1.0 + np.cos(2.0 * np.pi * t / taps)), 0.0)
+    return w / w.sum(axis=1, keepdims=True)
+
+
+def decimation_weights(p, pd, window="triangle", taps=2):
+    if window == "triangle":
+        return triangle_weights(p, pd)
+    if window == "sinc":
+        return sinc_weights(p, pd, taps)
+    raise ValueError(f"unknown decimation window {window!r}")
+
+
+def keys_cubic(d):
+    """Keys' cubic convolution kernel with a = -1/2 at distance d (samples):
+    (a+2)|d|^3 - (a+3)|d|^2 + 1 on [0, 1], a|d|^3 - 5a|d|^2 + 8a|d| - 4a on
+    (1, 2), zero beyond."""
+    d = np.abs(np.asarray(d, dtype=np.float64))
+    a = -0.5
+    near = (a + 2.0) * d ** 3 - (a + 3.0) * d ** 2 + 1.0
+    far = a * d ** 3 - 5.0 * a * d ** 2 + 8.0 * a * d - 4.0 * a
+    return np.where(d <= 1.0, near, np.where(d < 2.0, far, 0.0))
+
+
 def cascade121_weights(p, stages):
     """Decimation by 2^stages built as ``stages`` rounds of circular [1, 2, 1]/4
     smoothing followed by keeping the even samples (a half-band decimator).
@@ -163,9 +217,20 @@ def cascade121_weights(p, stages):
     return mat
 
 
-def crop_shift(frows, sq, betas, r, n):
+def u_taps(fu, interp):
+    """Offsets from floor(u) and weights of the shift's interpolation in u:
+    linear (Sec. 2.1), or Keys' cubic convolution (see keys_cubic)."""
+    if interp == "linear":
+        return ((0, 1.0 - fu), (1, fu))
+    if interp == "cubic":
+        return tuple((d, keys_cubic(fu - d)) for d in (-1, 0, 1, 2))
+    raise ValueError(f"unknown interpolation {interp!r}")
+
+
+def crop_shift(frows, sq, betas, r, n, interp="linear"):
     """Step 3: S[p, k, j] = Lin_u(q[p, rows[k], :], a_c(beta_p) + u0 + j), zero
-    outside the detector, for every filtered row k."""
+    outside the detector, for every filtered row k (``interp="cubic"``: Keys'
+    cubic kernel instead of the linear one)."""
     ac = centre_track(sq, betas, r)
     j = np.arange(sq.width, dtype=np.float64)
     nrow = len(frows.rows)
@@ -175,7 +240,7 @@ def crop_shift(frows, sq, betas, r, n):
         iu = np.floor(u).astype(np.int64)
         fu = u - iu
         row = frows.data[p]                            # [nrow, N]
-        for d, w in ((0, 1.0 - fu), (1, fu)):
+        for d, w in u_taps(fu, interp):
             ui = iu + d
             ok = (ui >= 0) & (ui < n)
             out[p] += np.where(ok[None, :], w[None, :] * row[:, np.clip(ui, 0, n - 1)], 0.0)
@@ -215,13 +280,13 @@ def _square_points(sq, n, nz, slices):
     return np.meshgrid(zs, ys, xs, indexing="ij")
 
 
-def square_pipeline(frows, r, sq, betas, betas_dec, weights, x, y, z, store=None):
+def square_pipeline(frows, r, sq, betas, betas_dec, weights, x, y, z, store=None, interp="linear"):
     """Steps 3-5 for one square at the voxel coordinates (x, y, z) that lie
     inside it, from the filtered rows ``frows`` (which must hold every row the
     points touch).  ``store`` optionally rounds the decimated data to a storage
     type (see oracle.storage); the filtered rows are rounded by the caller."""
     n = frows.data.shape[-1]
-    s_sub = crop_shift(frows, sq, betas, r, n)
+    s_sub = crop_shift(frows, sq, betas, r, n, interp)
     y_sub = decimate(s_sub, weights)
     if store is not None:
         y_sub = store(y_sub)
@@ -248,20 +313,22 @@ def _rows_subset(frows, x, y, z, betas_dec, r):
     return sub
 
 
-def fdkod(proj, r, s, k=0, slices=None, nz=None, store=None):
-    """FDK-OD of the listed slices (all by default).  Returns [S, N, N]."""
+def fdkod(proj, r, s, k=0, slices=None, nz=None, store=None, window="triangle", taps=2, interp="linear"):
+    """FDK-OD of the listed slices (all by default).  Returns [S, N, N].
+    ``window``, ``taps`` and ``interp`` select the decimation window and the
+    shift's interpolation (the defaults are the paper's method)."""
     p_count, nv, n = proj.shape
     nz = n if nz is None else nz
     slices = np.arange(nz) if slices is None else np.asarray(slices)
     sqs, betas, betas_dec = plan(n, p_count, r, s, k)
-    weights = triangle_weights(p_count, len(betas_dec))
+    weights = decimation_weights(p_count, len(betas_dec), window, taps)
     pts = [tuple(reversed(_square_points(sq, n, nz, slices))) for sq in sqs]
     frows = _filtered(proj, r, betas_dec, pts, store)
     out = np.zeros((len(slices), n, n))
     for sq, (x, y, z) in zip(sqs, pts):
         sub = _rows_subset(frows, x, y, z, betas_dec, r)
         out[:, sq.y0:sq.y1, sq.x0:sq.x1] = square_pipeline(
-            sub, r, sq, betas, betas_dec, weights, x, y, z, store)
+            sub, r, sq, betas, betas_dec, weights, x, y, z, store, interp)
     return out
 
 
@@ -285,9 +352,9 @@ def cone_row_scale(sq, beta, r):
     return r / g.depth(sq.xc, sq.yc, beta, r)
 
 
-def crop_shift_cone(frows, sq, betas, r, n):
+def crop_shift_cone(frows, sq, betas, r, n, interp="linear"):
     """Cone-corrected step 3 for every warped row v' = 0..N-1: S[p, v', j]
-    (frows must hold every detector row)."""
+    (frows must hold every detector row); linear in v, ``interp`` in u."""
     if len(frows.rows) != frows.nv:
         raise ValueError("the cone-corrected crop needs every filtered row")
     cv = g.centre(n)
@@ -297,8 +364,31 @@ def crop_shift_cone(frows, sq, betas, r, n):
     out = np.zeros((len(betas), frows.nv, sq.width))
     for p, beta in enumerate(betas):
         rows = (vw - cv) * cone_row_scale(sq, beta, r) + cv
-        out[p] = fdk_mod.bilinear(frows.data[p], frows.slot, frows.nv, rows[:, None],
-                                  (ac[p] + sq.u0 + j)[None, :])
+        out[p] = sample_vu(frows.data[p], frows.slot, frows.nv, rows[:, None],
+                           (ac[p] + sq.u0 + j)[None, :], interp)
+    return out
+
+
+def sample_vu(img, slot, nv, v, u, interp="linear"):
+    """img sampled at index coordinates (v, u): linear in v, ``interp`` in u,
+    zero outside [0, nv) x [0, nu) (bilinear for interp="linear")."""
+    if interp == "linear":
+        return fdk_mod.bilinear(img, slot, nv, v, u)
+    nu = img.shape[-1]
+    v = np.asarray(v, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    iv = np.floor(v).astype(np.int64)
+    iu = np.floor(u).astype(np.int64)
+    fv = v - iv
+    out = np.zeros(np.broadcast(v, u).shape)
+    for dv, wv in ((0, 1.0 - fv), (1, fv)):
+        vi = iv + dv
+        vin = (vi >= 0) & (vi < nv)
+        kk = slot[np.clip(vi, 0, nv - 1)]
+        for du, wu in u_taps(u - iu, interp):
+            ui = iu + du
+            ok = vin & (ui >= 0) & (ui < nu)
+            out += np.where(ok, wv * wu * img[np.clip(kk, 0, None), np.clip(ui, 0, nu - 1)], 0.0)
     return out
 
 
@@ -325,21 +415,22 @@ def backproject_square_cone(y_sub, nv, sq, betas_dec, r, n, x, y, z):
     return (np.pi / pd) * f
 
 
-def fdkod_cone(proj, r, s, k=0, slices=None, nz=None, store=None):
+def fdkod_cone(proj, r, s, k=0, slices=None, nz=None, store=None, window="triangle", taps=2,
+               interp="linear"):
     """FDK-OD with the cone-corrected decimation, listed slices (all by
     default).  Filters every detector row.  Returns [S, N, N]."""
     p_count, nv, n = proj.shape
     nz = n if nz is None else nz
     slices = np.arange(nz) if slices is None else np.asarray(slices)
     sqs, betas, betas_dec = plan(n, p_count, r, s, k)
-    weights = triangle_weights(p_count, len(betas_dec))
+    weights = decimation_weights(p_count, len(betas_dec), window, taps)
     frows = fdk_mod.filter_rows(proj, r, np.arange(nv))
     if store is not None:
         frows.data = store(frows.data)
     out = np.zeros((len(slices), n, n))
     for sq in sqs:
         z, y, x = _square_points(sq, n, nz, slices)
-        y_sub = decimate(crop_shift_cone(frows, sq, betas, r, n), weights)
+        y_sub = decimate(crop_shift_cone(frows, sq, betas, r, n, interp), weights)
         if store is not None:
             y_sub = store(y_sub)
         out[:, sq.y0:sq.y1, sq.x0:sq.x1] = backproject_square_cone(y_sub, nv, sq, betas_dec, r, n, x, y, z)
@@ -354,13 +445,13 @@ def square_of(n, s, i, j):
     return by * (2 ** s) + bx
 
 
-def fdkod_points(proj, r, s, k, idx, nz=None, store=None):
+def fdkod_points(proj, r, s, k, idx, nz=None, store=None, window="triangle", taps=2, interp="linear"):
     """FDK-OD at voxel indices ``idx`` ([K, 3] array of (l, j, i))."""
     p_count, nv, n = proj.shape
     nz = n if nz is None else nz
     idx = np.asarray(idx)
     sqs, betas, betas_dec = plan(n, p_count, r, s, k)
-    weights = triangle_weights(p_count, len(betas_dec))
+    weights = decimation_weights(p_count, len(betas_dec), window, taps)
     qid = np.array([square_of(n, s, i, j) for (_, j, i) in idx])
     c, cz = g.centre(n), g.centre(nz)
     groups = []
@@ -371,7 +462,7 @@ def fdkod_points(proj, r, s, k, idx, nz=None, store=None):
     out = np.zeros(len(idx))
     for q, sel, (x, y, z) in groups:
         sub = _rows_subset(frows, x, y, z, betas_dec, r)
-        out[sel] = square_pipeline(sub, r, sqs[q], betas, betas_dec, weights, x, y, z, store)
+        out[sel] = square_pipeline(sub, r, sqs[q], betas, betas_dec, weights, x, y, z, store, interp)
     return out
 
 
