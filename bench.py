@@ -201,7 +201,7 @@ def run_cone(torch, pkg, wl, s, k, store, res, steps):
         return None
     n, p, r, nz = wl.n, wl.p, wl.r, wl.nzv
     proj, filt, vol = res["proj"], res["filt"], res["vol"]
-    cplan = pkg.Plan(n, p, r, s=s, skip=k, nz=nz, store=store, decim="cone")
+    cplan = pkg.Plan(n, p, r, s=s, skip=k, nz=nz, store=store, rows="cone")
     cws = cplan.empty_workspace()
     cvol = cplan.empty_volume()
     stages = [("bounds", lambda: cplan.bounds()),

@@ -68,19 +68,36 @@ typedef enum {
 
 typedef enum { FDKOD_F32 = 0, FDKOD_F16 = 1, FDKOD_BF16 = 2 } fdkod_dtype;
 
-/* Decomposition of the filtered sinogram (Sec. 2.1, step 3):
- *  TRIANGLE  crop, shift and triangle decimation of each detector row, as in
+/* Window of the angular decimation (Sec. 2.1, step 4):
+ *  TRIANGLE  triangle of half-width one decimated step (the library's reading
+ *            of the paper's unspecified small low-pass kernel); taps = 2.
+ *  SINC      windowed sinc (an extension, a cheaper alternative to a learned
+ *            filter): the ideal low-pass cut off at the decimated rate's
+ *            Nyquist frequency, times a Hann window over `taps` decimated
+ *            steps (even, 2..6; 0 selects 4), normalised per window; each
+ *            projection feeds up to `taps` windows.  Needs P >= taps * D. */
+typedef enum { FDKOD_DECIM_TRIANGLE = 0, FDKOD_DECIM_SINC = 1 } fdkod_decim;
+
+/* Rows of the decomposed data:
+ *  DETECTOR  every detector row is cropped and decimated on its own, as in
  *            Sec. 2.1; the backprojection reads row z R / D(beta) + c_v (eq. (9)).
  *  CONE      cone-corrected rows (an extension beyond the paper): before the
  *            decimation, row v' of square q at angle beta is resampled from
- *            detector row (v' - c_v) R / D_c(beta) + c_v (bilinear; rows outside
- *            the detector read zero), D_c the depth of the square's centre, so
- *            a voxel's row coordinate z D_c / D + c_v varies little with beta
- *            and the angular decimation averages less of the z direction.
- *            Needs s > 0 to differ from TRIANGLE (s = 0 gives the same result);
- *            not available to the learned decimation, the slab mode and
- *            batches (FDKOD_E_UNSUPPORTED). */
-typedef enum { FDKOD_DECIM_TRIANGLE = 0, FDKOD_DECIM_CONE = 1 } fdkod_decim;
+ *            detector row (v' - c_v) R / D_c(beta) + c_v (linear in v; rows
+ *            outside the detector read zero), D_c the depth of the square's
+ *            centre, so a voxel's row coordinate z D_c / D + c_v varies little
+ *            with beta and the angular decimation averages less of the z
+ *            direction.  With s = 0 it equals DETECTOR.  Not available to the
+ *            learned decimation, the slab mode and batches (FDKOD_E_UNSUPPORTED). */
+typedef enum { FDKOD_ROWS_DETECTOR = 0, FDKOD_ROWS_CONE = 1 } fdkod_rows;
+
+/* Interpolation of the crop's shift along u (Sec. 2.1, step 3):
+ *  LINEAR  as in the paper;
+ *  CUBIC   Keys' cubic convolution kernel with a = -1/2 (Catmull-Rom), four
+ *          samples per cropped value, zero outside the detector (an
+ *          extension: Sec. 2.2 notes that a more precise interpolation
+ *          reduces smoothing). */
+typedef enum { FDKOD_INTERP_LINEAR = 0, FDKOD_INTERP_CUBIC = 1 } fdkod_interp;
 
 /* Problem statement, after Sec. 2.1: N, P, R, s, and the skipped
  * decimation stages k of Sec. 2.2 (D = 2^(s-k), P' = ceil(P / D)). */
@@ -92,7 +109,10 @@ typedef struct {
     int32_t s;      /* decomposition stages: 4^s squares; 2^s <= N; s = 0 is direct FDK */
     int32_t skip;   /* skipped decimation stages k, 0 <= k <= s */
     int32_t store;  /* fdkod_dtype of the filtered and decimated sinograms */
-    int32_t decim;  /* fdkod_decim */
+    int32_t decim;  /* fdkod_decim: window of the angular decimation */
+    int32_t taps;   /* SINC: window length in decimated steps (2, 4, 6; 0 = 4); TRIANGLE: 0 or 2 */
+    int32_t rows;   /* fdkod_rows */
+    int32_t interp; /* fdkod_interp */
 } fdkod_params;
 
 /* Sizes and derived quantities of a plan (filled by fdkod_plan_info). */

@@ -29,7 +29,8 @@ class FdkodError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nz", ctypes.c_int32), ("p", ctypes.c_int32),
                 ("r", ctypes.c_double), ("s", ctypes.c_int32), ("skip", ctypes.c_int32),
-                ("store", ctypes.c_int32), ("decim", ctypes.c_int32)]
+                ("store", ctypes.c_int32), ("decim", ctypes.c_int32), ("taps", ctypes.c_int32),
+                ("rows", ctypes.c_int32), ("interp", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -128,20 +129,25 @@ def _check(status):
         raise FdkodError(status, lib.fdkod_last_error().decode())
 
 
-DECIM_TYPES = {"triangle": 0, "cone": 1}
+DECIM_TYPES = {"triangle": 0, "sinc": 1}      # window of the angular decimation
+ROWS_TYPES = {"detector": 0, "cone": 1}       # plain or cone-corrected rows
+INTERP_TYPES = {"linear": 0, "cubic": 1}      # interpolation of the crop's shift
 
 
-def _params(n, p, r, s=0, skip=0, nz=0, store="f32", decim="triangle"):
-    if isinstance(store, str):
-        store = STORE_TYPES[store]
-    if isinstance(decim, str):
-        decim = DECIM_TYPES[decim]
-    return Params(int(n), int(nz), int(p), float(r), int(s), int(skip), int(store), int(decim))
+def _enum(value, table):
+    return table[value] if isinstance(value, str) else int(value)
 
 
-def validate(n, p, r, s=0, skip=0, nz=0, store="f32", decim="triangle"):
+def _params(n, p, r, s=0, skip=0, nz=0, store="f32", decim="triangle", taps=0, rows="detector",
+            interp="linear"):
+    return Params(int(n), int(nz), int(p), float(r), int(s), int(skip), _enum(store, STORE_TYPES),
+                  _enum(decim, DECIM_TYPES), int(taps), _enum(rows, ROWS_TYPES), _enum(interp, INTERP_TYPES))
+
+
+def validate(n, p, r, s=0, skip=0, nz=0, store="f32", decim="triangle", taps=0, rows="detector",
+             interp="linear"):
     """Host-only parameter check (no device needed)."""
-    prm = _params(n, p, r, s, skip, nz, store, decim)
+    prm = _params(n, p, r, s, skip, nz, store, decim, taps, rows, interp)
     _check(load_library().fdkod_validate(ctypes.byref(prm)))
 
 
@@ -190,10 +196,14 @@ def _stream_ptr(stream):
 class Plan:
     """An FDK-OD plan: geometry tables on one device, sizes of the buffers."""
 
-    def __init__(self, n, p, r, s=0, skip=0, nz=0, store="f32", device=0, decim="triangle", _handle=None):
+    def __init__(self, n, p, r, s=0, skip=0, nz=0, store="f32", device=0, decim="triangle", taps=0,
+                 rows="detector", interp="linear", _handle=None):
+        """decim: "triangle" or "sinc" (taps 2, 4 or 6; 0 = 4); rows: "detector"
+        or "cone" (cone-corrected); interp: "linear" or "cubic" shift."""
         self._lib = load_library()
-        self.params = _params(n, p, r, s, skip, nz, store, decim)
-        self.decim = self.params.decim
+        self.params = _params(n, p, r, s, skip, nz, store, decim, taps, rows, interp)
+        self.decim, self.taps = self.params.decim, self.params.taps
+        self.rows, self.interp = self.params.rows, self.params.interp
         self.n, self.p, self.r, self.s, self.skip = int(n), int(p), float(r), int(s), int(skip)
         self.nz = int(nz) or int(n)
         self.store = self.params.store
@@ -482,7 +492,8 @@ class Batch:
         self._lib = load_library()
         self.device = int(device)
         prms = [_params(v["n"], v["p"], v["r"], v.get("s", 0), v.get("skip", 0), v.get("nz", 0), store,
-                        v.get("decim", "triangle"))
+                        v.get("decim", "triangle"), v.get("taps", 0), v.get("rows", "detector"),
+                        v.get("interp", "linear"))
                 for v in volumes]
         arr = (Params * len(prms))(*prms)
         h = ctypes.c_void_p()

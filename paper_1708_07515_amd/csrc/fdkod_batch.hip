@@ -217,8 +217,9 @@ fdkod_status fdkod_batch_create(const fdkod_params* prms, int32_t count, int dev
         fdkod_status st = fdkod_validate(&prms[i]);
         if (st != FDKOD_OK) return st;
         if (prms[i].store != prms[0].store) return fail(FDKOD_E_ARG, "all volumes of a batch share the store type");
-        if (prms[i].decim != FDKOD_DECIM_TRIANGLE && prms[i].s > 0)
-            return fail(FDKOD_E_UNSUPPORTED, "batches use the triangle decimation");
+        if (prms[i].s > 0 && (prms[i].decim != FDKOD_DECIM_TRIANGLE || prms[i].rows != FDKOD_ROWS_DETECTOR ||
+                              prms[i].interp != FDKOD_INTERP_LINEAR))
+            return fail(FDKOD_E_UNSUPPORTED, "batches use the triangle decimation on detector rows, linear shift");
     }
     fdkod_batch_t b = new fdkod_batch_s();
     b->device = device;

@@ -55,6 +55,13 @@ int64_t floordiv(int64_t a, int64_t b) {
 
 int64_t ceildiv(int64_t a, int64_t b) { return -floordiv(-a, b); }
 
+// Windows a projection can feed: the decimation window's length in decimated
+// steps (2 for the triangle; the windowed sinc's taps, 4 by default).
+int window_taps(const fdkod_params& q) {
+    if (q.decim == FDKOD_DECIM_SINC) return q.taps ? q.taps : 4;
+    return 2;
+}
+
 // Near-equal contiguous blocks of [0, n), larger blocks first.
 std::vector<std::pair<int, int>> blocks(int n, int parts) {
     std::vector<std::pair<int, int>> out;
@@ -71,23 +78,48 @@ std::vector<std::pair<int, int>> blocks(int n, int parts) {
 // p_ext = lo(0) .. P - 1 that feeds the triangle windows of the decimated
 // angles in order.  Window m holds the p_ext with |p_ext P' - m P| < P and
 // weights (P - |p_ext P' - m P|) / sum; integers keep the support exact.
-std::vector<DecimStep> build_schedule(int P, int pd) {
-    auto lo = [&](int64_t m) { return floordiv(m * P - P, pd) + 1; };
-    auto hi = [&](int64_t m) { return ceildiv(m * P + P, pd) - 1; };
-    auto weight = [&](int64_t m, int64_t pe) { return (int64_t)P - std::llabs(pe * pd - m * P); };
+// Weights of the decimation windows in walk order.  Window m covers the
+// (unwrapped) projections pe with |pe P' - m P| < (taps / 2) P, i.e. within
+// taps / 2 decimated steps of beta'_m; the walk runs from window 0's first
+// projection to window P'-1's last, and at every projection the windows
+// cur .. cur + taps - 1 are the only ones open (window cur + taps opens after
+// window cur closes).  Step weights for windows cur and cur + 1 go in the
+// step itself, those of windows cur + 2 .. into `wext` (taps - 2 per step).
+// Triangle: P - |pe P' - m P| (integers, exact); windowed sinc:
+// sinc(t) (1 + cos(2 pi t / taps)) / 2 with t = |pe P' - m P| / P.  Both are
+// normalised per window in FP64.
+struct Schedule {
+    std::vector<DecimStep> steps;
+    std::vector<float> wext;
+};
+
+Schedule build_schedule(int P, int pd, int taps, bool sinc) {
+    const int64_t h = taps / 2;
+    auto lo = [&](int64_t m) { return floordiv(m * P - h * P, pd) + 1; };
+    auto hi = [&](int64_t m) { return ceildiv(m * P + h * P, pd) - 1; };
+    auto weight = [&](int64_t m, int64_t pe) -> double {
+        const int64_t e = std::llabs(pe * pd - m * P);
+        if (!sinc) return (double)((int64_t)P - e);
+        const double t = (double)e / (double)P;
+        const double sc = e == 0 ? 1.0 : std::sin(M_PI * t) / (M_PI * t);
+        return sc * 0.5 * (1.0 + std::cos(2.0 * M_PI * t / (double)taps));
+    };
     std::vector<double> sum(pd, 0.0);
     for (int m = 0; m < pd; ++m)
-        for (int64_t pe = lo(m); pe <= hi(m); ++pe) sum[m] += (double)weight(m, pe);
-    std::vector<DecimStep> out;
+        for (int64_t pe = lo(m); pe <= hi(m); ++pe) sum[m] += weight(m, pe);
+    auto w_of = [&](int64_t m, int64_t pe) -> float {
+        return (m < pd && pe >= lo(m) && pe <= hi(m)) ? (float)(weight(m, pe) / sum[m]) : 0.0f;
+    };
+    Schedule out;
     int cur = 0;
     for (int64_t pe = lo(0); pe <= hi(pd - 1); ++pe) {
         DecimStep st;
         st.p = (int)(((pe % P) + P) % P);
-        st.w0 = (pe >= lo(cur) && pe <= hi(cur)) ? (float)(weight(cur, pe) / sum[cur]) : 0.0f;
-        st.w1 = (cur + 1 < pd && pe >= lo(cur + 1) && pe <= hi(cur + 1))
-                    ? (float)(weight(cur + 1, pe) / sum[cur + 1]) : 0.0f;
+        st.w0 = w_of(cur, pe);
+        st.w1 = w_of(cur + 1, pe);
+        for (int i = 2; i < taps; ++i) out.wext.push_back(w_of(cur + i, pe));
         st.emit = (pe == hi(cur)) ? 1 : 0;
-        out.push_back(st);
+        out.steps.push_back(st);
         if (st.emit) ++cur;
     }
     return out;
@@ -238,7 +270,10 @@ DecimVol decim_args_band(const fdkod_plan_s* pl, const void* filt, void* ws, int
     a.crop = pl->d_crop;
     a.sched = pl->d_sched;
     a.rscale = pl->d_rscale;
+    a.wext = pl->d_wext;
     a.nsched = pl->nsched;
+    a.nw = pl->nw;
+    a.cubic = pl->cubic;
     a.cone = pl->cone;
     a.cv = (float)((pl->n - 1) / 2.0);
     a.n = pl->n;
@@ -316,7 +351,9 @@ std::string tune_key(const fdkod_plan_s* pl) {
     std::ostringstream k;
     k << "gfx950 n=" << pl->n << " nz=" << pl->nz << " p=" << pl->p << " r=" << pl->r
       << " s=" << pl->s << " k=" << pl->k << " store=" << pl->store;
-    if (pl->cone) k << " decim=cone";
+    if (pl->cone) k << " rows=cone";
+    if (pl->sinc) k << " decim=sinc" << pl->nw;
+    if (pl->cubic) k << " interp=cubic";
     return k.str();
 }
 
@@ -401,8 +438,15 @@ fdkod_status fdkod_validate(const fdkod_params* prm) {
     if (q.nz < 0 || q.nz > 65536) return fail(FDKOD_E_ARG, "nz must be in [0, 65536]");
     if (q.p < 1 || q.p > 65536) return fail(FDKOD_E_ARG, "p must be in [1, 65536]");
     if (q.store < FDKOD_F32 || q.store > FDKOD_BF16) return fail(FDKOD_E_ARG, "unknown store type");
-    if (q.decim != FDKOD_DECIM_TRIANGLE && q.decim != FDKOD_DECIM_CONE)
-        return fail(FDKOD_E_ARG, "unknown decimation");
+    if (q.decim != FDKOD_DECIM_TRIANGLE && q.decim != FDKOD_DECIM_SINC)
+        return fail(FDKOD_E_ARG, "unknown decimation window");
+    if (q.decim == FDKOD_DECIM_TRIANGLE && q.taps != 0 && q.taps != 2)
+        return fail(FDKOD_E_ARG, "the triangle window has 2 taps");
+    if (q.decim == FDKOD_DECIM_SINC && !(q.taps == 0 || q.taps == 2 || q.taps == 4 || q.taps == 6))
+        return fail(FDKOD_E_ARG, "windowed-sinc taps must be 2, 4 or 6");
+    if (q.rows != FDKOD_ROWS_DETECTOR && q.rows != FDKOD_ROWS_CONE) return fail(FDKOD_E_ARG, "unknown rows");
+    if (q.interp != FDKOD_INTERP_LINEAR && q.interp != FDKOD_INTERP_CUBIC)
+        return fail(FDKOD_E_ARG, "unknown interpolation");
     if (!std::isfinite(q.r)) return fail(FDKOD_E_GEOMETRY, "R is not finite");
     if (q.s < 0 || q.s > 12) return fail(FDKOD_E_GEOMETRY, "s must be in [0, 12]");
     if ((1 << q.s) > q.n) return fail(FDKOD_E_GEOMETRY, "2^s exceeds N");
@@ -411,6 +455,8 @@ fdkod_status fdkod_validate(const fdkod_params* prm) {
         return fail(FDKOD_E_GEOMETRY, "R must exceed (N-1)/sqrt(2) (eq. (1) denominator)");
     const int d = 1 << (q.s - q.skip);
     if (d > 1 && q.p < 2 * d) return fail(FDKOD_E_GEOMETRY, "decimation needs P >= 2 D");
+    if (d > 1 && q.p < window_taps(q) * d)
+        return fail(FDKOD_E_GEOMETRY, "the windowed sinc needs P >= taps * D");
     return FDKOD_OK;
 }
 
@@ -444,7 +490,10 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
     pl->pd = (int)ceildiv(pl->p, pl->d);
     pl->nsq = 1 << (2 * pl->s);
     pl->store = prm->store;
-    pl->cone = prm->decim == FDKOD_DECIM_CONE && prm->s > 0;
+    pl->cone = prm->rows == FDKOD_ROWS_CONE && prm->s > 0;
+    pl->sinc = prm->decim == FDKOD_DECIM_SINC;
+    pl->nw = window_taps(*prm);
+    pl->cubic = prm->interp == FDKOD_INTERP_CUBIC;
     {
         int m = 8;
         while (m < 2 * pl->n - 1) m <<= 1;
@@ -477,8 +526,12 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
     std::vector<float2> resp, tw;
     std::vector<float> gtail;
     ramp_tables(pl->n, 1 << pl->logm, resp, gtail, tw);
-    std::vector<DecimStep> sched = build_schedule(pl->p, pl->pd);
-    while (sched.size() % kDecimUnroll) sched.push_back(DecimStep{0, 0, 0.0f, 0.0f});
+    Schedule schedule = build_schedule(pl->p, pl->pd, pl->nw, pl->sinc != 0);
+    std::vector<DecimStep>& sched = schedule.steps;
+    while (sched.size() % kDecimUnroll) {
+        sched.push_back(DecimStep{0, 0, 0.0f, 0.0f});
+        for (int i = 2; i < pl->nw; ++i) schedule.wext.push_back(0.0f);
+    }
     pl->nsched = (int)sched.size();
     {
         int emits = 0;
@@ -493,6 +546,7 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
     if ((st = upload(pl, &pl->d_gtail, gtail)) != FDKOD_OK) return bail(st);
     if ((st = upload(pl, &pl->d_tw, tw)) != FDKOD_OK) return bail(st);
     if ((st = upload(pl, &pl->d_sched, sched)) != FDKOD_OK) return bail(st);
+    if (pl->nw > 2 && (st = upload(pl, &pl->d_wext, schedule.wext)) != FDKOD_OK) return bail(st);
     if ((st = upload(pl, &pl->d_grid_direct, std::vector<int2>{make_int2(0, pl->n)})) != FDKOD_OK)
         return bail(st);
     if ((st = dev_alloc(pl->allocs, (void**)&pl->d_ac_p, sizeof(float) * (size_t)pl->nsq * pl->p)) != FDKOD_OK)
@@ -539,7 +593,7 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
     // the longest z run whose block footprint fits an LDS tile, two angles per
     // stage
     int ch = 1;
-    while (ch < 8 && 64 * ch < pl->wmax) ch <<= 1;
+    while (ch < max_chunks(pl) && 64 * ch < pl->wmax) ch <<= 1;
     pl->dec_chunks = ch;
     pl->bp_ok = false;
     for (int zr : {32, 16, 64}) {
@@ -556,7 +610,7 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
         BpVariant cv{};
         int cc = 0;
         if (pl->bp_ok && tune_cache_lookup(pl, &cv, &cc) && variant_holds(pl, cv) &&
-            (cc == 1 || cc == 2 || cc == 4 || cc == 8)) {
+            (cc == 1 || cc == 2 || cc == 4 || cc == 8) && cc <= max_chunks(pl)) {
             pl->bpv = cv;
             pl->dec_chunks = cc;
         }
@@ -717,6 +771,8 @@ fdkod_status fdkod_set_tuning(fdkod_plan_t pl, const fdkod_tuning* t) {
         return fail(FDKOD_E_UNSUPPORTED, "backprojection variant missing or too small for this geometry");
     const int c = t->decim_chunks;
     if (!(c == 1 || c == 2 || c == 4 || c == 8)) return fail(FDKOD_E_UNSUPPORTED, "decim_chunks must be 1, 2, 4 or 8");
+    if (c > max_chunks(pl))
+        return fail(FDKOD_E_UNSUPPORTED, "decim_chunks above 4 with more than two decimation windows");
     pl->bpv = v;
     pl->dec_chunks = c;
     pl->tuned_bp_ms = t->bp_ms;
@@ -735,6 +791,7 @@ fdkod_status fdkod_tune(fdkod_plan_t pl, const void* filt, void* ws, float* vol,
         float best = 1e30f;
         int bestc = pl->dec_chunks;
         for (int c : {1, 2, 4, 8}) {
+            if (c > max_chunks(pl)) continue;
             pl->dec_chunks = c;
             float ms = 0.0f;
             r = time_ms(st, 3, [&] { return fdkod_decompose(pl, filt, ws, stream); }, &ms);

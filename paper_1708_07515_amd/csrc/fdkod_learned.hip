@@ -12,7 +12,9 @@ namespace {
 
 fdkod_status learned_check(const fdkod_plan_s* pl) {
     if (pl->s == 0) return fail(FDKOD_E_UNSUPPORTED, "the learned decimation needs s > 0");
-    if (pl->cone) return fail(FDKOD_E_UNSUPPORTED, "the learned decimation corrects the triangle decimation");
+    if (pl->cone || pl->sinc || pl->cubic)
+        return fail(FDKOD_E_UNSUPPORTED,
+                    "the learned decimation corrects the triangle decimation of detector rows, linear shift");
     if (pl->wmax > kLearnedMaxWidth)
         return fail(FDKOD_E_UNSUPPORTED, "a square is wider than 252 local columns");
     if (pl->p > kLearnedMaxP) return fail(FDKOD_E_UNSUPPORTED, "more than 2048 projections");

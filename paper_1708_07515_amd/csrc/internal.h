@@ -73,7 +73,10 @@ struct DecimVol {
     const int2* crop;       // [nsq][nsched] integer shift and fraction per step
     const DecimStep* sched;
     const float* rscale;    // [nsq][nsched] row scale R / D_c(beta) (cone-corrected rows)
+    const float* wext;      // [nsched][nw - 2] weights of the open windows 2.. (nw > 2)
     int nsched;
+    int nw;                 // decimation windows a projection can feed (2, 4 or 6)
+    int cubic;              // 1: Keys' cubic shift along u (four samples), else linear
     int cone;               // 1: rows resampled by rscale about cv before the decimation
     float cv;               // (N-1)/2
     int n, p, pd, nsq;
@@ -210,5 +213,6 @@ hipError_t launch_adamw(const AdamArgs& a, hipStream_t st);
 // Limits the host checks before choosing a backprojection variant.
 constexpr int kTileXY = 16;      // voxels per tile side in x and y
 constexpr int kDecimUnroll = 8;  // the decimation schedule is padded to a multiple of this
+constexpr int kDecimMaxChunksWide = 4;  // column chunks per task when more than 2 windows are open
 
 }  // namespace fdkod

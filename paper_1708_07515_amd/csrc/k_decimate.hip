@@ -22,32 +22,59 @@
 // The row scale is uniform over the wavefront, so the two rows are two more
 // range-checked buffer resources (an empty range for a row outside the
 // detector, which reads zero).
+//
+// Quality knobs: a windowed-sinc decimation keeps `taps` windows open (each
+// projection is added to all of them with its own weight; the schedule
+// carries the extra weights), and the cubic shift reads four samples per
+// cropped value and weights them with Keys' kernel of the step's fraction.
 #include "internal.h"
 #include "dtype.h"
 
 namespace fdkod {
 
-// Read-only tables of the decimation (schedule, crop offsets), read word by
-// word through the constant address space so that their lane-uniform loads
-// are scalar.
+// Read-only tables of the decimation (schedule, crop offsets, row scales,
+// extra window weights), read word by word through the constant address
+// space so that their lane-uniform loads are scalar.
 typedef __attribute__((address_space(4))) const int* cword_ptr;
 static_assert(sizeof(DecimStep) == 16 && sizeof(int2) == 8, "table layouts");
 
-// Steps whose samples one group loads; two groups are in flight (the next
-// group's loads are issued before the current group's arithmetic).
-template <int CH>
-struct DecimGroup {
-    static constexpr int U = CH >= 8 ? 1 : 8 / CH;
+// Shape of one task's inner loop: CH column chunks of 64, NW decimation
+// windows open at once (2 for the triangle, `taps` for the windowed sinc), NT
+// samples per cropped value along u (2 linear, 4 cubic), NR detector rows per
+// cropped value (1, or 2 for cone-corrected rows).  U steps are loaded per
+// group and two groups are in flight (the next group's loads are issued
+// before the current group's arithmetic), so U shrinks as a step's loads grow.
+template <int CH, int NW, int NT, int NR>
+struct DecimShape {
+    static constexpr int LOADS = NT * NR / 2;          // relative to the linear, plain case
+    // at most 4 steps per group: the scalar state of 8 steps (schedule, crop
+    // and buffer resources of two groups in flight) spilled and doubled the
+    // one-chunk kernel's time
+    static constexpr int U0 = CH * LOADS >= 8 ? 1 : 8 / (CH * LOADS);
+    static constexpr int U = U0 > 4 ? 4 : U0;
+    static constexpr int NX = NW > 2 ? NW - 2 : 1;     // extra weights per step (array size)
 };
+
+// Keys' cubic convolution weights (a = -1/2) of the samples at offsets
+// -1, 0, 1, 2 from floor(u), for the fraction f of u.
+__device__ __forceinline__ void keys_weights(float f, float (&c)[4]) {
+    c[0] = ((-0.5f * f + 1.0f) * f - 0.5f) * f;
+    c[1] = (1.5f * f - 2.5f) * f * f + 1.0f;
+    c[2] = ((-1.5f * f + 2.0f) * f + 0.5f) * f;
+    c[3] = (0.5f * f - 0.5f) * f * f;
+}
 
 // One task: square q, detector row v (warped row v' for CONE), column group g
 // of 64*CH columns, run by one wavefront (lane = 0..63).
-template <int CH, int STORE, bool CONE>
+template <int CH, int STORE, bool CONE, int NW, bool CUBIC>
 __device__ __forceinline__ void decimate_task(const DecimVol& a, int task, int lane) {
     using S = Store<STORE>;
     using T = typename S::T;
-    constexpr int U = DecimGroup<CH>::U;
-    constexpr int CC = CONE ? CH : 1;   // second-row samples (CONE only)
+    constexpr int NT = CUBIC ? 4 : 2;
+    constexpr int NR = CONE ? 2 : 1;
+    using Sh = DecimShape<CH, NW, NT, NR>;
+    constexpr int U = Sh::U;
+    constexpr int NX = Sh::NX;
     static_assert(kDecimUnroll % U == 0, "the schedule is padded to whole groups");
     // task = (v * nsq + q) * tasks_per_sq + g: the squares of one detector row
     // run together and share its reads in L2.  CONE: task = (q * nv + v) *
@@ -59,10 +86,9 @@ __device__ __forceinline__ void decimate_task(const DecimVol& a, int task, int l
     const int v = CONE ? vq % a.nv : vq / a.nsq;   // row within the buffer (detector row v0 + v)
     const int n = a.n;
     const int2 gd = a.grid[q];
-    const int u0 = gd.x, width = gd.y;
+    const int width = gd.y;
     const int jbase = g * 64 * CH + lane;
     if (g * 64 * CH >= width) return;
-    (void)u0;
 
     // row v of projection 0 (CONE: row 0, the rows vary with the projection)
     const T* frow = (const T*)uniform_ptr((const T*)a.filt + (CONE ? 0 : (size_t)v * n));
@@ -70,6 +96,7 @@ __device__ __forceinline__ void decimate_task(const DecimVol& a, int task, int l
     const cword_ptr sched = (cword_ptr)a.sched;                       // 4 words per step
     const cword_ptr crop = (cword_ptr)(a.crop + (size_t)q * a.nsched);  // 2 words per step
     const cword_ptr rsc = (cword_ptr)(CONE ? a.rscale + (size_t)q * a.nsched : nullptr);
+    const cword_ptr wext = (cword_ptr)(NW > 2 ? a.wext : nullptr);    // NW - 2 words per step
     const float vrel = (float)v - a.cv;          // v' - c_v (CONE)
     const int64_t yoff = a.squares[q].y_off_row * a.nv;
     const size_t plane = (size_t)a.nv * width;   // elements per decimated angle
@@ -80,120 +107,138 @@ __device__ __forceinline__ void decimate_task(const DecimVol& a, int task, int l
 #pragma unroll
     for (int c = 0; c < CH; ++c) lane_off[c] = (jbase + 64 * c) * ES;
 
-    float acc0[CH], acc1[CH];
+    // acc[i]: the i-th open window (acc[0] is written out next)
+    float acc[NW][CH];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) {
-        acc0[c] = 0.0f;
-        acc1[c] = 0.0f;
-    }
+    for (int i = 0; i < NW; ++i)
+#pragma unroll
+        for (int c = 0; c < CH; ++c) acc[i][c] = 0.0f;
     int m = 0;
+
+    // Per-group state: the steps, their crop entries, row fractions, extra
+    // window weights and the loaded samples x[row][tap][step][chunk].
+    struct Group {
+        DecimStep st[U];
+        int2 cr[U];
+        float fv[U];
+        float wx[U][NX];
+        float x[NR][NT][U][CH];
+    };
     // Each detector row is read through a buffer resource spanning exactly
     // that row: the hardware range check returns zero outside [0, N), which is
     // the zero extension of the crop (offsets below the row wrap to huge
-    // unsigned values and are out of range too).  Two separately
-    // range-checked loads per sample: the empty asm hides that off1 = off0 +
-    // ES, so the loads are not merged into one wider load (whose range check
-    // would zero both elements at the detector's left edge).
-    auto issue = [&](int t, DecimStep (&st)[U], int2 (&cr)[U], float (&fv)[U], float (&x0)[U][CH],
-                     float (&x1)[U][CH], float (&y0)[U][CC], float (&y1)[U][CC]) {
+    // unsigned values and are out of range too).  Every tap is a separately
+    // range-checked load: the empty asm hides that the offsets are ES apart,
+    // so the loads are not merged into one wider load (whose range check
+    // would zero all its elements at the detector's left edge).
+    auto issue = [&](int t, Group& G) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int e = t + u;
-            st[u].p = sched[4 * e];
-            st[u].emit = sched[4 * e + 1];
-            st[u].w0 = __int_as_float(sched[4 * e + 2]);
-            st[u].w1 = __int_as_float(sched[4 * e + 3]);
-            cr[u] = make_int2(crop[2 * e], crop[2 * e + 1]);
+            G.st[u].p = sched[4 * e];
+            G.st[u].emit = sched[4 * e + 1];
+            G.st[u].w0 = __int_as_float(sched[4 * e + 2]);
+            G.st[u].w1 = __int_as_float(sched[4 * e + 3]);
+            G.cr[u] = make_int2(crop[2 * e], crop[2 * e + 1]);
+            if constexpr (NW > 2) {
+#pragma unroll
+                for (int i = 0; i < NX; ++i) G.wx[u][i] = __int_as_float(wext[(NW - 2) * e + i]);
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const T* pbase = frow + (size_t)st[u].p * pstride;
+            const T* pbase = frow + (size_t)G.st[u].p * pstride;
             int r0 = 0;
             if constexpr (CONE) {
                 // warped row -> detector row (v' - c_v) R / D_c + c_v, wave-uniform
                 const float rr = fmaf(vrel, __int_as_float(rsc[t + u]), a.cv);
                 const float rf = floorf(rr);
-                fv[u] = rr - rf;
+                G.fv[u] = rr - rf;
                 r0 = __builtin_amdgcn_readfirstlane((int)rf);
             }
-            // CONE: the row's address and extent go through readfirstlane so that
-            // the resource is built in scalar registers (a resource the compiler
-            // holds in vector registers costs a loop around every load)
-            const __amdgpu_buffer_rsrc_t rs =
-                CONE ? __builtin_amdgcn_make_buffer_rsrc(
-                           uniform_ptr(pbase + (ptrdiff_t)r0 * n), (short)0,
-                           __builtin_amdgcn_readfirstlane((unsigned)r0 < (unsigned)n ? n * ES : 0), 0x00020000)
-                     : __builtin_amdgcn_make_buffer_rsrc((void*)pbase, (short)0, n * ES, 0x00020000);
 #pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const int off0 = cr[u].x * ES + lane_off[c];
-                int off1 = off0 + ES;
-                asm volatile("" : "+v"(off1));
-                x0[u][c] = S::raw(rs, off0);
-                x1[u][c] = S::raw(rs, off1);
-            }
-            if constexpr (CONE) {
-                const int r1 = r0 + 1;
-                const __amdgpu_buffer_rsrc_t rs1 = __builtin_amdgcn_make_buffer_rsrc(
-                    uniform_ptr(pbase + (ptrdiff_t)r1 * n), (short)0,
-                    __builtin_amdgcn_readfirstlane((unsigned)r1 < (unsigned)n ? n * ES : 0), 0x00020000);
+            for (int rw = 0; rw < NR; ++rw) {
+                // CONE: the row's address and extent go through readfirstlane
+                // so that the resource is built in scalar registers (a resource
+                // the compiler holds in vector registers costs a loop around
+                // every load)
+                const int rowi = r0 + rw;
+                const __amdgpu_buffer_rsrc_t rs =
+                    CONE ? __builtin_amdgcn_make_buffer_rsrc(
+                               uniform_ptr(pbase + (ptrdiff_t)rowi * n), (short)0,
+                               __builtin_amdgcn_readfirstlane((unsigned)rowi < (unsigned)n ? n * ES : 0),
+                               0x00020000)
+                         : __builtin_amdgcn_make_buffer_rsrc((void*)pbase, (short)0, n * ES, 0x00020000);
 #pragma unroll
                 for (int c = 0; c < CH; ++c) {
-                    const int off0 = cr[u].x * ES + lane_off[c];
-                    int off1 = off0 + ES;
-                    asm volatile("" : "+v"(off1));
-                    y0[u][c] = S::raw(rs1, off0);
-                    y1[u][c] = S::raw(rs1, off1);
+                    const int off0 = G.cr[u].x * ES + lane_off[c];
+#pragma unroll
+                    for (int k = 0; k < NT; ++k) {
+                        int off = off0 + (k - (NT == 4 ? 1 : 0)) * ES;
+                        if (k > 0) asm volatile("" : "+v"(off));
+                        G.x[rw][k][u][c] = S::raw(rs, off);
+                    }
                 }
             }
         }
     };
-    auto consume = [&](const DecimStep (&st)[U], const int2 (&cr)[U], const float (&fv)[U],
-                       const float (&x0)[U][CH], const float (&x1)[U][CH], const float (&y0)[U][CC],
-                       const float (&y1)[U][CC]) {
+    auto consume = [&](const Group& G) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const float phi = __int_as_float(cr[u].y);
+            const float phi = __int_as_float(G.cr[u].y);
+            float cw[4];
+            if constexpr (CUBIC) keys_weights(phi, cw);
+            float w[NW];
+            w[0] = G.st[u].w0;
+            w[1] = G.st[u].w1;
+#pragma unroll
+            for (int i = 2; i < NW; ++i) w[i] = G.wx[u][i - 2];
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
-                float val = fmaf(phi, x1[u][c] - x0[u][c], x0[u][c]);
-                if constexpr (CONE) {
-                    const float hi = fmaf(phi, y1[u][c] - y0[u][c], y0[u][c]);
-                    val = fmaf(fv[u], hi - val, val);
+                float rowv[NR];
+#pragma unroll
+                for (int rw = 0; rw < NR; ++rw) {
+                    if constexpr (CUBIC) {
+                        float t = cw[0] * G.x[rw][0][u][c];
+                        t = fmaf(cw[1], G.x[rw][1][u][c], t);
+                        t = fmaf(cw[2], G.x[rw][2][u][c], t);
+                        rowv[rw] = fmaf(cw[3], G.x[rw][3][u][c], t);
+                    } else {
+                        rowv[rw] = fmaf(phi, G.x[rw][1][u][c] - G.x[rw][0][u][c], G.x[rw][0][u][c]);
+                    }
                 }
-                acc0[c] = fmaf(st[u].w0, val, acc0[c]);
-                acc1[c] = fmaf(st[u].w1, val, acc1[c]);
+                float val = rowv[0];
+                if constexpr (CONE) val = fmaf(G.fv[u], rowv[NR - 1] - val, val);
+#pragma unroll
+                for (int i = 0; i < NW; ++i) acc[i][c] = fmaf(w[i], val, acc[i][c]);
             }
-            if (st[u].emit) {
+            if (G.st[u].emit) {
                 const size_t base = (size_t)yoff + (size_t)m * plane + (size_t)v * width;
 #pragma unroll
                 for (int c = 0; c < CH; ++c) {
                     const int j = jbase + 64 * c;
-                    if (j < width) S::put(ws, base + j, acc0[c]);
-                    acc0[c] = acc1[c];
-                    acc1[c] = 0.0f;
+                    if (j < width) S::put(ws, base + j, acc[0][c]);
+#pragma unroll
+                    for (int i = 0; i + 1 < NW; ++i) acc[i][c] = acc[i + 1][c];
+                    acc[NW - 1][c] = 0.0f;
                 }
                 ++m;
             }
         }
     };
     // two groups (ping, pong) per iteration; the schedule holds whole groups
-    DecimStep sa[U], sb[U];
-    int2 ca[U], cb[U];
-    float fa[U], fb[U];
-    float xa0[U][CH], xa1[U][CH], xb0[U][CH], xb1[U][CH];
-    float ya0[U][CC], ya1[U][CC], yb0[U][CC], yb1[U][CC];
-    issue(0, sa, ca, fa, xa0, xa1, ya0, ya1);
+    Group ga, gb;
+    issue(0, ga);
     for (int t = 0; t < a.nsched; t += 2 * U) {
         const bool b_ok = t + U < a.nsched;
-        if (b_ok) issue(t + U, sb, cb, fb, xb0, xb1, yb0, yb1);
-        consume(sa, ca, fa, xa0, xa1, ya0, ya1);
-        if (t + 2 * U < a.nsched) issue(t + 2 * U, sa, ca, fa, xa0, xa1, ya0, ya1);
-        if (b_ok) consume(sb, cb, fb, xb0, xb1, yb0, yb1);
+        if (b_ok) issue(t + U, gb);
+        consume(ga);
+        if (t + 2 * U < a.nsched) issue(t + 2 * U, ga);
+        if (b_ok) consume(gb);
     }
 }
 
-template <int CH, int STORE, bool CONE>
+template <int CH, int STORE, bool CONE, int NW, bool CUBIC>
 __global__ __launch_bounds__(256) void k_decimate(DecimVol a) {
     // XCD-aware order: consecutive logical blocks share an XCD (and its L2)
     const int nblk = gridDim.x;
@@ -205,7 +250,7 @@ __global__ __launch_bounds__(256) void k_decimate(DecimVol a) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int task = lblk * 4 + wave;
     if (task >= a.ntasks) return;         // no barriers in this kernel
-    decimate_task<CH, STORE, CONE>(a, task, threadIdx.x & 63);
+    decimate_task<CH, STORE, CONE, NW, CUBIC>(a, task, threadIdx.x & 63);
 }
 
 // Many volumes in one launch (tasks concatenated volume after volume).  Each
@@ -225,25 +270,43 @@ __global__ __launch_bounds__(256) void k_decimate_batch(DecimBatchArgs a) {
     const int t = task - bv.y;
     if (t >= dv.ntasks) return;                         // padding of the volume's range
     const int lane = threadIdx.x & 63;
-    if (CHMAX >= 8 && dv.chunks >= 8) decimate_task<(CHMAX >= 8 ? 8 : 1), STORE, false>(dv, t, lane);
-    else if (CHMAX >= 4 && dv.chunks >= 4) decimate_task<(CHMAX >= 4 ? 4 : 1), STORE, false>(dv, t, lane);
-    else if (CHMAX >= 2 && dv.chunks >= 2) decimate_task<(CHMAX >= 2 ? 2 : 1), STORE, false>(dv, t, lane);
-    else decimate_task<1, STORE, false>(dv, t, lane);
+    if (CHMAX >= 8 && dv.chunks >= 8) decimate_task<(CHMAX >= 8 ? 8 : 1), STORE, false, 2, false>(dv, t, lane);
+    else if (CHMAX >= 4 && dv.chunks >= 4) decimate_task<(CHMAX >= 4 ? 4 : 1), STORE, false, 2, false>(dv, t, lane);
+    else if (CHMAX >= 2 && dv.chunks >= 2) decimate_task<(CHMAX >= 2 ? 2 : 1), STORE, false, 2, false>(dv, t, lane);
+    else decimate_task<1, STORE, false, 2, false>(dv, t, lane);
 }
 
-template <int CH, bool CONE>
-static void launch_ch_rows(const DecimVol& a, int store, dim3 grid, hipStream_t st) {
+template <int CH, bool CONE, int NW, bool CUBIC>
+static void launch_shape(const DecimVol& a, int store, dim3 grid, hipStream_t st) {
     switch (store) {
-        case 0: hipLaunchKernelGGL((k_decimate<CH, 0, CONE>), grid, dim3(256), 0, st, a); break;
-        case 1: hipLaunchKernelGGL((k_decimate<CH, 1, CONE>), grid, dim3(256), 0, st, a); break;
-        default: hipLaunchKernelGGL((k_decimate<CH, 2, CONE>), grid, dim3(256), 0, st, a); break;
+        case 0: hipLaunchKernelGGL((k_decimate<CH, 0, CONE, NW, CUBIC>), grid, dim3(256), 0, st, a); break;
+        case 1: hipLaunchKernelGGL((k_decimate<CH, 1, CONE, NW, CUBIC>), grid, dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_decimate<CH, 2, CONE, NW, CUBIC>), grid, dim3(256), 0, st, a); break;
     }
 }
 
+template <int CH, int NW>
+static void launch_nw(const DecimVol& a, int store, dim3 grid, hipStream_t st) {
+    if (a.cone) {
+        if (a.cubic) launch_shape<CH, true, NW, true>(a, store, grid, st);
+        else launch_shape<CH, true, NW, false>(a, store, grid, st);
+    } else {
+        if (a.cubic) launch_shape<CH, false, NW, true>(a, store, grid, st);
+        else launch_shape<CH, false, NW, false>(a, store, grid, st);
+    }
+}
+
+// false when no kernel exists for the chunk count and window count
 template <int CH>
-static void launch_ch(const DecimVol& a, int store, dim3 grid, hipStream_t st) {
-    if (a.cone) launch_ch_rows<CH, true>(a, store, grid, st);
-    else launch_ch_rows<CH, false>(a, store, grid, st);
+static bool launch_ch(const DecimVol& a, int store, dim3 grid, hipStream_t st) {
+    switch (a.nw) {
+        case 2: launch_nw<CH, 2>(a, store, grid, st); return true;
+        case 4: if constexpr (CH <= kDecimMaxChunksWide) { launch_nw<CH, 4>(a, store, grid, st); return true; }
+                return false;
+        case 6: if constexpr (CH <= kDecimMaxChunksWide) { launch_nw<CH, 6>(a, store, grid, st); return true; }
+                return false;
+        default: return false;
+    }
 }
 
 template <int CH>
@@ -262,13 +325,15 @@ static dim3 decimate_grid(int ntasks) {
 
 hipError_t launch_decimate(const DecimVol& a, int chunks, int store, hipStream_t st) {
     const dim3 grid = decimate_grid(a.ntasks);
+    bool ok = false;
     switch (chunks) {
-        case 1: launch_ch<1>(a, store, grid, st); break;
-        case 2: launch_ch<2>(a, store, grid, st); break;
-        case 4: launch_ch<4>(a, store, grid, st); break;
-        case 8: launch_ch<8>(a, store, grid, st); break;
-        default: return hipErrorInvalidValue;
+        case 1: ok = launch_ch<1>(a, store, grid, st); break;
+        case 2: ok = launch_ch<2>(a, store, grid, st); break;
+        case 4: ok = launch_ch<4>(a, store, grid, st); break;
+        case 8: ok = launch_ch<8>(a, store, grid, st); break;
+        default: break;
     }
+    if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

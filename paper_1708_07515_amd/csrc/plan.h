@@ -12,7 +12,10 @@ struct fdkod_plan_s {
     int device = 0;
     int n = 0, nz = 0, p = 0, s = 0, k = 0, d = 1, pd = 0, nsq = 1, store = 0;
     int logm = 0;
-    int cone = 0;           // cone-corrected rows (FDKOD_DECIM_CONE with s > 0)
+    int cone = 0;           // cone-corrected rows (FDKOD_ROWS_CONE with s > 0)
+    int nw = 2;             // windows a projection can feed: the decimation window's taps
+    int sinc = 0;           // windowed-sinc decimation (FDKOD_DECIM_SINC)
+    int cubic = 0;          // cubic shift (FDKOD_INTERP_CUBIC)
     double r = 0;
     std::vector<fdkod::SquareDesc> sq;
     std::vector<int2> grid;
@@ -33,6 +36,7 @@ struct fdkod_plan_s {
     float* d_ac_p = nullptr;
     int2* d_crop = nullptr;
     float* d_rscale = nullptr;  // [nsq][nsched] R / D_c (cone-corrected rows only)
+    float* d_wext = nullptr;    // [nsched][nw - 2] weights of windows 2.. (nw > 2 only)
     float4* d_geo_m = nullptr;
     int2* d_grid = nullptr;
     int2* d_grid_direct = nullptr;
@@ -56,6 +60,8 @@ fdkod_status dev_alloc(std::vector<void*>& owner, void** ptr, size_t bytes);
 // geometry; false when no tile holds it.  cone_side > 0: cone-corrected rows
 // of squares at most cone_side voxels wide.
 bool bp_tiles_for(int n, int nz, double r, int zrun, int cone_side, int* tw, int* th);
+// largest column-chunk count the plan's decimation kernels exist for
+inline int max_chunks(const fdkod_plan_s* pl) { return pl->nw > 2 ? kDecimMaxChunksWide : 8; }
 // square side bound for bp_tiles_for (0 unless the plan's rows are cone-corrected)
 inline int cone_side(const fdkod_plan_s* pl) { return pl->cone ? (pl->n + (1 << pl->s) - 1) >> pl->s : 0; }
 // a backprojection variant exists and its LDS footprint holds the plan's

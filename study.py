@@ -17,6 +17,10 @@ evaluations (Sec. 2.2 cost model, Sec. 4 quality), on synthetic phantoms:
    Total = C1 N^3 P / 2^s + C2 N^2 P 2^s fitted by least squares (one
    constant per term), with the optimum 2^s = sqrt(C1 N / C2) against the
    measured best s.
+4. The non-learned quality knobs (windowed-sinc decimation, cubic shift)
+   against the learned decimation filter on the same held-out phantoms (the
+   learned filter trained as in its GPU test), and the decomposition cost of
+   each at 512^3, P = 360, s = 3.
 
 Usage: python study.py [--quick] > study.json (progress on stderr).  Every
 reconstruction runs in the HIP library; the analysis is plain NumPy.
@@ -151,10 +155,11 @@ def fit_costs(rows):
 
 # ----------------------------------------------------------------- GPU runs
 
-def reconstruct(torch, pkg, proj, n, p, r, s, k=0, decim="triangle", reps=0):
+def reconstruct(torch, pkg, proj, n, p, r, s, k=0, rows="detector", reps=0, **knobs):
     """Volume (device tensor) and, with reps > 0, the median decomposition and
-    reconstruction kernel times (ms) over ``reps`` runs."""
-    with pkg.Plan(n, p, r, s=s, skip=k, decim=decim) as plan:
+    reconstruction kernel times (ms) over ``reps`` runs.  ``knobs``: decim,
+    taps, interp of the plan."""
+    with pkg.Plan(n, p, r, s=s, skip=k, rows=rows, **knobs) as plan:
         filt, ws, vol = plan.empty_filtered(), plan.empty_workspace(), plan.empty_volume()
         plan.filter(proj, filt)
         plan.decompose(filt, ws)
@@ -182,8 +187,8 @@ def combos(smax):
     out = []
     for s in range(1, smax + 1):
         for k in range(0, min(2, s) + 1):
-            for decim in ("triangle", "cone"):
-                out.append((s, k, decim))
+            for rows in ("detector", "cone"):
+                out.append((s, k, rows))
     return out
 
 
@@ -205,18 +210,18 @@ def quality_sweep(torch, pkg, n, p, r, smax):
     edge_ref = slanted_edge(bref[mid].cpu().double().numpy(), (0.0, 0.0), box_angle, half_vox)
     log(f"[study] direct FDK edge: {edge_ref}")
     rows = []
-    for s, k, decim in combos(smax):
-        vol, _ = reconstruct(torch, pkg, proj, n, p, r, s, k, decim)
+    for s, k, rw in combos(smax):
+        vol, _ = reconstruct(torch, pkg, proj, n, p, r, s, k, rw)
         v = vol.cpu().double().numpy()
         ratio = v[sl][mask] / ref_in
-        bvol, _ = reconstruct(torch, pkg, bproj, n, p, r, s, k, decim)
+        bvol, _ = reconstruct(torch, pkg, bproj, n, p, r, s, k, rw)
         edge = slanted_edge(bvol[mid].cpu().double().numpy(), (0.0, 0.0), box_angle, half_vox)
-        row = {"s": s, "k": k, "d": 2 ** (s - k), "decim": decim,
+        row = {"s": s, "k": k, "d": 2 ** (s - k), "rows": rw,
                "rel_rmse_vs_fdk": rel_rmse(v, ref_np),
                "interior_ratio_mean": float(ratio.mean()), "interior_ratio_std": float(ratio.std()),
                "interior_ratio_p01": float(np.percentile(ratio, 1)),
                "interior_ratio_p99": float(np.percentile(ratio, 99)), **edge}
-        log(f"[study] s={s} k={k} {decim}: rel-RMSE {row['rel_rmse_vs_fdk']:.4f}, interior ratio "
+        log(f"[study] s={s} k={k} {rw} rows: rel-RMSE {row['rel_rmse_vs_fdk']:.4f}, interior ratio "
             f"{row['interior_ratio_mean']:.4f} +- {row['interior_ratio_std']:.4f}, MTF50 {edge['mtf50']:.3f} "
             f"MTF10 {edge['mtf10']:.3f}, 10-90 {edge['width_10_90']:.2f}")
         rows.append(row)
@@ -235,7 +240,7 @@ def time_split(torch, pkg, sizes, smax, reps):
         proj = phantom.project(ell, n, p, r, device="cuda:0").contiguous()
         rows = []
         for s in range(1, smax + 1):
-            _, (dec, rec) = reconstruct(torch, pkg, proj, n, p, r, s, 0, "triangle", reps)
+            _, (dec, rec) = reconstruct(torch, pkg, proj, n, p, r, s, 0, "detector", reps)
             rows.append({"n": n, "p": p, "s": s, "decompose_ms": dec, "reconstruct_ms": rec,
                          "total_ms": dec + rec})
             log(f"[study] N={n} P={p} s={s}: decompose {dec:.3f} ms, reconstruct {rec:.3f} ms")
@@ -248,6 +253,98 @@ def time_split(torch, pkg, sizes, smax, reps):
         del proj
         torch.cuda.empty_cache()
     return out
+
+
+KNOBS = [("triangle", {}), ("sinc2", dict(decim="sinc", taps=2)), ("sinc4", dict(decim="sinc", taps=4)),
+         ("sinc6", dict(decim="sinc", taps=6)), ("cubic", dict(interp="cubic")),
+         ("sinc4+cubic", dict(decim="sinc", taps=4, interp="cubic")),
+         ("sinc6+cubic", dict(decim="sinc", taps=6, interp="cubic"))]
+
+
+def _filtered_scans(torch, pkg, direct, n, p, r, seeds):
+    """Filtered projections and direct-FDK volumes of seeded phantoms."""
+    from synth import phantom
+    out = []
+    for sd in seeds:
+        proj = phantom.project(phantom.random_ellipsoids(8, sd), n, p, r, device="cuda:0").contiguous()
+        filt = direct.empty_filtered()
+        direct.filter(proj, filt)
+        tgt = direct.empty_volume()
+        direct.reconstruct(filt, None, tgt)
+        out.append((filt, tgt))
+    return out
+
+
+def knobs_vs_learned(torch, pkg, steps=600, cost_reps=5):
+    """Held-out error against direct FDK of every knob setting and of the
+    trained learned filter (N = 96, N_z = 24, P = 128, R = 384, s = 2; 8
+    training and 4 held-out phantoms of 8 ellipsoids), and the decomposition
+    time of each at 512^3, P = 360, R = 2048, s = 3, FP32."""
+    n, nz, p, r, s = 96, 24, 128, 384.0, 2
+    direct = pkg.Plan(n, p, r, s=0, nz=nz)
+    train = _filtered_scans(torch, pkg, direct, n, p, r, range(100, 108))
+    held = _filtered_scans(torch, pkg, direct, n, p, r, range(200, 204))
+
+    def rel(a, b):
+        return float(torch.linalg.norm((a - b).double()) / torch.linalg.norm(b.double()))
+
+    err = {}
+    for name, knobs in KNOBS:
+        with pkg.Plan(n, p, r, s=s, nz=nz, **knobs) as plan:
+            ws, vol = plan.empty_workspace(), plan.empty_volume()
+            e = []
+            for filt, tgt in held:
+                plan.decompose(filt, ws)
+                plan.reconstruct(filt, ws, vol)
+                e.append(rel(vol, tgt))
+            err[name] = float(np.mean(e))
+    with pkg.Plan(n, p, r, s=s, nz=nz) as plan:
+        ws, vol = plan.empty_workspace(), plan.empty_volume()
+        resid = torch.empty_like(vol)
+        dws = torch.empty(plan.workspace_elems, dtype=torch.float32, device="cuda:0")
+        net = pkg.LearnedDecimation("cuda:0", seed=0, lr=3e-3)
+        for it in range(steps):
+            filt, tgt = train[it % len(train)]
+            net.train_step(plan, filt, ws, vol, tgt, resid, dws)
+        e = []
+        for filt, tgt in held:
+            net.forward(plan, filt, ws, vol)
+            e.append(rel(vol, tgt))
+        err["learned"] = float(np.mean(e))
+    direct.close()
+    log("[study] held-out rel-RMSE vs direct FDK: " + ", ".join(f"{a} {b:.4f}" for a, b in err.items()))
+
+    from synth import phantom
+    n2, p2, r2, s2 = 512, 360, 2048.0, 3
+    proj = phantom.project(phantom.random_ellipsoids(20, 2), n2, p2, r2, device="cuda:0").contiguous()
+    cost = {}
+
+    def median_ms(fn):
+        fn()
+        t = []
+        for _ in range(cost_reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            t.append(e0.elapsed_time(e1))
+        return float(np.median(t))
+
+    for name, knobs in KNOBS + [("learned", None)]:
+        with pkg.Plan(n2, p2, r2, s=s2, **(knobs or {})) as plan:
+            filt, ws = plan.empty_filtered(), plan.empty_workspace()
+            plan.filter(proj, filt)
+            if knobs is None:
+                w = pkg.LearnedDecimation("cuda:0", seed=0).weights
+                cost[name] = median_ms(lambda: plan.learned_decompose(filt, ws, w))
+            else:
+                cost[name] = median_ms(lambda: plan.decompose(filt, ws))
+            del filt, ws
+    log("[study] decomposition ms at 512^3, s=3: " + ", ".join(f"{a} {b:.3f}" for a, b in cost.items()))
+    return {"held_out": {"n": n, "nz": nz, "p": p, "r": r, "s": s, "train_phantoms": 8, "held_out_phantoms": 4,
+                         "learned_steps": steps, "rel_rmse_vs_fdk": err},
+            "decompose_ms_512_p360_s3": cost}
 
 
 def main():
@@ -263,12 +360,14 @@ def main():
     if args.quick:
         sweep = quality_sweep(torch, pkg, 96, 120, 384.0, 3)
         split = time_split(torch, pkg, [(128, 180)], 3, 2)
+        knobs = knobs_vs_learned(torch, pkg, steps=50, cost_reps=2)
     else:
         sweep = quality_sweep(torch, pkg, 256, 360, 1024.0, 5)
         split = time_split(torch, pkg, [(256, 360), (512, 360), (1024, 720)], 5, args.reps)
+        knobs = knobs_vs_learned(torch, pkg)
     print(json.dumps({"study": "FDK-OD quality and cost on one MI355X", "data": "synthetic",
-                      "quality": sweep, "time_split": split, "seconds": round(time.time() - t0, 1)}),
-          flush=True)
+                      "quality": sweep, "time_split": split, "knobs": knobs,
+                      "seconds": round(time.time() - t0, 1)}), flush=True)
 
 
 if __name__ == "__main__":

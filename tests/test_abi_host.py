@@ -48,6 +48,12 @@ def test_version_and_status_strings():
     (dict(n=64, p=7, r=512.0, s=2), "E_GEOMETRY"),       # P < 2 D
     (dict(n=64, p=90, r=512.0, nz=-1), "E_ARG"),
     (dict(n=64, p=90, r=512.0, s=2, decim=2), "E_ARG"),
+    (dict(n=64, p=90, r=512.0, s=2, decim="sinc", taps=3), "E_ARG"),
+    (dict(n=64, p=90, r=512.0, s=2, decim="sinc", taps=8), "E_ARG"),
+    (dict(n=64, p=90, r=512.0, s=2, taps=4), "E_ARG"),                  # the triangle has 2
+    (dict(n=64, p=90, r=512.0, s=2, rows=2), "E_ARG"),
+    (dict(n=64, p=90, r=512.0, s=2, interp=2), "E_ARG"),
+    (dict(n=64, p=23, r=512.0, s=2, decim="sinc", taps=6), "E_GEOMETRY"),  # P < taps D
 ])
 def test_validation_codes(args, code):
     with pytest.raises(pkg.FdkodError) as ei:
@@ -57,8 +63,10 @@ def test_validation_codes(args, code):
 
 @pytest.mark.parametrize("args", [dict(n=64, p=90, r=512.0, s=2), dict(n=2000, p=720, r=8000.0, s=4),
                                   dict(n=64, p=8, r=45.0, s=2, skip=0), dict(n=3, p=1, r=2.0),
-                                  dict(n=64, p=90, r=512.0, s=2, decim="cone"),
-                                  dict(n=64, p=90, r=512.0, s=0, decim="cone")])
+                                  dict(n=64, p=90, r=512.0, s=2, rows="cone"),
+                                  dict(n=64, p=90, r=512.0, s=0, rows="cone"),
+                                  dict(n=64, p=90, r=512.0, s=2, decim="sinc", taps=6, interp="cubic"),
+                                  dict(n=64, p=24, r=512.0, s=2, decim="sinc", taps=6)])
 def test_validation_accepts(args):
     pkg.validate(**args)
 
@@ -92,9 +100,11 @@ def test_batch_validation_before_device():
     assert lib.fdkod_batch_create(arr, 2, 0, ctypes.byref(h)) == 2
     arr = (_lib.Params * 2)(good, mixed)
     assert lib.fdkod_batch_create(arr, 2, 0, ctypes.byref(h)) == 1
-    cone = _lib.Params(32, 0, 45, 128.0, 1, 0, 0, 1)       # cone-corrected rows
-    arr = (_lib.Params * 2)(good, cone)
-    assert lib.fdkod_batch_create(arr, 2, 0, ctypes.byref(h)) == 3
+    for knob in (_lib.Params(32, 0, 45, 128.0, 1, 0, 0, 0, 0, 1, 0),     # cone-corrected rows
+                 _lib.Params(32, 0, 45, 128.0, 1, 0, 0, 1, 4, 0, 0),     # windowed sinc
+                 _lib.Params(32, 0, 45, 128.0, 1, 0, 0, 0, 0, 0, 1)):    # cubic shift
+        arr = (_lib.Params * 2)(good, knob)
+        assert lib.fdkod_batch_create(arr, 2, 0, ctypes.byref(h)) == 3
     assert lib.fdkod_batch_create(arr, 0, 0, ctypes.byref(h)) == 1
     assert h.value is None
     assert lib.fdkod_batch_run(None, None) == 1

@@ -1,4 +1,4 @@
-"""GPU tests of the cone-corrected decimation (FDKOD_DECIM_CONE): parity with
+"""GPU tests of the cone-corrected decimation (FDKOD_ROWS_CONE): parity with
 the FP64 oracle's fdkod_cone (rel-RMSE <= 1e-4 FP32, <= 2e-3 BF16 storage),
 s = 0 unchanged, the quality property it exists for (less off-midplane error
 than the plain decimation at a large D), and the calls that reject it."""
@@ -29,8 +29,8 @@ def _gpu():
     require_gpu()
 
 
-def run(proj, n, p, r, s, k=0, nz=0, store="f32", decim="cone"):
-    with pkg.Plan(n, p, r, s=s, skip=k, nz=nz, store=store, decim=decim) as plan:
+def run(proj, n, p, r, s, k=0, nz=0, store="f32", rows="cone"):
+    with pkg.Plan(n, p, r, s=s, skip=k, nz=nz, store=store, rows=rows) as plan:
         filt, ws, vol = plan.empty_filtered(), plan.empty_workspace(), plan.empty_volume()
         plan.filter(proj.to(DEV), filt)
         plan.backproject(filt, vol, ws)
@@ -57,15 +57,15 @@ def test_cone_matches_oracle(case):
     err, _ = report(f"cone {case}", got, ref)
     assert err <= (TOL_F32 if store == "f32" else TOL_HALF)
     # the plain decimation differs from the cone-corrected one off the mid-plane
-    plain = run(proj, n, p, r, s, k, nz, store, decim="triangle")
+    plain = run(proj, n, p, r, s, k, nz, store, rows="detector")
     assert metrics.rel_rmse(plain, ref) > 10 * err
 
 
 def test_cone_is_plain_fdkod_at_s0():
     n, p, r = 48, 60, 200.0
     proj = scan(n, p, r, 6, 7)
-    a = run(proj, n, p, r, 0, decim="cone")
-    b = run(proj, n, p, r, 0, decim="triangle")
+    a = run(proj, n, p, r, 0, rows="cone")
+    b = run(proj, n, p, r, 0, rows="detector")
     assert np.array_equal(a, b)
 
 
@@ -75,8 +75,8 @@ def test_cone_reduces_off_midplane_error_against_direct_fdk():
     the plain decimation's."""
     n, p, r, s = 96, 96, 192.0, 4
     proj = phantom.project(thin_discs(), n, p, r).contiguous()
-    direct = run(proj, n, p, r, 0, decim="triangle")
-    plain = run(proj, n, p, r, s, decim="triangle")
+    direct = run(proj, n, p, r, 0, rows="detector")
+    plain = run(proj, n, p, r, s, rows="detector")
     cone = run(proj, n, p, r, s)
     cz = (n - 1) / 2.0
     sl = [int(cz + 0.55 * n / 2), int(cz - 0.5 * n / 2)]
@@ -88,7 +88,7 @@ def test_cone_reduces_off_midplane_error_against_direct_fdk():
 
 def test_calls_that_need_detector_rows_reject_cone():
     n, p, r = 64, 90, 256.0
-    with pkg.Plan(n, p, r, s=2, decim="cone") as plan:
+    with pkg.Plan(n, p, r, s=2, rows="cone") as plan:
         for call in (lambda: plan.band_rows(0, 8),
                      lambda: plan.learned_decompose(plan.empty_filtered(), plan.empty_workspace(),
                                                     torch.zeros(pkg.LEARNED_PARAMS, dtype=torch.bfloat16,
@@ -97,5 +97,5 @@ def test_calls_that_need_detector_rows_reject_cone():
                 call()
             assert ei.value.code == "E_UNSUPPORTED"
     with pytest.raises(pkg.FdkodError) as ei:
-        pkg.Batch([dict(n=n, p=p, r=r, s=2), dict(n=n, p=p, r=r, s=2, decim="cone")])
+        pkg.Batch([dict(n=n, p=p, r=r, s=2), dict(n=n, p=p, r=r, s=2, rows="cone")])
     assert ei.value.code == "E_UNSUPPORTED"

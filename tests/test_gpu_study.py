@@ -29,10 +29,10 @@ def test_quality_sweep_properties():
     for r in rows:
         assert abs(r["interior_ratio_mean"] - 1.0) <= 5e-3, r
         assert r["width_10_90"] > fdk_w, r
-    by = {(r["s"], r["k"], r["decim"]): r for r in rows}
-    for (s, k, decim), r in by.items():
-        if (s, k + 1, decim) in by:
-            assert by[(s, k + 1, decim)]["rel_rmse_vs_fdk"] < r["rel_rmse_vs_fdk"], (s, k, decim)
+    by = {(r["s"], r["k"], r["rows"]): r for r in rows}
+    for (s, k, rw), r in by.items():
+        if (s, k + 1, rw) in by:
+            assert by[(s, k + 1, rw)]["rel_rmse_vs_fdk"] < r["rel_rmse_vs_fdk"], (s, k, rw)
     w0 = np.mean([r["width_10_90"] for r in rows if r["k"] == 0])
     w1 = np.mean([r["width_10_90"] for r in rows if r["k"] == 1])
     log(f"mean 10-90 edge width: k=0 {w0:.2f}, k=1 {w1:.2f}")
