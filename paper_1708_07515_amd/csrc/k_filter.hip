@@ -88,16 +88,26 @@ __device__ __forceinline__ void fft_stage(float2* z, int t, const float2* __rest
     constexpr int ns = NS;
     float2 v[BPT][R];
     constexpr int tstep = M / (R * ns);
+    // the twiddles (an L2-resident table) are all requested before the LDS
+    // reads, so their latencies overlap instead of adding up
+    float2 w[BPT][R];
+    if constexpr (NS > 1) {
+#pragma unroll
+        for (int b = 0; b < BPT; ++b) {
+            const int k = (t + b * TP) & (ns - 1);
+#pragma unroll
+            for (int r = 1; r < R; ++r) w[b][r] = tw[(r * k * tstep) & (M - 1)];
+        }
+    }
 #pragma unroll
     for (int b = 0; b < BPT; ++b) {
         const int j = t + b * TP;
         if (j < NB) {
-            const int k = j & (ns - 1);
 #pragma unroll
             for (int r = 0; r < R; ++r) v[b][r] = z[pidx(j + r * NB)];
             if constexpr (NS > 1) {
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[(r * k * tstep) & (M - 1)]);
+                for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], w[b][r]);
             }
             if constexpr (R == 16) {
                 dft16(v[b]);
@@ -190,40 +200,76 @@ void k_filter(FilterArgs a) {
     const float rb0 = rr + b0 * b0, rb1 = rr + b1 * b1;
     const float* p0 = a.proj + (size_t)r0 * n;
     const float* p1 = a.proj + (size_t)r1 * n;
-    auto weighted = [&](int u, float& x0, float& x1) {
+    auto weight = [&](int u, float rb) {
         const float au = (float)u - a.c;
-        x0 = has0 ? p0[u] * (a.r * rsqrtf(rb0 + au * au)) : 0.0f;
-        x1 = has1 ? p1[u] * (a.r * rsqrtf(rb1 + au * au)) : 0.0f;
+        return a.r * rsqrtf(rb + au * au);
     };
-    for (int u = t; u < M; u += TP) {
-        float d0 = 0.0f, d1 = 0.0f;      // the difference at u = N is applied after the FFT
-        if (u < n) {
-            weighted(u, d0, d1);
-            if (u > 0) {
-                float e0, e1;
-                weighted(u - 1, e0, e1);
-                d0 -= e0;
-                d1 -= e1;
+    // every sample of the thread is requested before any is used: samples
+    // u - 1 and u in one 8-byte load (u >= 1; u = 0 reads samples 0 and 1 and
+    // uses the first), both rows, all positions
+    constexpr int IT = (M + TP - 1) / TP;
+    float2 q0[IT], q1[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const int u = t + i * TP;
+        const int u1 = u > 0 ? u - 1 : 0;
+        const bool in = u < n;
+        q0[i] = (in && has0) ? *(const float2*)(p0 + u1) : make_float2(0.0f, 0.0f);
+        q1[i] = (in && has1) ? *(const float2*)(p1 + u1) : make_float2(0.0f, 0.0f);
+    }
+    // pre-weighted first difference d[u] = p~[u] - p~[u-1] (zero-padded); the
+    // difference at u = N is applied after the FFT
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const int u = t + i * TP;
+        if (u < M) {
+            float d0 = 0.0f, d1 = 0.0f;
+            if (u == 0) {
+                d0 = q0[i].x * weight(0, rb0);
+                d1 = q1[i].x * weight(0, rb1);
+            } else if (u < n) {
+                d0 = q0[i].y * weight(u, rb0) - q0[i].x * weight(u - 1, rb0);
+                d1 = q1[i].y * weight(u, rb1) - q1[i].x * weight(u - 1, rb1);
             }
+            z[pidx(u)] = make_float2(d0, d1);
         }
-        z[pidx(u)] = make_float2(d0, d1);
     }
-    float last0, last1;
-    weighted(n - 1, last0, last1);
+    const float last0 = has0 ? p0[n - 1] * weight(n - 1, rb0) : 0.0f;
+    const float last1 = has1 ? p1[n - 1] * weight(n - 1, rb1) : 0.0f;
     __syncthreads();
     fft_lds<LOGM, TP>(z, t, a.twiddle);
-    for (int k = t; k < M; k += TP) {
-        const float2 v = cmul(z[pidx(k)], a.resp[k]);
-        z[pidx(k)] = make_float2(v.x, -v.y);          // conj(Z G)
+    // tables (L2-resident) are requested in one batch before their first use
+    float2 gr[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const int k = t + i * TP;
+        gr[i] = k < M ? a.resp[k] : make_float2(0.0f, 0.0f);
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const int k = t + i * TP;
+        if (k < M) {
+            const float2 v = cmul(z[pidx(k)], gr[i]);
+            z[pidx(k)] = make_float2(v.x, -v.y);      // conj(Z G)
+        }
     }
     __syncthreads();
     fft_lds<LOGM, TP>(z, t, a.twiddle);
+    float gtl[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const int u = t + i * TP;
+        gtl[i] = u < n ? a.gtail[u] : 0.0f;          // g[u - N]
+    }
     typename S::T* out = (typename S::T*)a.out;
-    for (int u = t; u < n; u += TP) {
-        const float2 v = z[pidx(u)];                  // conj of the result
-        const float gt = a.gtail[u];                  // g[u - N]
-        if (has0) S::put(out, (size_t)r0 * n + u, v.x - last0 * gt);
-        if (has1) S::put(out, (size_t)r1 * n + u, -v.y - last1 * gt);
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const int u = t + i * TP;
+        if (u < n) {
+            const float2 v = z[pidx(u)];              // conj of the result
+            if (has0) S::put(out, (size_t)r0 * n + u, v.x - last0 * gtl[i]);
+            if (has1) S::put(out, (size_t)r1 * n + u, -v.y - last1 * gtl[i]);
+        }
     }
 }
 
