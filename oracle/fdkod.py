@@ -385,6 +385,8 @@ def sample_vu(img, slot, nv, v, u, interp="linear"):
         vi = iv + dv
         vin = (vi >= 0) & (vi < nv)
         kk = slot[np.clip(vi, 0, nv - 1)]
+        if np.any(vin & (kk < 0)):
+            raise KeyError("detector row needed but not filtered")
         for du, wu in u_taps(u - iu, interp):
             ui = iu + du
             ok = vin & (ui >= 0) & (ui < nu)
@@ -397,13 +399,14 @@ def cone_row(sq, x, y, z, beta, r):
     return z * g.depth(sq.xc, sq.yc, beta, r) / g.depth(x, y, beta, r)
 
 
-def backproject_square_cone(y_sub, nv, sq, betas_dec, r, n, x, y, z):
+def backproject_square_cone(y_sub, nv, sq, betas_dec, r, n, x, y, z, slot=None):
     """Step 5 on cone-corrected data Y[m, v', j]: as backproject_square, with
-    the row coordinate cone_row + c_v."""
+    the row coordinate cone_row + c_v.  ``slot`` maps warped rows to the rows
+    of y_sub (all rows by default; -1 = not computed)."""
     cu = cv = g.centre(n)
     pd = len(betas_dec)
     ac = centre_track(sq, betas_dec, r)
-    slot = np.arange(nv)
+    slot = np.arange(nv) if slot is None else slot
     f = np.zeros(np.broadcast(x, y, z).shape)
     for m, beta in enumerate(betas_dec):
         u_mag = g.depth(x, y, beta, r) / r
@@ -434,6 +437,65 @@ def fdkod_cone(proj, r, s, k=0, slices=None, nz=None, store=None, window="triang
         if store is not None:
             y_sub = store(y_sub)
         out[:, sq.y0:sq.y1, sq.x0:sq.x1] = backproject_square_cone(y_sub, nv, sq, betas_dec, r, n, x, y, z)
+    return out
+
+
+def cone_rows_for_points(n, nv, r, sq, betas, betas_dec, x, y, z):
+    """Warped rows that the cone-corrected backprojection of the points reads
+    (both bilinear neighbours, at every decimated angle) and the detector rows
+    that those warped rows are resampled from at every original angle."""
+    cv = g.centre(n)
+    iv = np.floor(np.array([cone_row(sq, x, y, z, b, r) for b in betas_dec]) + cv).astype(np.int64)
+    warped = np.unique(np.concatenate([iv.ravel(), iv.ravel() + 1]))
+    warped = warped[(warped >= 0) & (warped < nv)]
+    det = set()
+    for beta in betas:
+        f = np.floor((warped - cv) * cone_row_scale(sq, beta, r) + cv).astype(np.int64)
+        det.update(f.tolist())
+        det.update((f + 1).tolist())
+    det = np.array(sorted(d for d in det if 0 <= d < nv), dtype=np.int64)
+    return warped, det
+
+
+def fdkod_cone_points(proj, r, s, k, idx, nz=None, store=None, window="triangle", taps=2, interp="linear"):
+    """Cone-corrected FDK-OD at voxel indices ``idx`` ([K, 3] array of
+    (l, j, i)): the same steps as fdkod_cone, restricted to the warped rows
+    the voxels read and the detector rows those are resampled from."""
+    p_count, nv, n = proj.shape
+    nz = n if nz is None else nz
+    idx = np.asarray(idx)
+    sqs, betas, betas_dec = plan(n, p_count, r, s, k)
+    weights = decimation_weights(p_count, len(betas_dec), window, taps)
+    qid = np.array([square_of(n, s, i, j) for (_, j, i) in idx])
+    c, cz = g.centre(n), g.centre(nz)
+    groups, det_all = [], []
+    for q in np.unique(qid):
+        sel = qid == q
+        x, y, z = idx[sel, 2] - c, idx[sel, 1] - c, idx[sel, 0] - cz
+        warped, det = cone_rows_for_points(n, nv, r, sqs[q], betas, betas_dec, x, y, z)
+        groups.append((q, sel, (x, y, z), warped))
+        det_all.append(det)
+    rows = np.unique(np.concatenate(det_all + [np.zeros(0, np.int64)]))
+    frows = fdk_mod.filter_rows(proj, r, rows)
+    if store is not None:
+        frows.data = store(frows.data)
+    cv = g.centre(n)
+    out = np.zeros(len(idx))
+    for q, sel, (x, y, z), warped in groups:
+        sq = sqs[q]
+        ac = centre_track(sq, betas, r)
+        j = np.arange(sq.width, dtype=np.float64)
+        s_sub = np.zeros((len(betas), len(warped), sq.width))
+        for p, beta in enumerate(betas):
+            rp = (warped - cv) * cone_row_scale(sq, beta, r) + cv
+            s_sub[p] = sample_vu(frows.data[p], frows.slot, frows.nv, rp[:, None],
+                                 (ac[p] + sq.u0 + j)[None, :], interp)
+        y_sub = decimate(s_sub, weights)
+        if store is not None:
+            y_sub = store(y_sub)
+        slot = np.full(nv, -1, dtype=np.int64)
+        slot[warped] = np.arange(len(warped))
+        out[sel] = backproject_square_cone(y_sub, nv, sq, betas_dec, r, n, x, y, z, slot)
     return out
 
 

@@ -33,8 +33,8 @@ class DeviceRows:
         return self.t.index_select(1, idx).cpu().numpy()
 
 
-def reconstruct(proj, wl, s, store):
-    with pkg.Plan(wl.n, wl.p, wl.r, s=s, skip=wl.k, nz=wl.nzv, store=store) as plan:
+def reconstruct(proj, wl, s, store, **knobs):
+    with pkg.Plan(wl.n, wl.p, wl.r, s=s, skip=wl.k, nz=wl.nzv, store=store, **knobs) as plan:
         filt = plan.empty_filtered()
         vol = plan.empty_volume()
         ws = plan.empty_workspace()
@@ -98,3 +98,26 @@ def test_n2000_sampled_voxels(store, tol):
     ref = ofdkod.fdkod_points(DeviceRows(proj), wl.r, s, wl.k, idx, nz=wl.nzv)
     err, _ = report(f"cone2000_p720 s={s} {store} {len(idx)} voxels", got, ref)
     assert err <= tol
+
+
+@pytest.mark.parametrize("knobs", [dict(rows="cone"), dict(decim="sinc", taps=4, interp="cubic")])
+def test_n2000_sampled_voxels_extensions(knobs):
+    """cone2000_p720, s = 4, BF16 storage (the bench's configuration) with
+    cone-corrected rows, or with the windowed sinc and the cubic shift."""
+    wl = configs.C5
+    s = max(wl.s)
+    proj = scan_on_gpu(wl)
+    idx = _clusters(wl.n, wl.nzv)
+    vol = reconstruct(proj, wl, s, "bf16", **knobs)
+    got = vol[idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy()
+    del vol
+    torch.cuda.empty_cache()
+    log(f"oracle on {len(idx)} voxels of cone2000_p720 with {knobs}")
+    ok = {"window": knobs.get("decim", "triangle"), "taps": knobs.get("taps", 2),
+          "interp": knobs.get("interp", "linear")}
+    if knobs.get("rows") == "cone":
+        ref = ofdkod.fdkod_cone_points(DeviceRows(proj), wl.r, s, wl.k, idx, nz=wl.nzv, **ok)
+    else:
+        ref = ofdkod.fdkod_points(DeviceRows(proj), wl.r, s, wl.k, idx, nz=wl.nzv, **ok)
+    err, _ = report(f"cone2000_p720 s={s} bf16 {knobs} {len(idx)} voxels", got, ref)
+    assert err <= 2e-3

@@ -99,3 +99,18 @@ def test_cone_correction_reduces_off_midplane_error():
     plain = _rel(fdkod.fdkod(proj, r, s, 0, slices=sl), ref)
     cone = _rel(fdkod.fdkod_cone(proj, r, s, 0, slices=sl), ref)
     assert cone <= 0.7 * plain, (plain, cone)
+
+
+@pytest.mark.parametrize("knobs", [{}, dict(window="sinc", taps=4, interp="cubic")])
+def test_points_form_equals_volume_form(knobs):
+    """The sampled-voxel form (only the rows the voxels need) gives the volume
+    form's values, top and bottom slices and a ragged square included."""
+    n, nz, p, r, s = 40, 36, 48, 96.0, 2
+    proj = phantom.project(phantom.random_ellipsoids(6, 8), n, p, r).double().numpy()
+    vol = fdkod.fdkod_cone(proj, r, s, 0, nz=nz, **knobs)
+    rng = np.random.default_rng(4)
+    idx = np.stack([rng.integers(0, nz, 25), rng.integers(0, n, 25), rng.integers(0, n, 25)], axis=1)
+    idx = np.concatenate([idx, [[0, 3, 37], [nz - 1, 39, 0], [nz // 2, 20, 20]]])
+    got = fdkod.fdkod_cone_points(proj, r, s, 0, idx, nz=nz, **knobs)
+    want = vol[idx[:, 0], idx[:, 1], idx[:, 2]]
+    assert np.allclose(got, want, rtol=1e-12, atol=1e-12 * np.max(np.abs(vol)))
