@@ -283,7 +283,8 @@ DecimVol decim_args_band(const fdkod_plan_s* pl, const void* filt, void* ws, int
     a.v0 = v0;
     a.nv = nv;
     a.tasks_per_sq = dec_tasks_per_sq(pl->wmax, chunks);
-    a.ntasks = pl->nsq * nv * a.tasks_per_sq;
+    const int rpt = decim_rows_per_task(pl->cone != 0, pl->cubic != 0, chunks);
+    a.ntasks = pl->nsq * ((nv + rpt - 1) / rpt) * a.tasks_per_sq;
     a.chunks = chunks;
     return a;
 }

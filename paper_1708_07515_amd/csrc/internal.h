@@ -82,7 +82,7 @@ struct DecimVol {
     int n, p, pd, nsq;
     int v0, nv;             // detector rows [v0, v0 + nv): filt is [P][nv][N], ws blocks [P'][nv][W_q]
     int tasks_per_sq;       // column groups per square
-    int ntasks;             // nsq * nv * tasks_per_sq
+    int ntasks;             // nsq * ceil(nv / rows per task) * tasks_per_sq
     int chunks;             // 64-column chunks per wave (1, 2, 4 or 8)
 };
 
@@ -214,5 +214,11 @@ hipError_t launch_adamw(const AdamArgs& a, hipStream_t st);
 constexpr int kTileXY = 16;      // voxels per tile side in x and y
 constexpr int kDecimUnroll = 8;  // the decimation schedule is padded to a multiple of this
 constexpr int kDecimMaxChunksWide = 4;  // column chunks per task when more than 2 windows are open
+// detector rows per decimation task: two for one column chunk with the
+// linear shift of detector rows (squares narrower than a wavefront: the two
+// rows share the step's tables and fill more of the wave's work), else one
+__host__ __device__ constexpr int decim_rows_per_task(bool cone, bool cubic, int chunks) {
+    return !cone && !cubic && chunks == 1 ? 2 : 1;
+}
 
 }  // namespace fdkod

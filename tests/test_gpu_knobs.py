@@ -66,20 +66,23 @@ def test_knobs_match_oracle(case):
     assert metrics.rel_rmse(plain, ref) > 10 * err, "the knobs left the result unchanged"
 
 
-def test_chunk_count_does_not_change_the_result():
-    """Several column groups per square and several open windows: every
-    chunk count the kernels exist for gives the same bits; 8 chunks do not
-    exist with more than two windows."""
-    n, p, r = 200, 120, 800.0
-    proj = scan(n, p, r, 8, 5)
-    knobs = dict(decim="sinc", taps=6, interp="cubic")
-    vols = [run(proj, n, p, r, 1, chunks=c, **knobs) for c in (1, 2, 4)]
-    assert all(np.array_equal(vols[0], v) for v in vols[1:])
-    with pkg.Plan(n, p, r, s=1, **knobs) as plan:
+@pytest.mark.parametrize("knobs,chunks", [(dict(decim="sinc", taps=6, interp="cubic"), (1, 2, 4)),
+                                          ({}, (1, 2, 4, 8))])
+def test_chunk_count_does_not_change_the_result(knobs, chunks):
+    """Several column groups per square, several open windows, and (the plain
+    linear shift at one chunk) two detector rows per task: every chunk count
+    the kernels exist for gives the same bits; 8 chunks do not exist with more
+    than two windows."""
+    for n, p, r, s in ((200, 120, 800.0, 1), (97, 90, 300.0, 3)):
+        proj = scan(n, p, r, 8, 5)
+        vols = [run(proj, n, p, r, s, chunks=c, **knobs) for c in chunks]
+        assert all(np.array_equal(vols[0], v) for v in vols[1:]), (n, s)
+    with pkg.Plan(200, 120, 800.0, s=1, **knobs) as plan:
         assert plan.info.max_width > 64           # several column groups at 1 chunk
-        with pytest.raises(pkg.FdkodError) as ei:
-            plan.set_tuning(decim_chunks=8)
-        assert ei.value.code == "E_UNSUPPORTED"
+        if knobs:
+            with pytest.raises(pkg.FdkodError) as ei:
+                plan.set_tuning(decim_chunks=8)
+            assert ei.value.code == "E_UNSUPPORTED"
 
 
 def test_streamed_knobs_equal_in_memory():
