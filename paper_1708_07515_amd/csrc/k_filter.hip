@@ -79,6 +79,21 @@ __device__ __forceinline__ void dft16(float2 (&v)[16]) {
         for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[4 * k1 + k2];
 }
 
+// Synchronisation of the TP threads of one transform.  A transform of at
+// most 64 threads lives in one wavefront, whose LDS accesses complete in
+// program order, so only the compiler has to be kept from moving them across
+// (the other transforms of the workgroup need not wait); larger transforms
+// span waves and take a workgroup barrier.
+template <int TP>
+__device__ __forceinline__ void transform_sync() {
+    if constexpr (TP <= 64) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        __syncthreads();
+    }
+}
+
 // One Stockham stage of radix R (16, 4 or 2) at stride NS, TP threads.  The
 // first stage (NS = 1) needs no twiddles.
 template <int R, int M, int TP, int NS>
@@ -120,7 +135,7 @@ __device__ __forceinline__ void fft_stage(float2* z, int t, const float2* __rest
             }
         }
     }
-    __syncthreads();
+    transform_sync<TP>();
 #pragma unroll
     for (int b = 0; b < BPT; ++b) {
         const int j = t + b * TP;
@@ -131,7 +146,7 @@ __device__ __forceinline__ void fft_stage(float2* z, int t, const float2* __rest
             for (int r = 0; r < R; ++r) z[pidx(dst + r * ns)] = v[b][r];
         }
     }
-    __syncthreads();
+    transform_sync<TP>();
 }
 
 // The stages from stride NS on: radix 16 while at least four bits remain,
@@ -236,7 +251,7 @@ void k_filter(FilterArgs a) {
     }
     const float last0 = has0 ? p0[n - 1] * weight(n - 1, rb0) : 0.0f;
     const float last1 = has1 ? p1[n - 1] * weight(n - 1, rb1) : 0.0f;
-    __syncthreads();
+    transform_sync<TP>();
     fft_lds<LOGM, TP>(z, t, a.twiddle);
     // tables (L2-resident) are requested in one batch before their first use
     float2 gr[IT];
@@ -253,7 +268,7 @@ void k_filter(FilterArgs a) {
             z[pidx(k)] = make_float2(v.x, -v.y);      // conj(Z G)
         }
     }
-    __syncthreads();
+    transform_sync<TP>();
     fft_lds<LOGM, TP>(z, t, a.twiddle);
     float gtl[IT];
 #pragma unroll
