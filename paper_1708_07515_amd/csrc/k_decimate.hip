@@ -5,11 +5,11 @@
 //
 //   Y_q[m][v][j] = sum_p w[m][p] * Lin(q[p][v][.], a_c(beta_p) + u0_q + j)
 //
-// One wavefront per task (square, row, group of 64*CH local columns).  The
-// wavefront walks the projections once, in the order of a host-built
-// schedule; each projection feeds at most two open decimation windows, held
-// in two accumulators per column, and a window is written out as soon as its
-// last projection has been added.  The shift's fractional part is the same
+// One wavefront per task (square, one or two rows, group of 64*CH local
+// columns).  The wavefront walks the projections once, in the order of a
+// host-built schedule; with the triangle each projection feeds at most two
+// open decimation windows, held in two accumulators per column, and a window
+// is written out as soon as its last projection has been added.  The shift's fractional part is the same
 // for every column of a (square, projection), so each cropped sample costs
 // one interpolation and two multiply-adds.  Rows are read with unit stride
 // (coalesced); the re-reads of a row by the squares that overlap it hit L2
