@@ -19,6 +19,10 @@ template <> struct Store<0> {
     static __device__ __forceinline__ float raw(__amdgpu_buffer_rsrc_t r, int off) {
         return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
     }
+    // store through a raw buffer resource at a byte offset (dropped when out of range)
+    static __device__ __forceinline__ void put_raw(__amdgpu_buffer_rsrc_t r, int off, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
+    }
 };
 
 template <> struct Store<1> {
@@ -30,6 +34,9 @@ template <> struct Store<1> {
         const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
         return (float)__builtin_bit_cast(_Float16, h);
     }
+    static __device__ __forceinline__ void put_raw(__amdgpu_buffer_rsrc_t r, int off, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r, off, 0, 0);
+    }
 };
 
 template <> struct Store<2> {
@@ -38,18 +45,20 @@ template <> struct Store<2> {
     static __device__ __forceinline__ float load(const T* p, size_t i) {
         return __uint_as_float(((uint32_t)p[i]) << 16);
     }
-    static __device__ __forceinline__ void put(T* p, size_t i, float v) {
+    static __device__ __forceinline__ uint16_t enc(float v) {
         uint32_t b = __float_as_uint(v);
-        if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu)) {
-            p[i] = (uint16_t)((b >> 16) | 0x40u);    // quiet NaN
-            return;
-        }
+        if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu))
+            return (uint16_t)((b >> 16) | 0x40u);     // quiet NaN
         b += 0x7FFFu + ((b >> 16) & 1u);              // round to nearest even
-        p[i] = (uint16_t)(b >> 16);
+        return (uint16_t)(b >> 16);
     }
+    static __device__ __forceinline__ void put(T* p, size_t i, float v) { p[i] = enc(v); }
     static __device__ __forceinline__ float raw(__amdgpu_buffer_rsrc_t r, int off) {
         const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
         return __uint_as_float(((uint32_t)h) << 16);
+    }
+    static __device__ __forceinline__ void put_raw(__amdgpu_buffer_rsrc_t r, int off, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)enc(v), r, off, 0, 0);
     }
 };
 

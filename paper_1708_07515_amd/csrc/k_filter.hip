@@ -215,22 +215,46 @@ void k_filter(FilterArgs a) {
     const float rb0 = rr + b0 * b0, rb1 = rr + b1 * b1;
     const float* p0 = a.proj + (size_t)r0 * n;
     const float* p1 = a.proj + (size_t)r1 * n;
+    // the argument is at least R^2, a normal number, so the hardware
+    // reciprocal square root needs none of the library's denormal scaling
     auto weight = [&](int u, float rb) {
         const float au = (float)u - a.c;
-        return a.r * rsqrtf(rb + au * au);
+        return a.r * __builtin_amdgcn_rsqf(rb + au * au);
     };
     // every sample of the thread is requested before any is used: samples
     // u - 1 and u in one 8-byte load (u >= 1; u = 0 reads samples 0 and 1 and
     // uses the first), both rows, all positions
     constexpr int IT = (M + TP - 1) / TP;
     float2 q0[IT], q1[IT];
+    if constexpr (TP >= 64) {
+        // one row pair per wave or more waves per pair: the rows are wave-
+        // uniform, so they are read through buffer resources (32-bit offsets,
+        // no per-load addresses; an absent row has an empty range and reads
+        // zero, as does every sample past the row's end)
+        const int u0r = __builtin_amdgcn_readfirstlane(has0 ? r0 : 0);
+        const int u1r = __builtin_amdgcn_readfirstlane(has1 ? r1 : 0);
+        const __amdgpu_buffer_rsrc_t rs0 = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(a.proj + (size_t)u0r * n), (short)0, __builtin_amdgcn_readfirstlane(has0 ? n * 4 : 0),
+            0x00020000);
+        const __amdgpu_buffer_rsrc_t rs1 = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(a.proj + (size_t)u1r * n), (short)0, __builtin_amdgcn_readfirstlane(has1 ? n * 4 : 0),
+            0x00020000);
 #pragma unroll
-    for (int i = 0; i < IT; ++i) {
-        const int u = t + i * TP;
-        const int u1 = u > 0 ? u - 1 : 0;
-        const bool in = u < n;
-        q0[i] = (in && has0) ? *(const float2*)(p0 + u1) : make_float2(0.0f, 0.0f);
-        q1[i] = (in && has1) ? *(const float2*)(p1 + u1) : make_float2(0.0f, 0.0f);
+        for (int i = 0; i < IT; ++i) {
+            const int u = t + i * TP;
+            const int off = (u > 0 ? u - 1 : 0) * 4;
+            q0[i] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs0, off, 0, 0));
+            q1[i] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs1, off, 0, 0));
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const int u = t + i * TP;
+            const int u1 = u > 0 ? u - 1 : 0;
+            const bool in = u < n;
+            q0[i] = (in && has0) ? *(const float2*)(p0 + u1) : make_float2(0.0f, 0.0f);
+            q1[i] = (in && has1) ? *(const float2*)(p1 + u1) : make_float2(0.0f, 0.0f);
+        }
     }
     // pre-weighted first difference d[u] = p~[u] - p~[u-1] (zero-padded); the
     // difference at u = N is applied after the FFT
@@ -277,13 +301,36 @@ void k_filter(FilterArgs a) {
         gtl[i] = u < n ? a.gtail[u] : 0.0f;          // g[u - N]
     }
     typename S::T* out = (typename S::T*)a.out;
+    if constexpr (TP >= 64) {
+        // output rows through buffer resources likewise (an absent row's
+        // stores are dropped)
+        constexpr int ES = (int)sizeof(typename S::T);
+        const int u0r = __builtin_amdgcn_readfirstlane(has0 ? r0 : 0);
+        const int u1r = __builtin_amdgcn_readfirstlane(has1 ? r1 : 0);
+        const __amdgpu_buffer_rsrc_t ro0 = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(out + (size_t)u0r * n), (short)0, __builtin_amdgcn_readfirstlane(has0 ? n * ES : 0),
+            0x00020000);
+        const __amdgpu_buffer_rsrc_t ro1 = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(out + (size_t)u1r * n), (short)0, __builtin_amdgcn_readfirstlane(has1 ? n * ES : 0),
+            0x00020000);
 #pragma unroll
-    for (int i = 0; i < IT; ++i) {
-        const int u = t + i * TP;
-        if (u < n) {
-            const float2 v = z[pidx(u)];              // conj of the result
-            if (has0) S::put(out, (size_t)r0 * n + u, v.x - last0 * gtl[i]);
-            if (has1) S::put(out, (size_t)r1 * n + u, -v.y - last1 * gtl[i]);
+        for (int i = 0; i < IT; ++i) {
+            const int u = t + i * TP;
+            if (u < n) {
+                const float2 v = z[pidx(u)];          // conj of the result
+                S::put_raw(ro0, u * ES, v.x - last0 * gtl[i]);
+                S::put_raw(ro1, u * ES, -v.y - last1 * gtl[i]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const int u = t + i * TP;
+            if (u < n) {
+                const float2 v = z[pidx(u)];          // conj of the result
+                if (has0) S::put(out, (size_t)r0 * n + u, v.x - last0 * gtl[i]);
+                if (has1) S::put(out, (size_t)r1 * n + u, -v.y - last1 * gtl[i]);
+            }
         }
     }
 }
