@@ -75,7 +75,9 @@ typedef enum { FDKOD_F32 = 0, FDKOD_F16 = 1, FDKOD_BF16 = 2 } fdkod_dtype;
  *            filter): the ideal low-pass cut off at the decimated rate's
  *            Nyquist frequency, times a Hann window over `taps` decimated
  *            steps (even, 2..6; 0 selects 4), normalised per window; each
- *            projection feeds up to `taps` windows.  Needs P >= taps * D. */
+ *            projection feeds up to `taps` windows.  Needs P >= taps * D.
+ *            Not available to the learned decimation and batches
+ *            (FDKOD_E_UNSUPPORTED); the slab mode supports it. */
 typedef enum { FDKOD_DECIM_TRIANGLE = 0, FDKOD_DECIM_SINC = 1 } fdkod_decim;
 
 /* Rows of the decomposed data:
@@ -96,13 +98,14 @@ typedef enum { FDKOD_ROWS_DETECTOR = 0, FDKOD_ROWS_CONE = 1 } fdkod_rows;
  *  CUBIC   Keys' cubic convolution kernel with a = -1/2 (Catmull-Rom), four
  *          samples per cropped value, zero outside the detector (an
  *          extension: Sec. 2.2 notes that a more precise interpolation
- *          reduces smoothing). */
+ *          reduces smoothing).  Not available to the learned decimation and
+ *          batches (FDKOD_E_UNSUPPORTED); the slab mode supports it. */
 typedef enum { FDKOD_INTERP_LINEAR = 0, FDKOD_INTERP_CUBIC = 1 } fdkod_interp;
 
 /* Problem statement, after Sec. 2.1: N, P, R, s, and the skipped
  * decimation stages k of Sec. 2.2 (D = 2^(s-k), P' = ceil(P / D)). */
 typedef struct {
-    int32_t n;      /* detector width = height = volume side in x, y; 1..4096 */
+    int32_t n;      /* detector width = height = volume side in x, y; 2..4096 */
     int32_t nz;     /* volume slices; 0 means n */
     int32_t p;      /* projections over 360 degrees; 1..65536 */
     double r;       /* R of eq. (1), voxel units; must exceed (N-1)/sqrt(2) */
