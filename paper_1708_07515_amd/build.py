@@ -15,6 +15,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfdkod.so")
 
+# Per-file options.  The learned convolutions keep their MFMA accumulators in
+# ordinary VGPRs (no AGPR copies), which lowers their register count to five
+# waves per SIMD.
+FILE_FLAGS = {"k_learned.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
 
 def hipcc():
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc"):
@@ -35,7 +40,7 @@ def build(verbose=False, jobs=8):
     for src in srcs:
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
         objs.append(obj)
-        cmd = [hipcc()] + flags + ["-c", src, "-o", obj]
+        cmd = [hipcc()] + flags + FILE_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

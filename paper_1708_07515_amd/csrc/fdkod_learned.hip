@@ -52,7 +52,8 @@ fdkod_status fdkod_learned_decompose(fdkod_plan_t pl, const void* filt, void* ws
     if (st != FDKOD_OK) return st;
     if ((st = fdkod_decompose(pl, filt, ws, stream)) != FDKOD_OK) return st;
     const LearnedArgs a = learned_args(pl, filt, ws, nullptr, weights, nullptr);
-    HIP_TRY(launch_learned_fwd(a, pl->wmax, pl->store, (hipStream_t)stream), "learned decimation kernel launch");
+    HIP_TRY(launch_learned_fwd(a, pl->wmax, pl->d, pl->store, (hipStream_t)stream),
+            "learned decimation kernel launch");
     return FDKOD_OK;
 }
 

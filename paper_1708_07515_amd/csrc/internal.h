@@ -203,7 +203,8 @@ struct AdamArgs {
     float lr, beta1, beta2, eps, weight_decay;
 };
 
-hipError_t launch_learned_fwd(const LearnedArgs& a, int max_width, int store, hipStream_t st);
+// dfac: the decimation factor D (selects the row-reusing form when D | P, D >= 4)
+hipError_t launch_learned_fwd(const LearnedArgs& a, int max_width, int dfac, int store, hipStream_t st);
 hipError_t launch_learned_bwd(const LearnedArgs& a, int store, hipStream_t st);
 hipError_t launch_bp_adjoint(const AdjArgs& a, hipStream_t st);
 hipError_t launch_residual(const float* f, const float* ref, float* r, double* loss, int64_t count,

@@ -98,7 +98,7 @@ __device__ __forceinline__ void learned_setup(const LearnedArgs& a, int q, int u
 // span exactly one detector row, so samples outside the detector, and every
 // sample of a column outside [0, W) (given a negative offset), read zero.
 template <int STORE>
-__device__ __forceinline__ void s_fetch_rows(const LearnedArgs& a, const LearnedSmem& sm, int v, int c, int jj,
+__device__ __forceinline__ void s_fetch_rows(const LearnedArgs& a, const float* o_tab, int v, int c, int jj,
                                              bool valid, const int offr[9], float x0[9], float x1[9],
                                              float ph[9]) {
     using S = Store<STORE>;
@@ -108,7 +108,7 @@ __device__ __forceinline__ void s_fetch_rows(const LearnedArgs& a, const Learned
     for (int t = 0; t < 9; ++t) {
         int p = c + offr[t];
         if (p >= a.p) p -= a.p;
-        const float o = sm.o_tab[p];
+        const float o = o_tab[p];
         const float of = floorf(o);
         ph[t] = o - of;
         const __amdgpu_buffer_rsrc_t rs = row_rsrc((const T*)a.filt + ((size_t)p * a.n + v) * a.n, a.n);
@@ -170,14 +170,127 @@ __device__ __forceinline__ void load_weight_operands(const uint16_t* w, s4v w1op
     for (int i = 0; i < 4; ++i) b1v[i] = bf2f(w[kOffB1 + 4 * lg + i]);
 }
 
+// The forward pass keeps the nine S rows in a pair layout: entry x of row t
+// holds the BF16 values of staged columns x (low half) and x + 1 (high half),
+// so one 32-bit LDS load gives a lane two of its conv1 taps.  Its K order
+// groups the taps in horizontal pairs: pair pi = 3 a + e (a = 0..4, e = 0..2)
+// holds taps (a, 2e) and (a, 2e + 1), where tap (a, 5) has weight zero; pair
+// 15 is padding (weight zero, reads pair 0's finite values).  K slot 2 pi + h
+// is half h of pair pi.
+constexpr int kPP = 16 * ((kLearnedMaxWidth + 15) / 16) + 4;   // pitch in pairs (ntile * 16 + 4 read)
+static_assert(kPP >= kThreads + 1, "every staged column has a pair entry");
+
+struct FwdSmem {
+    float o_tab[kLearnedMaxP];
+    int off_tab[9];
+    uint32_t sp[9 * kPP];
+};
+
+// Weight operands of the forward pass in the pair K order, and the lane's
+// pair offsets into a tile of row pitch PP (pairs 8 ks + 2 lg and
+// 8 ks + 2 lg + 1).
+template <int PP>
+__device__ __forceinline__ void load_fwd_operands(const uint16_t* w, s4v w1op[2], s4v w2op[5], f4v& b1v,
+                                                  int poff[4]) {
+    const int lane = threadIdx.x & 63;
+    const int lr = lane & 15, lg = lane >> 4;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int pi = 8 * ks + 2 * lg + i / 2;
+            const int ta = pi / 3, tb = 2 * (pi % 3) + (i & 1);
+            w1op[ks][i] = pi < 15 && tb < 5 ? (short)w[kOffW1 + lr * 25 + ta * 5 + tb] : (short)0;
+            if ((i & 1) == 0) poff[2 * ks + i / 2] = pi < 15 ? ta * PP + 2 * (pi % 3) + lr : lr;
+        }
+#pragma unroll
+    for (int a2 = 0; a2 < 5; ++a2)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int ch = 4 * lg + i;                          // A[row = b2 = lr][k = channel]
+            w2op[a2][i] = lr < 5 ? (short)w[kOffW2 + ch * 25 + a2 * 5 + lr] : (short)0;
+        }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b1v[i] = bf2f(w[kOffB1 + 4 * lg + i]);
+}
+
+// Stage the thread's column x of the nine rows: the low half of pair x and
+// the high half of pair x - 1.
+__device__ __forceinline__ void s_stage_pairs(uint32_t* sp, int x, const float x0[9], const float x1[9],
+                                              const float ph[9]) {
+    uint16_t* h = reinterpret_cast<uint16_t*>(sp);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const uint16_t v = f2bf(fmaf(ph[t], x1[t] - x0[t], x0[t]));
+        h[2 * (t * kPP + x)] = v;
+        if (x > 0) h[2 * (t * kPP + x - 1) + 1] = v;
+    }
+}
+
+// ReLU of a conv1 output (FP32, bias included) as the BF16 B operand of
+// conv2.  Rounding commutes with ReLU, so the values are rounded first and
+// the negative BF16 codes (sign bit set: negative as 16-bit integers) are then
+// cleared by a packed integer maximum with zero.
+__device__ __forceinline__ s4v relu_bf16(f4v h) {
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+    typedef short s2v __attribute__((ext_vector_type(2)));
+    const s2v zero = {0, 0};
+    const s2v lo = __builtin_elementwise_max(
+        __builtin_bit_cast(s2v, __builtin_convertvector((f2v){h[0], h[1]}, bf2v)), zero);
+    const s2v hi = __builtin_elementwise_max(
+        __builtin_bit_cast(s2v, __builtin_convertvector((f2v){h[2], h[3]}, bf2v)), zero);
+    return (s4v){lo[0], lo[1], hi[0], hi[1]};
+}
+
+// One 16-column tile of the forward pass for the nine S rows starting at sp
+// (pair layout, row pitch PP): conv1 at the five dilated angles (ten
+// independent MFMAs, the bias as the initial accumulator), ReLU, conv2; Q
+// rows 0..4 go to qt (row pitch QP, column c at index c + 2) for the columns
+// inside [0, W) only: outside, A and hence Q are zero, and the Q tile keeps
+// the zeros it was cleared to.
+template <int PP, int QP>
+__device__ __forceinline__ void fwd_tile(const uint32_t* sp, float* qt, int col0, int width, const int poff[4],
+                                         const s4v w1op[2], const s4v w2op[5], f4v b1v) {
+    const int lane = threadIdx.x & 63;
+    const int lr = lane & 15, lg = lane >> 4;
+    const uint32_t* pb[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pb[k] = sp + col0 + poff[k];
+    f4v h[5];
+#pragma unroll
+    for (int a2 = 0; a2 < 5; ++a2) h[a2] = b1v;
+#pragma unroll
+    for (int a2 = 0; a2 < 5; ++a2)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+            const u2v d = {pb[2 * ks][a2 * PP], pb[2 * ks + 1][a2 * PP]};
+            h[a2] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1op[ks], __builtin_bit_cast(s4v, d), h[a2], 0, 0, 0);
+        }
+    f4v qacc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int a2 = 0; a2 < 5; ++a2)
+        qacc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w2op[a2], relu_bf16(h[a2]), qacc, 0, 0, 0);
+    if (col0 + lr < width) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int bb = 4 * lg + i;
+            if (bb < 5) qt[bb * QP + col0 + lr + 2] = qacc[i];
+        }
+    }
+}
+
 // Forward (inference): Y(m) += R(m) for every decimated angle of one
 // (square, row).  Thread t stages column t - 2 of the tile and owns output
-// column t.
+// column t; the waves share the 16-column tiles.  This form fetches the nine
+// S rows of every angle; k_learned_fwd_ring below reuses them when the
+// decimated angles fall on original ones.
 template <int STORE>
 __global__ __launch_bounds__(kThreads) void k_learned_fwd(LearnedArgs a) {
     using S = Store<STORE>;
     using T = typename S::T;
-    __shared__ LearnedSmem sm;
+    __shared__ FwdSmem sm;
     __shared__ float q_tile[5 * kSP];
     const int task = blockIdx.x;
     if (task >= a.ntasks) return;
@@ -187,12 +300,17 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd(LearnedArgs a) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lg = lane >> 4;
     s4v w1op[2], w2op[5];
-    float b1v[4];
-    int toff[8];
-    load_weight_operands(a.w, w1op, w2op, b1v, toff);
+    f4v b1v;
+    int poff[4];
+    load_fwd_operands<kPP>(a.w, w1op, w2op, b1v, poff);
     const float b2 = bf2f(a.w[kOffB2]);
     const int ntile = (width + 15) >> 4;
-    learned_setup(a, q, u0, sm);
+    for (int p = threadIdx.x; p < a.p; p += kThreads) sm.o_tab[p] = a.ac_p[(size_t)q * a.p + p] + (float)u0;
+    if (threadIdx.x < 9) {
+        int off = ((int)threadIdx.x - 4) * a.d % a.p;
+        sm.off_tab[threadIdx.x] = off < 0 ? off + a.p : off;
+    }
+    for (int e = threadIdx.x; e < 9 * kPP; e += kThreads) sm.sp[e] = 0u;
     for (int e = threadIdx.x; e < 5 * kSP; e += kThreads) q_tile[e] = 0.0f;
     const int col = threadIdx.x;               // staged column index (local column col - 2)
     const int jj = col - 2;
@@ -209,36 +327,20 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd(LearnedArgs a) {
     for (int t = 0; t < 9; ++t) offr[t] = __builtin_amdgcn_readfirstlane(sm.off_tab[t]);
 
     float x0[9], x1[9], ph[9];
-    s_fetch_rows<STORE>(a, sm, v, cw.c, jj, valid, offr, x0, x1, ph);
+    s_fetch_rows<STORE>(a, sm.o_tab, v, cw.c, jj, valid, offr, x0, x1, ph);
     float y_cur = j < width ? S::load(ws, yrow + j) : 0.0f;
-    if (stager) s_stage_rows(sm, col, x0, x1, ph);
+    if (stager) s_stage_pairs(sm.sp, col, x0, x1, ph);
     __syncthreads();
     for (int m = 0; m < a.pd; ++m) {
         const bool more = m + 1 < a.pd;
         float y_next = 0.0f;
         if (more) {
             cw.next();
-            s_fetch_rows<STORE>(a, sm, v, cw.c, jj, valid, offr, x0, x1, ph);
+            s_fetch_rows<STORE>(a, sm.o_tab, v, cw.c, jj, valid, offr, x0, x1, ph);
             if (j < width) y_next = S::load(ws, yrow + (size_t)(m + 1) * yplane + j);
         }
-        for (int tile = wave; tile < ntile; tile += kThreads / 64) {
-            const int col0 = tile * 16;
-            const bool cin = col0 + lr < width;
-            f4v qacc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int a2 = 0; a2 < 5; ++a2) {
-                const f4v h = conv1_tile(sm.s_tile, a2, col0, toff, w1op);
-                f4v act;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) act[i] = cin ? fmaxf(h[i] + b1v[i], 0.0f) : 0.0f;
-                qacc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w2op[a2], f2bf4(act), qacc, 0, 0, 0);
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int bb = 4 * lg + i;
-                if (bb < 5) q_tile[bb * kSP + col0 + lr + 2] = qacc[i];
-            }
-        }
+        for (int tile = wave; tile < ntile; tile += kThreads / 64)
+            fwd_tile<kPP, kSP>(sm.sp, q_tile, tile * 16, width, poff, w1op, w2op, b1v);
         __syncthreads();
         if (j < width) {
             float r = b2;
@@ -246,9 +348,144 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd(LearnedArgs a) {
             for (int bb = 0; bb < 5; ++bb) r += q_tile[bb * kSP + j + bb];
             S::put(ws, yrow + (size_t)m * yplane + j, y_cur + r);
         }
-        if (more && stager) s_stage_rows(sm, col, x0, x1, ph);
+        if (more && stager) s_stage_pairs(sm.sp, col, x0, x1, ph);
         y_cur = y_next;
         __syncthreads();
+    }
+}
+
+// Row reuse.  When D divides P and D >= 4 (so d = D / 4), c(m) = m D and the
+// nine S rows of angle m are the rows u = 4m .. 4m + 8 of the sequence
+// p(u) = (u - 4) d mod P: consecutive angles share five rows.  The rows live
+// in a ring of 16 LDS slots, row u in slot u mod 16, with slots 0..8 mirrored
+// at 16..24 so that every window of nine is contiguous.  Each angle fetches
+// its successor's four new rows and stages them while its own products run
+// (their slots, and mirrors, lie outside its window), and the Q tile
+// alternates between two buffers, so one barrier per angle orders the whole
+// pipeline.  PW: the widest square's tiles (128 or 256 columns).
+constexpr int kRing = 16;
+constexpr int kRingSlots = kRing + 9;
+
+template <int PW>
+struct RingSmem {
+    static constexpr int kPitch = PW + 4;   // pairs: a tile reads up to index 16 ntile + 3
+    uint32_t sp[kRingSlots * kPitch];
+    float qb[2][5 * kPitch];                // Q rows: columns -2 .. 16 ntile + 1
+};
+static_assert(sizeof(RingSmem<256>) + 4 * kLearnedMaxP <= 65536, "ring tile fits the LDS of a workgroup");
+
+// Row p of S at the thread's staged column (local column jj): the two
+// detector samples and the interpolation fraction (zero outside the row and
+// for columns outside [0, W), as s_fetch_rows).
+template <int STORE>
+__device__ __forceinline__ void ring_fetch(const LearnedArgs& a, const float* o_tab, int v, int p, int jj,
+                                           bool valid, float& x0, float& x1, float& ph) {
+    using S = Store<STORE>;
+    using T = typename S::T;
+    constexpr int ES = (int)sizeof(T);
+    const float o = o_tab[p];
+    const float of = floorf(o);
+    ph = o - of;
+    const __amdgpu_buffer_rsrc_t rs = row_rsrc((const T*)a.filt + ((size_t)p * a.n + v) * a.n, a.n);
+    const int off0 = valid ? ((int)of + jj) * ES : -4 * ES;
+    int off1 = off0 + ES;
+    asm volatile("" : "+v"(off1));   // two separately range-checked loads, never one wider load
+    x0 = S::raw(rs, off0);
+    x1 = S::raw(rs, off1);
+}
+
+// Stage the thread's column x of one row into ring slot `slot` (and its
+// mirror): the low half of pair x and the high half of pair x - 1.
+template <int PP>
+__device__ __forceinline__ void ring_stage(uint32_t* sp, int slot, int x, float x0, float x1, float ph) {
+    uint16_t* h = reinterpret_cast<uint16_t*>(sp);
+    const uint16_t val = f2bf(fmaf(ph, x1 - x0, x0));
+    h[2 * (slot * PP + x)] = val;
+    if (x > 0) h[2 * (slot * PP + x - 1) + 1] = val;
+    if (slot < 9) {
+        h[2 * ((slot + kRing) * PP + x)] = val;
+        if (x > 0) h[2 * ((slot + kRing) * PP + x - 1) + 1] = val;
+    }
+}
+
+template <int STORE, int PW>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_learned_fwd_ring(LearnedArgs a) {
+    using S = Store<STORE>;
+    using T = typename S::T;
+    using R = RingSmem<PW>;
+    constexpr int PP = R::kPitch;
+    __shared__ R sm;
+    extern __shared__ float o_tab[];     // [P]: a_c(beta_p) + u0
+    const int task = blockIdx.x;
+    if (task >= a.ntasks) return;
+    const int q = task % a.nsq, v = task / a.nsq;
+    const int2 gd = a.grid[q];
+    const int u0 = gd.x, width = gd.y;
+    const int wave = threadIdx.x >> 6;
+    s4v w1op[2], w2op[5];
+    f4v b1v;
+    int poff[4];
+    load_fwd_operands<PP>(a.w, w1op, w2op, b1v, poff);
+    const float b2 = bf2f(a.w[kOffB2]);
+    const int ntile = (width + 15) >> 4;
+    for (int p = threadIdx.x; p < a.p; p += kThreads) o_tab[p] = a.ac_p[(size_t)q * a.p + p] + (float)u0;
+    for (int e = threadIdx.x; e < kRingSlots * PP; e += kThreads) sm.sp[e] = 0u;
+    for (int e = threadIdx.x; e < 2 * 5 * PP; e += kThreads) (&sm.qb[0][0])[e] = 0.0f;
+    const int x = threadIdx.x;                 // staged column index (local column x - 2)
+    const int jj = x - 2;
+    const bool stager = x < width + 4;
+    const bool valid = jj >= 0 && jj < width;
+    T* ws = (T*)a.ws;
+    const size_t yrow = (size_t)a.squares[q].y_off_row * a.n + (size_t)v * width;   // + m n W + j
+    const size_t yplane = (size_t)a.n * width;
+    const int j = threadIdx.x;                                           // output column
+    const int d = a.d;
+    int pn = (a.p - (4 * d) % a.p) % a.p;      // p(0) = -4 d mod P
+    __syncthreads();
+    {
+        float x0[9], x1[9], ph[9];
+#pragma unroll
+        for (int u = 0; u < 9; ++u) {
+            ring_fetch<STORE>(a, o_tab, v, pn, jj, valid, x0[u], x1[u], ph[u]);
+            pn += d;
+            if (pn >= a.p) pn -= a.p;
+        }
+        if (stager) {
+#pragma unroll
+            for (int u = 0; u < 9; ++u) ring_stage<PP>(sm.sp, u, x, x0[u], x1[u], ph[u]);
+        }
+    }
+    float y_cur = j < width ? S::load(ws, yrow + j) : 0.0f;
+    __syncthreads();
+    for (int m = 0; m < a.pd; ++m) {
+        const bool more = m + 1 < a.pd;
+        float x0[4], x1[4], ph[4];
+        float y_next = 0.0f;
+        if (more) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                ring_fetch<STORE>(a, o_tab, v, pn, jj, valid, x0[k], x1[k], ph[k]);
+                pn += d;
+                if (pn >= a.p) pn -= a.p;
+            }
+            if (j < width) y_next = S::load(ws, yrow + (size_t)(m + 1) * yplane + j);
+        }
+        const uint32_t* win = sm.sp + ((4 * m) & (kRing - 1)) * PP;
+        float* qt = sm.qb[m & 1];
+        for (int tile = wave; tile < ntile; tile += kThreads / 64)
+            fwd_tile<PP, PP>(win, qt, tile * 16, width, poff, w1op, w2op, b1v);
+        if (more && stager) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) ring_stage<PP>(sm.sp, (4 * m + 9 + k) & (kRing - 1), x, x0[k], x1[k], ph[k]);
+        }
+        __syncthreads();
+        if (j < width) {
+            float r = b2;
+#pragma unroll
+            for (int bb = 0; bb < 5; ++bb) r += qt[bb * PP + j + bb];
+            S::put(ws, yrow + (size_t)m * yplane + j, y_cur + r);
+        }
+        y_cur = y_next;
     }
 }
 
@@ -312,7 +549,7 @@ __global__ __launch_bounds__(kThreads) void k_learned_bwd(LearnedArgs a) {
     for (int m = 0; m < a.pd; ++m) {
         {
             float x0[9], x1[9], ph[9];
-            s_fetch_rows<STORE>(a, sm, v, cw.c, jj, valid, offr, x0, x1, ph);
+            s_fetch_rows<STORE>(a, sm.o_tab, v, cw.c, jj, valid, offr, x0, x1, ph);
             if (stager) s_stage_rows(sm, col_s, x0, x1, ph);
             cw.next();
         }
@@ -486,8 +723,25 @@ __global__ void k_adamw(AdamArgs a) {
     a.w_bf16[i] = (uint16_t)f2bf(w);
 }
 
-hipError_t launch_learned_fwd(const LearnedArgs& a, int max_width, int store, hipStream_t st) {
+template <int STORE>
+void launch_fwd_ring(const LearnedArgs& a, int max_width, hipStream_t st) {
+    const size_t dyn = sizeof(float) * (size_t)a.p;
+    if (max_width <= 128)
+        hipLaunchKernelGGL((k_learned_fwd_ring<STORE, 128>), dim3(a.ntasks), dim3(kThreads), dyn, st, a);
+    else
+        hipLaunchKernelGGL((k_learned_fwd_ring<STORE, 256>), dim3(a.ntasks), dim3(kThreads), dyn, st, a);
+}
+
+hipError_t launch_learned_fwd(const LearnedArgs& a, int max_width, int dfac, int store, hipStream_t st) {
     if (max_width > kLearnedMaxWidth || a.p > kLearnedMaxP) return hipErrorInvalidValue;
+    if (dfac >= 4 && a.p % dfac == 0 && a.pd * dfac == a.p && a.d * 4 == dfac) {
+        switch (store) {
+            case 0: launch_fwd_ring<0>(a, max_width, st); break;
+            case 1: launch_fwd_ring<1>(a, max_width, st); break;
+            default: launch_fwd_ring<2>(a, max_width, st); break;
+        }
+        return hipGetLastError();
+    }
     switch (store) {
         case 0: hipLaunchKernelGGL(k_learned_fwd<0>, dim3(a.ntasks), dim3(kThreads), 0, st, a); break;
         case 1: hipLaunchKernelGGL(k_learned_fwd<1>, dim3(a.ntasks), dim3(kThreads), 0, st, a); break;

@@ -11,7 +11,9 @@ from oracle import fdk as ofdk, fdkod as ofdkod, learned, metrics, storage
 
 pytestmark = pytest.mark.gpu
 
-# N, P, R, s, k: D = 4 (d = 1), D = 8 (d = 2), a ragged N with a skipped stage
+# N, P, R, s, k: D = 4 (d = 1), D = 8 (d = 2), a ragged N with a skipped stage.
+# The first two have D | P (the decimated angles fall on original ones: the
+# row-reusing kernel); the third does not (the general kernel).
 CASES = [(32, 48, 128.0, 2, 0), (40, 64, 160.0, 3, 0), (37, 50, 150.0, 3, 1)]
 
 
@@ -112,6 +114,39 @@ def test_learned_forward_matches_oracle(case):
     assert max(errs_r) <= 1e-3
     assert max(errs_y) <= 1e-3
     plan.close()
+
+
+def test_learned_forward_wide_squares():
+    """Squares 122..148 columns wide (the wider tile pitch of the row-reusing
+    kernel, tiles shared unevenly by the waves), D = 4 | P; checked on a few
+    detector rows against the oracle."""
+    n, p, r, s, k = 320, 48, 640.0, 2, 0
+    net = random_net(5)
+    proj = scan(n, p, r, 6, 29)
+    with pkg.Plan(n, p, r, s=s, skip=k) as plan:
+        filt = plan.empty_filtered()
+        plan.filter(proj.to(DEV), filt)
+        ws_plain, ws_l = plan.empty_workspace(), plan.empty_workspace()
+        plan.decompose(filt, ws_plain)
+        plan.learned_decompose(filt, ws_l, device_weights(net))
+        torch.cuda.synchronize()
+        widths = [int(w) for w in plan.get_bounds()["width"]]
+        got_y = square_views(plan, _as(plan, ws_l))
+        got_t = square_views(plan, _as(plan, ws_plain))
+    assert max(widths) > 128 and min(widths) < 128
+    rows = np.array([0, 101, 160, 247, n - 1])
+    sqs, betas, betas_dec = ofdkod.plan(n, p, r, s, k)
+    frows = ofdk.filter_rows(proj.numpy().astype(np.float64), r, rows)
+    d_factor = ofdkod.decimation_factor(s, k)
+    errs = []
+    for q, sq in enumerate(sqs):
+        assert sq.width == widths[q]
+        sub = np.moveaxis(ofdkod.crop_shift(frows, sq, betas, r, n), 0, 1)     # [rows, P, W]
+        r_or, _ = learned.forward(sub, net, d_factor, len(betas_dec), bf16=True)
+        gr = (got_y[q] - got_t[q]).numpy()[:, rows, :].transpose(1, 0, 2)
+        errs.append(metrics.rel_rmse(gr, r_or))
+    log(f"learned forward, wide squares {widths[0]}..{max(widths)}: R rel-RMSE max {max(errs):.2e}")
+    assert max(errs) <= 1e-3
 
 
 def test_zero_second_layer_is_plain_decimation():
