@@ -53,6 +53,13 @@ __device__ __forceinline__ uint16_t f2bf(float v) { return __builtin_bit_cast(ui
 
 __device__ __forceinline__ s4v f2bf4(f4v v) { return __builtin_bit_cast(s4v, __builtin_convertvector(v, bf4v)); }
 
+// Wait for every outstanding vector memory access of the wave (s_waitcnt
+// vmcnt(0); expcnt and lgkmcnt left at their maxima).  Placed after the
+// staging of prefetched rows, on every path: without it, loads whose only
+// consumer sits in a branch that a wave skipped stay pending in the
+// compiler's bookkeeping and later code waits on them.
+__device__ __forceinline__ void vmem_drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // c(m) = floor(m P / P' + 1/2) = floor((2 m P + P') / (2 P')), walked in m
 // with an integer quotient and remainder (c(m) < P for m < P').
 struct CentreWalk {
@@ -175,9 +182,9 @@ __device__ __forceinline__ void load_weight_operands(const uint16_t* w, s4v w1op
 // so one 32-bit LDS load gives a lane two of its conv1 taps.  Its K order
 // groups the taps in horizontal pairs: pair pi = 3 a + e (a = 0..4, e = 0..2)
 // holds taps (a, 2e) and (a, 2e + 1), where tap (a, 5) has weight zero; pair
-// 15 is padding (weight zero, reads pair 0's finite values).  K slot 2 pi + h
-// is half h of pair pi.
-constexpr int kPP = 16 * ((kLearnedMaxWidth + 15) / 16) + 4;   // pitch in pairs (ntile * 16 + 4 read)
+// (0, 3) pads the K dimension (weight zero; the entries beyond the staged
+// columns stay at the zeros the tile was cleared to).
+constexpr int kPP = 16 * ((kLearnedMaxWidth + 15) / 16) + 8;   // pitch in pairs (index 16 ntile + 5 read)
 static_assert(kPP >= kThreads + 1, "every staged column has a pair entry");
 
 struct FwdSmem {
@@ -186,32 +193,66 @@ struct FwdSmem {
     uint32_t sp[9 * kPP];
 };
 
-// Weight operands of the forward pass in the pair K order, and the lane's
-// pair offsets into a tile of row pitch PP (pairs 8 ks + 2 lg and
-// 8 ks + 2 lg + 1).
+// Operands of the forward pass, which runs on the K = 32 BF16 MFMA
+// (16x16x32: a lane of group g = lane / 16 holds eight K slots of its row or
+// column; the product pairs A's and B's slots of the same lane group and
+// element, so any K order common to both is valid).
+//   conv1: lane group g holds two dominoes of pairs, a horizontal one (pairs
+//          (a, e) and (a, e + 1), two entries apart) and a vertical one
+//          ((a, e) and (a + 1, e), one row apart), so that each is one
+//          two-address LDS load into consecutive registers.  The eight
+//          dominoes cover the 15 pairs and one padding pair (0, 3), i.e.
+//          taps (0, 6) and (0, 7), whose weights are zero like tap (a, 5).
+//          Slot (g, i): pair k = i / 2 of the group (H first, H second,
+//          V first, V second), half i % 2.
+//   conv2: K = two dilated angles x 16 channels, three products t = 0..2;
+//          slot (g, i) is channel 4 g + i % 4 of angle 2 t + i / 4 (angle 5:
+//          weight zero), which is exactly how conv1's outputs for angles 2 t
+//          and 2 t + 1 sit in the lane (channels 4 g .. 4 g + 3 of its column).
+typedef short s8v __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+// first pairs (a, e) of each group's horizontal and vertical domino
+__device__ constexpr int kDomH[4][2] = {{0, 0}, {0, 2}, {1, 1}, {4, 1}};
+__device__ constexpr int kDomV[4][2] = {{1, 0}, {2, 1}, {2, 2}, {3, 0}};
+
+struct FwdOperands {
+    bf8v w1;          // A of conv1: row = channel lr
+    bf8v w2[3];       // A of conv2: row = R offset b = lr (0..4 used)
+    f4v b1;           // conv1 bias of the lane's output channels 4 g .. 4 g + 3
+    int hoff, voff;   // the lane's dominoes in a tile of pitch PP (column lr)
+};
+
 template <int PP>
-__device__ __forceinline__ void load_fwd_operands(const uint16_t* w, s4v w1op[2], s4v w2op[5], f4v& b1v,
-                                                  int poff[4]) {
+__device__ __forceinline__ FwdOperands load_fwd_operands(const uint16_t* w) {
     const int lane = threadIdx.x & 63;
     const int lr = lane & 15, lg = lane >> 4;
+    FwdOperands op;
+    s8v w1;
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks)
+    for (int i = 0; i < 8; ++i) {
+        const int k = i / 2;
+        const int* dom = k < 2 ? kDomH[lg] : kDomV[lg];
+        const int ta = dom[0] + (k == 3 ? 1 : 0), e = dom[1] + (k == 1 ? 1 : 0);
+        const int tb = 2 * e + (i & 1);
+        w1[i] = tb < 5 ? (short)w[kOffW1 + lr * 25 + ta * 5 + tb] : (short)0;
+    }
+    op.w1 = __builtin_bit_cast(bf8v, w1);
+    op.hoff = kDomH[lg][0] * PP + 2 * kDomH[lg][1] + lr;
+    op.voff = kDomV[lg][0] * PP + 2 * kDomV[lg][1] + lr;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int pi = 8 * ks + 2 * lg + i / 2;
-            const int ta = pi / 3, tb = 2 * (pi % 3) + (i & 1);
-            w1op[ks][i] = pi < 15 && tb < 5 ? (short)w[kOffW1 + lr * 25 + ta * 5 + tb] : (short)0;
-            if ((i & 1) == 0) poff[2 * ks + i / 2] = pi < 15 ? ta * PP + 2 * (pi % 3) + lr : lr;
+    for (int t = 0; t < 3; ++t) {
+        s8v w2;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int a2 = 2 * t + i / 4, ch = 4 * lg + i % 4;
+            w2[i] = lr < 5 && a2 < 5 ? (short)w[kOffW2 + ch * 25 + a2 * 5 + lr] : (short)0;
         }
+        op.w2[t] = __builtin_bit_cast(bf8v, w2);
+    }
 #pragma unroll
-    for (int a2 = 0; a2 < 5; ++a2)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int ch = 4 * lg + i;                          // A[row = b2 = lr][k = channel]
-            w2op[a2][i] = lr < 5 ? (short)w[kOffW2 + ch * 25 + a2 * 5 + lr] : (short)0;
-        }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) b1v[i] = bf2f(w[kOffB1 + 4 * lg + i]);
+    for (int i = 0; i < 4; ++i) op.b1[i] = bf2f(w[kOffB1 + 4 * lg + i]);
+    return op;
 }
 
 // Stage the thread's column x of the nine rows: the low half of pair x and
@@ -244,34 +285,34 @@ __device__ __forceinline__ s4v relu_bf16(f4v h) {
 }
 
 // One 16-column tile of the forward pass for the nine S rows starting at sp
-// (pair layout, row pitch PP): conv1 at the five dilated angles (ten
-// independent MFMAs, the bias as the initial accumulator), ReLU, conv2; Q
-// rows 0..4 go to qt (row pitch QP, column c at index c + 2) for the columns
-// inside [0, W) only: outside, A and hence Q are zero, and the Q tile keeps
-// the zeros it was cleared to.
+// (pair layout, row pitch PP): conv1 at the five dilated angles (five
+// independent MFMAs, the bias as the initial accumulator), ReLU, conv2 (three
+// MFMAs); Q rows 0..4 go to qt (row pitch QP, column c at index c + 2) for
+// the columns inside [0, W) only: outside, A and hence Q are zero, and the Q
+// tile keeps the zeros it was cleared to.
 template <int PP, int QP>
-__device__ __forceinline__ void fwd_tile(const uint32_t* sp, float* qt, int col0, int width, const int poff[4],
-                                         const s4v w1op[2], const s4v w2op[5], f4v b1v) {
+__device__ __forceinline__ void fwd_tile(const uint32_t* sp, float* qt, int col0, int width,
+                                         const FwdOperands& op) {
+    typedef uint32_t u4v __attribute__((ext_vector_type(4)));
     const int lane = threadIdx.x & 63;
     const int lr = lane & 15, lg = lane >> 4;
-    const uint32_t* pb[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) pb[k] = sp + col0 + poff[k];
+    const uint32_t* ph = sp + col0 + op.hoff;
+    const uint32_t* pv = sp + col0 + op.voff;
     f4v h[5];
 #pragma unroll
-    for (int a2 = 0; a2 < 5; ++a2) h[a2] = b1v;
-#pragma unroll
-    for (int a2 = 0; a2 < 5; ++a2)
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            typedef uint32_t u2v __attribute__((ext_vector_type(2)));
-            const u2v d = {pb[2 * ks][a2 * PP], pb[2 * ks + 1][a2 * PP]};
-            h[a2] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1op[ks], __builtin_bit_cast(s4v, d), h[a2], 0, 0, 0);
-        }
+    for (int a2 = 0; a2 < 5; ++a2) {
+        const u4v d = {ph[a2 * PP], ph[a2 * PP + 2], pv[a2 * PP], pv[a2 * PP + PP]};
+        h[a2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.w1, __builtin_bit_cast(bf8v, d), op.b1, 0, 0, 0);
+    }
     f4v qacc = {0.0f, 0.0f, 0.0f, 0.0f};
+    const s4v zero = {0, 0, 0, 0};
 #pragma unroll
-    for (int a2 = 0; a2 < 5; ++a2)
-        qacc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w2op[a2], relu_bf16(h[a2]), qacc, 0, 0, 0);
+    for (int t = 0; t < 3; ++t) {
+        const s4v lo = relu_bf16(h[2 * t]);
+        const s4v hi = t < 2 ? relu_bf16(h[2 * t + 1]) : zero;
+        const s8v act = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        qacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(op.w2[t], __builtin_bit_cast(bf8v, act), qacc, 0, 0, 0);
+    }
     if (col0 + lr < width) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -299,10 +340,7 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd(LearnedArgs a) {
     const int u0 = gd.x, width = gd.y;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lg = lane >> 4;
-    s4v w1op[2], w2op[5];
-    f4v b1v;
-    int poff[4];
-    load_fwd_operands<kPP>(a.w, w1op, w2op, b1v, poff);
+    const FwdOperands op = load_fwd_operands<kPP>(a.w);
     const float b2 = bf2f(a.w[kOffB2]);
     const int ntile = (width + 15) >> 4;
     for (int p = threadIdx.x; p < a.p; p += kThreads) sm.o_tab[p] = a.ac_p[(size_t)q * a.p + p] + (float)u0;
@@ -330,6 +368,7 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd(LearnedArgs a) {
     s_fetch_rows<STORE>(a, sm.o_tab, v, cw.c, jj, valid, offr, x0, x1, ph);
     float y_cur = j < width ? S::load(ws, yrow + j) : 0.0f;
     if (stager) s_stage_pairs(sm.sp, col, x0, x1, ph);
+    vmem_drain();
     __syncthreads();
     for (int m = 0; m < a.pd; ++m) {
         const bool more = m + 1 < a.pd;
@@ -339,8 +378,11 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd(LearnedArgs a) {
             s_fetch_rows<STORE>(a, sm.o_tab, v, cw.c, jj, valid, offr, x0, x1, ph);
             if (j < width) y_next = S::load(ws, yrow + (size_t)(m + 1) * yplane + j);
         }
-        for (int tile = wave; tile < ntile; tile += kThreads / 64)
-            fwd_tile<kPP, kSP>(sm.sp, q_tile, tile * 16, width, poff, w1op, w2op, b1v);
+#pragma unroll
+        for (int k = 0; k < kPP / 64; ++k) {
+            const int tile = wave + 4 * k;
+            if (tile < ntile) fwd_tile<kPP, kSP>(sm.sp, q_tile, tile * 16, width, op);
+        }
         __syncthreads();
         if (j < width) {
             float r = b2;
@@ -349,6 +391,7 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd(LearnedArgs a) {
             S::put(ws, yrow + (size_t)m * yplane + j, y_cur + r);
         }
         if (more && stager) s_stage_pairs(sm.sp, col, x0, x1, ph);
+        vmem_drain();
         y_cur = y_next;
         __syncthreads();
     }
@@ -368,9 +411,10 @@ constexpr int kRingSlots = kRing + 9;
 
 template <int PW>
 struct RingSmem {
-    static constexpr int kPitch = PW + 4;   // pairs: a tile reads up to index 16 ntile + 3
+    static constexpr int kPitch = PW + 8;   // pairs: a tile reads up to index 16 ntile + 5
+    static constexpr int kQPitch = PW + 4;  // Q rows: columns -2 .. 16 ntile + 1
     uint32_t sp[kRingSlots * kPitch];
-    float qb[2][5 * kPitch];                // Q rows: columns -2 .. 16 ntile + 1
+    float qb[2][5 * kQPitch];
 };
 static_assert(sizeof(RingSmem<256>) + 4 * kLearnedMaxP <= 65536, "ring tile fits the LDS of a workgroup");
 
@@ -409,11 +453,11 @@ __device__ __forceinline__ void ring_stage(uint32_t* sp, int slot, int x, float 
 }
 
 template <int STORE, int PW>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_learned_fwd_ring(LearnedArgs a) {
+__global__ __launch_bounds__(kThreads) void k_learned_fwd_ring(LearnedArgs a) {
     using S = Store<STORE>;
     using T = typename S::T;
     using R = RingSmem<PW>;
-    constexpr int PP = R::kPitch;
+    constexpr int PP = R::kPitch, QP = R::kQPitch;
     __shared__ R sm;
     extern __shared__ float o_tab[];     // [P]: a_c(beta_p) + u0
     const int task = blockIdx.x;
@@ -422,15 +466,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
     const int2 gd = a.grid[q];
     const int u0 = gd.x, width = gd.y;
     const int wave = threadIdx.x >> 6;
-    s4v w1op[2], w2op[5];
-    f4v b1v;
-    int poff[4];
-    load_fwd_operands<PP>(a.w, w1op, w2op, b1v, poff);
+    const FwdOperands op = load_fwd_operands<PP>(a.w);
     const float b2 = bf2f(a.w[kOffB2]);
     const int ntile = (width + 15) >> 4;
     for (int p = threadIdx.x; p < a.p; p += kThreads) o_tab[p] = a.ac_p[(size_t)q * a.p + p] + (float)u0;
     for (int e = threadIdx.x; e < kRingSlots * PP; e += kThreads) sm.sp[e] = 0u;
-    for (int e = threadIdx.x; e < 2 * 5 * PP; e += kThreads) (&sm.qb[0][0])[e] = 0.0f;
+    for (int e = threadIdx.x; e < 2 * 5 * QP; e += kThreads) (&sm.qb[0][0])[e] = 0.0f;
     const int x = threadIdx.x;                 // staged column index (local column x - 2)
     const int jj = x - 2;
     const bool stager = x < width + 4;
@@ -454,6 +495,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
 #pragma unroll
             for (int u = 0; u < 9; ++u) ring_stage<PP>(sm.sp, u, x, x0[u], x1[u], ph[u]);
         }
+        vmem_drain();
     }
     float y_cur = j < width ? S::load(ws, yrow + j) : 0.0f;
     __syncthreads();
@@ -472,17 +514,23 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
         }
         const uint32_t* win = sm.sp + ((4 * m) & (kRing - 1)) * PP;
         float* qt = sm.qb[m & 1];
-        for (int tile = wave; tile < ntile; tile += kThreads / 64)
-            fwd_tile<PP, PP>(win, qt, tile * 16, width, poff, w1op, w2op, b1v);
+        // a fixed number of tile slots per wave (no inner loop: the prefetched
+        // rows stay in flight across the products)
+#pragma unroll
+        for (int k = 0; k < PW / 64; ++k) {
+            const int tile = wave + 4 * k;
+            if (tile < ntile) fwd_tile<PP, QP>(win, qt, tile * 16, width, op);
+        }
         if (more && stager) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) ring_stage<PP>(sm.sp, (4 * m + 9 + k) & (kRing - 1), x, x0[k], x1[k], ph[k]);
         }
+        vmem_drain();
         __syncthreads();
         if (j < width) {
             float r = b2;
 #pragma unroll
-            for (int bb = 0; bb < 5; ++bb) r += qt[bb * PP + j + bb];
+            for (int bb = 0; bb < 5; ++bb) r += qt[bb * QP + j + bb];
             S::put(ws, yrow + (size_t)m * yplane + j, y_cur + r);
         }
         y_cur = y_next;
