@@ -322,6 +322,23 @@ __device__ __forceinline__ void fwd_tile(const uint32_t* sp, float* qt, int col0
     }
 }
 
+// XCD-aware task order of the forward kernels.  Workgroups are dealt to the
+// XCDs round-robin (workgroup b to XCD b mod 8), so the workgroups of XCD x
+// take the detector rows v = x (mod 8), all squares of a row consecutively:
+// the overlapping crops of one detector row read the same filtered rows, and
+// that XCD's L2 then fetches them once.  Grid: nsq * 8 * ceil(N / 8); the
+// workgroups with v >= N exit at once.
+__device__ __forceinline__ bool fwd_task(const LearnedArgs& a, int& q, int& v) {
+    const int x = (int)blockIdx.x % kXcds, i = (int)blockIdx.x / kXcds;
+    q = i % a.nsq;
+    v = (i / a.nsq) * kXcds + x;
+    return v < a.n;
+}
+
+inline unsigned fwd_grid(const LearnedArgs& a) {
+    return (unsigned)a.nsq * kXcds * ((a.n + kXcds - 1) / kXcds);
+}
+
 // Forward (inference): Y(m) += R(m) for every decimated angle of one
 // (square, row).  Thread t stages column t - 2 of the tile and owns output
 // column t; the waves share the 16-column tiles.  This form fetches the nine
@@ -333,13 +350,11 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd(LearnedArgs a) {
     using T = typename S::T;
     __shared__ FwdSmem sm;
     __shared__ float q_tile[5 * kSP];
-    const int task = blockIdx.x;
-    if (task >= a.ntasks) return;
-    const int q = task % a.nsq, v = task / a.nsq;
+    int q, v;
+    if (!fwd_task(a, q, v)) return;
     const int2 gd = a.grid[q];
     const int u0 = gd.x, width = gd.y;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int lr = lane & 15, lg = lane >> 4;
+    const int wave = threadIdx.x >> 6;
     const FwdOperands op = load_fwd_operands<kPP>(a.w);
     const float b2 = bf2f(a.w[kOffB2]);
     const int ntile = (width + 15) >> 4;
@@ -460,9 +475,8 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd_ring(LearnedArgs a) {
     constexpr int PP = R::kPitch, QP = R::kQPitch;
     __shared__ R sm;
     extern __shared__ float o_tab[];     // [P]: a_c(beta_p) + u0
-    const int task = blockIdx.x;
-    if (task >= a.ntasks) return;
-    const int q = task % a.nsq, v = task / a.nsq;
+    int q, v;
+    if (!fwd_task(a, q, v)) return;
     const int2 gd = a.grid[q];
     const int u0 = gd.x, width = gd.y;
     const int wave = threadIdx.x >> 6;
@@ -775,9 +789,9 @@ template <int STORE>
 void launch_fwd_ring(const LearnedArgs& a, int max_width, hipStream_t st) {
     const size_t dyn = sizeof(float) * (size_t)a.p;
     if (max_width <= 128)
-        hipLaunchKernelGGL((k_learned_fwd_ring<STORE, 128>), dim3(a.ntasks), dim3(kThreads), dyn, st, a);
+        hipLaunchKernelGGL((k_learned_fwd_ring<STORE, 128>), dim3(fwd_grid(a)), dim3(kThreads), dyn, st, a);
     else
-        hipLaunchKernelGGL((k_learned_fwd_ring<STORE, 256>), dim3(a.ntasks), dim3(kThreads), dyn, st, a);
+        hipLaunchKernelGGL((k_learned_fwd_ring<STORE, 256>), dim3(fwd_grid(a)), dim3(kThreads), dyn, st, a);
 }
 
 hipError_t launch_learned_fwd(const LearnedArgs& a, int max_width, int dfac, int store, hipStream_t st) {
@@ -791,9 +805,9 @@ hipError_t launch_learned_fwd(const LearnedArgs& a, int max_width, int dfac, int
         return hipGetLastError();
     }
     switch (store) {
-        case 0: hipLaunchKernelGGL(k_learned_fwd<0>, dim3(a.ntasks), dim3(kThreads), 0, st, a); break;
-        case 1: hipLaunchKernelGGL(k_learned_fwd<1>, dim3(a.ntasks), dim3(kThreads), 0, st, a); break;
-        default: hipLaunchKernelGGL(k_learned_fwd<2>, dim3(a.ntasks), dim3(kThreads), 0, st, a); break;
+        case 0: hipLaunchKernelGGL(k_learned_fwd<0>, dim3(fwd_grid(a)), dim3(kThreads), 0, st, a); break;
+        case 1: hipLaunchKernelGGL(k_learned_fwd<1>, dim3(fwd_grid(a)), dim3(kThreads), 0, st, a); break;
+        default: hipLaunchKernelGGL(k_learned_fwd<2>, dim3(fwd_grid(a)), dim3(kThreads), 0, st, a); break;
     }
     return hipGetLastError();
 }
