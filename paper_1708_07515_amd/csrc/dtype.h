@@ -86,6 +86,14 @@ __device__ __forceinline__ T uniform_load(const T* p) {
     return out;
 }
 
+// Wait for every outstanding vector memory access of the wave (s_waitcnt
+// vmcnt(0) on gfx9 encodings; expcnt and lgkmcnt left at their maxima).  A
+// kernel places it where every load it issued has been consumed, on every
+// path: loads whose consumer sits in a branch that a wave skipped otherwise
+// stay pending in the compiler's bookkeeping, and later code then waits on
+// loads issued after them.
+__device__ __forceinline__ void vmem_drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Buffer resource over n elements of ES bytes at a lane-uniform address; raw
 // loads through it return zero outside [0, n * ES).
 template <class T>

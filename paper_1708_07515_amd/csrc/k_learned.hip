@@ -53,13 +53,6 @@ __device__ __forceinline__ uint16_t f2bf(float v) { return __builtin_bit_cast(ui
 
 __device__ __forceinline__ s4v f2bf4(f4v v) { return __builtin_bit_cast(s4v, __builtin_convertvector(v, bf4v)); }
 
-// Wait for every outstanding vector memory access of the wave (s_waitcnt
-// vmcnt(0); expcnt and lgkmcnt left at their maxima).  Placed after the
-// staging of prefetched rows, on every path: without it, loads whose only
-// consumer sits in a branch that a wave skipped stay pending in the
-// compiler's bookkeeping and later code waits on them.
-__device__ __forceinline__ void vmem_drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }
-
 // c(m) = floor(m P / P' + 1/2) = floor((2 m P + P') / (2 P')), walked in m
 // with an integer quotient and remainder (c(m) < P for m < P').
 struct CentreWalk {
