@@ -13,23 +13,26 @@
 // on the columns [0, W) and zero outside, c(m) the original angle nearest to
 // the decimated angle m, d = max(1, D / 4), 16 channels, 5 x 5 taps.
 //
-// Matrix cores: conv1 is an MFMA 16x16x16 BF16 product per 16 columns,
+// Matrix cores.  conv1 is a BF16 MFMA product per 16 columns,
 //   H^T[16 ch][16 col] = W1[16 ch][32 taps] x X^T[32 taps][16 col]
-// (two K steps; X^T gathers S at the taps), FP32 accumulation.  Its output
-// layout (lane l holds channels 4(l/16)..+3 of column l%16) is exactly the
-// B-operand layout of a second MFMA, which contracts the channels of conv2:
+// (X^T gathers S at the taps), FP32 accumulation.  Its output layout (lane l
+// holds channels 4(l/16)..+3 of column l%16) is exactly the B-operand layout
+// of a second MFMA, which contracts the channels of conv2:
 //   Q[b][col] += W2_a[16 (b, 5 used)][16 ch] x A^T[16 ch][16 col]
-// accumulated over the five dilated angles a; then R[j] = b2 + sum_b Q[b][j+b-2].
-// The weight gradient of conv1 is an MFMA reduction over positions:
+// over the five dilated angles a; then R[j] = b2 + sum_b Q[b][j+b-2].  The
+// forward pass uses the K = 32 product (one per conv1 angle, three for conv2
+// with two angles per product), the training pass the K = 16 one.  The weight
+// gradient of conv1 is an MFMA reduction over positions:
 //   dW1^T[32 taps][16 ch] += X[taps][16 pos] x dH[16 pos][16 ch].
 // Weights are BF16 (817 values: W1 [16][5][5], b1 [16], W2 [16][5][5], b2).
 //
 // One workgroup per (square, row) walks the decimated angles m.  The S values
 // of the nine original angles c(m) + (t - 4) d, t = 0..8, are kept in LDS as
-// BF16 (the precision conv1 multiplies them in).  The forward kernel loads the
-// next angle's S values and the next output row into registers before it runs
-// the current angle's matrix products, so the global-memory latency of one
-// angle overlaps the arithmetic of the previous one.
+// BF16 (the precision conv1 multiplies them in).  The next angle's S values
+// and output row are loaded into registers before the current angle's matrix
+// products, so the global-memory latency of one angle overlaps the
+// arithmetic of the previous one; when the decimated angles fall on original
+// ones the forward pass fetches only the four rows that the next angle adds.
 #include "internal.h"
 #include "dtype.h"
 #include "geom.h"
