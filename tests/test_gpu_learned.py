@@ -11,10 +11,12 @@ from oracle import fdk as ofdk, fdkod as ofdkod, learned, metrics, storage
 
 pytestmark = pytest.mark.gpu
 
-# N, P, R, s, k: D = 4 (d = 1), D = 8 (d = 2), a ragged N with a skipped stage.
-# The first two have D | P (the decimated angles fall on original ones: the
-# row-reusing kernel); the third does not (the general kernel).
-CASES = [(32, 48, 128.0, 2, 0), (40, 64, 160.0, 3, 0), (37, 50, 150.0, 3, 1)]
+# N, P, R, s, k: D = 4 (d = 1), D = 8 (d = 2), a ragged N with a skipped stage,
+# and a ragged N with D | P.  The first, second and fourth have D | P (the
+# decimated angles fall on original ones: the row-reusing kernel); the third
+# does not (the general kernel).  N = 37 and 36 leave detector rows over for
+# the last XCD's share of the task order.
+CASES = [(32, 48, 128.0, 2, 0), (40, 64, 160.0, 3, 0), (37, 50, 150.0, 3, 1), (36, 96, 144.0, 3, 1)]
 
 
 @pytest.fixture(scope="module", autouse=True)
