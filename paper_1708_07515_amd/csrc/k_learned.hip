@@ -77,24 +77,6 @@ struct CentreWalk {
     }
 };
 
-// Shared set-up of both kernels: the crop origin a_c(beta_p) + u0 of every
-// original angle, the angle offset (t - 4) d mod P of every tile row, and the
-// BF16 S tile (row t, column j at index j + 2; zero outside [0, W)).
-struct LearnedSmem {
-    float o_tab[kLearnedMaxP];
-    int off_tab[9];
-    uint16_t s_tile[9 * kSP];
-};
-
-__device__ __forceinline__ void learned_setup(const LearnedArgs& a, int q, int u0, LearnedSmem& sm) {
-    for (int p = threadIdx.x; p < a.p; p += blockDim.x) sm.o_tab[p] = a.ac_p[(size_t)q * a.p + p] + (float)u0;
-    if (threadIdx.x < 9) {
-        int off = ((int)threadIdx.x - 4) * a.d % a.p;
-        sm.off_tab[threadIdx.x] = off < 0 ? off + a.p : off;
-    }
-    for (int e = threadIdx.x; e < 9 * kSP; e += blockDim.x) sm.s_tile[e] = 0;
-}
-
 // The nine rows of S for centre angle c at the thread's column jj: detector
 // samples x0, x1 and the (row-uniform) interpolation fraction.  offr[t]: the
 // row offsets (t - 4) d mod P.  Rows are read through buffer resources that
@@ -121,56 +103,6 @@ __device__ __forceinline__ void s_fetch_rows(const LearnedArgs& a, const float* 
         x0[t] = S::raw(rs, off0);
         x1[t] = S::raw(rs, off1);
     }
-}
-
-__device__ __forceinline__ void s_stage_rows(LearnedSmem& sm, int col, const float x0[9], const float x1[9],
-                                             const float ph[9]) {
-#pragma unroll
-    for (int t = 0; t < 9; ++t) sm.s_tile[t * kSP + col] = f2bf(fmaf(ph[t], x1[t] - x0[t], x0[t]));
-}
-
-// conv1 for one dilated angle a2 and one 16-column tile: H^T in the MFMA
-// output layout (lane l: channels 4(l/16)+i, column col0 + l%16), no bias.
-// toff[8]: per-lane LDS offsets of the lane's eight taps (0 for the padding
-// taps 25..31, whose weights are zero).
-__device__ __forceinline__ f4v conv1_tile(const uint16_t* s_tile, int a2, int col0, const int toff[8],
-                                          const s4v w1op[2]) {
-    const int lr = threadIdx.x & 15;
-    const uint16_t* base = s_tile + a2 * kSP + col0 + lr;
-    f4v h = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-        s4v x;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) x[i] = (short)base[toff[4 * ks + i]];
-        h = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1op[ks], x, h, 0, 0, 0);
-    }
-    return h;
-}
-
-// Weight operands held in registers for the whole kernel, and the lane's
-// tap offsets into the S tile.
-__device__ __forceinline__ void load_weight_operands(const uint16_t* w, s4v w1op[2], s4v w2op[5],
-                                                     float b1v[4], int toff[8]) {
-    const int lane = threadIdx.x & 63;
-    const int lr = lane & 15, lg = lane >> 4;
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int tap = 16 * ks + 4 * lg + i;               // A[row = channel lr][k = tap]
-            w1op[ks][i] = tap < 25 ? (short)w[kOffW1 + lr * 25 + tap] : (short)0;
-            toff[4 * ks + i] = tap < 25 ? (tap / 5) * kSP + tap % 5 : 0;
-        }
-#pragma unroll
-    for (int a2 = 0; a2 < 5; ++a2)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int ch = 4 * lg + i;                          // A[row = b2 = lr][k = channel]
-            w2op[a2][i] = lr < 5 ? (short)w[kOffW2 + ch * 25 + a2 * 5 + lr] : (short)0;
-        }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) b1v[i] = bf2f(w[kOffB1 + 4 * lg + i]);
 }
 
 // The forward pass keeps the nine S rows in a pair layout: entry x of row t
@@ -331,7 +263,7 @@ __device__ __forceinline__ bool fwd_task(const LearnedArgs& a, int& q, int& v) {
     return v < a.n;
 }
 
-inline unsigned fwd_grid(const LearnedArgs& a) {
+__host__ __device__ inline unsigned fwd_grid(const LearnedArgs& a) {
     return (unsigned)a.nsq * kXcds * ((a.n + kXcds - 1) / kXcds);
 }
 
@@ -547,143 +479,182 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd_ring(LearnedArgs a) {
     }
 }
 
-// 16-lane (column) sum within each group of a wavefront.
-__device__ __forceinline__ float sum16(float x) {
-#pragma unroll
-    for (int off = 1; off < 16; off <<= 1) x += __shfl_xor(x, off, 64);
-    return x;
-}
+// Backward (training): gradients of sum_{m,v,j} R[m][v][j] dY[m][v][j] with
+// respect to the weights (dY = dL/dY in FP32, workspace layout), accumulated
+// into grad.  A workgroup takes (square, row) tasks in the forward kernels'
+// XCD-aware order with a grid stride, walks each task's decimated angles with
+// the forward's staging and operands, and keeps its gradient partials in
+// registers until all its tasks are done.
+//
+// conv1 runs in the transposed orientation, H[col][ch] = X[col][taps] x
+// W1^T[taps][ch] (the forward's operands with their roles swapped), so a lane
+// holds columns 4g .. 4g + 3 of channel lr.  That is the B-operand layout of a
+// product over columns, so every reduction over positions is an MFMA:
+//   dW2^T_a[b][ch] += G^T[b][col] x A_a[col][ch],   G[col][b] = dR[col - b + 2]
+//   dA_a[col][ch]   = G[col][b] x W2_a^T[b][ch]      (b = 0..4, padded to 8)
+//   dW1^T[tap][ch] += X^T[tap][col] x dH[col][ch]
+// The first two take FP32 operands (16x16x4 products: A, the BF16-rounded
+// activation, and dR, in FP32), the third BF16 ones (dH rounded, as S).
+// db1 is a per-lane sum of dH, reduced over the lane groups at the end.
+constexpr int kDrPad = 16;                          // dR row: column c at index c + 16
+constexpr int kDrLen = kDrPad + 16 * ((kLearnedMaxWidth + 15) / 16) + 18;
 
-// Backward: gradients of sum_{m,v,j} R[m][v][j] dY[m][v][j] with respect to
-// the weights (dY = dL/dY in FP32, workspace layout), accumulated into grad.
+struct BwdSmem {
+    float o_tab[kLearnedMaxP];
+    int off_tab[9];
+    uint32_t sp[9 * kPP];
+    float dr[kDrLen];
+};
+
 template <int STORE>
 __global__ __launch_bounds__(kThreads) void k_learned_bwd(LearnedArgs a) {
-    __shared__ LearnedSmem sm;
-    __shared__ float dr[kSP];
-    __shared__ float w2f[16 * 25];
-    __shared__ float gw2[16 * 25];
-    __shared__ float gb1[16];
-    __shared__ float tr[kThreads / 64][16 * 17];
-    __shared__ float gb2;
-    const int task = blockIdx.x;
-    if (task >= a.ntasks) return;
-    const int q = task % a.nsq, v = task / a.nsq;
-    const int2 gd = a.grid[q];
-    const int u0 = gd.x, width = gd.y;
+    __shared__ BwdSmem sm;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lg = lane >> 4;
-    s4v w1op[2], w2op[5];
-    float b1v[4];
-    int toff[8];
-    load_weight_operands(a.w, w1op, w2op, b1v, toff);
-    learned_setup(a, q, u0, sm);
-    for (int e = threadIdx.x; e < 400; e += blockDim.x) {
-        w2f[e] = bf2f(a.w[kOffW2 + e]);
-        gw2[e] = 0.0f;
-    }
-    if (threadIdx.x < 16) gb1[threadIdx.x] = 0.0f;
-    if (threadIdx.x == 0) gb2 = 0.0f;
-    for (int e = threadIdx.x; e < kSP; e += blockDim.x) dr[e] = 0.0f;
-    // A-operand offsets of the dW1 product: lane holds tap 16 tt + lr
+    const FwdOperands op = load_fwd_operands<kPP>(a.w);
+    const float b1l = bf2f(a.w[kOffB1 + lr]);             // bias of the lane's channel
+    // B operands of dA: W2[ch = lr][a2][b = 4 t + g] (zero for b >= 5)
+    float w2b[5][2];
+#pragma unroll
+    for (int a2 = 0; a2 < 5; ++a2)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int b = 4 * t + lg;
+            w2b[a2][t] = b < 5 ? bf2f(a.w[kOffW2 + lr * 25 + a2 * 5 + b]) : 0.0f;
+        }
+    // the lane's dW1 rows: taps lr and lr + 16 (taps >= 25 read a valid
+    // tile entry and give discarded rows)
     int xoff[2];
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt) {
-        const int tap = 16 * tt + lr;
-        xoff[tt] = tap < 25 ? (tap / 5) * kSP + tap % 5 : 0;   // taps >= 25 give discarded rows
+    for (int mt = 0; mt < 2; ++mt) {
+        const int tap = lr + 16 * mt;
+        xoff[mt] = tap < 25 ? (tap / 5) * kPP + tap % 5 + 4 * lg : 4 * lg;
     }
     f4v gw1[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
-    float db2 = 0.0f;
-    const int ntile = (width + 15) >> 4;
-    const int64_t yoff = a.squares[q].y_off_row * a.n;
-    float* trw = tr[wave];
-    const int col_s = threadIdx.x, jj = col_s - 2;
-    const bool stager = col_s < width + 4;
-    const bool valid = jj >= 0 && jj < width;
-    CentreWalk cw(a.p, a.pd);
-    __syncthreads();
-    int offr[9];
+    f4v gw2[5];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) offr[t] = __builtin_amdgcn_readfirstlane(sm.off_tab[t]);
-    for (int m = 0; m < a.pd; ++m) {
-        {
-            float x0[9], x1[9], ph[9];
-            s_fetch_rows<STORE>(a, sm.o_tab, v, cw.c, jj, valid, offr, x0, x1, ph);
-            if (stager) s_stage_rows(sm, col_s, x0, x1, ph);
-            cw.next();
+    for (int a2 = 0; a2 < 5; ++a2) gw2[a2] = (f4v){0.0f, 0.0f, 0.0f, 0.0f};
+    float gb1 = 0.0f, gb2 = 0.0f;
+
+    const unsigned ntot = fwd_grid(a);
+    for (unsigned task = blockIdx.x; task < ntot; task += gridDim.x) {
+        const int x8 = (int)(task % kXcds), i8 = (int)(task / kXcds);
+        const int q = i8 % a.nsq, v = (i8 / a.nsq) * kXcds + x8;
+        if (v >= a.n) continue;                            // uniform over the workgroup
+        const int2 gd = a.grid[q];
+        const int u0 = gd.x, width = gd.y;
+        const int ntile = (width + 15) >> 4;
+        __syncthreads();                                   // the previous task's reads are done
+        for (int p = threadIdx.x; p < a.p; p += kThreads) sm.o_tab[p] = a.ac_p[(size_t)q * a.p + p] + (float)u0;
+        if (threadIdx.x < 9) {
+            int off = ((int)threadIdx.x - 4) * a.d % a.p;
+            sm.off_tab[threadIdx.x] = off < 0 ? off + a.p : off;
         }
-        const size_t base = (size_t)yoff + ((size_t)m * a.n + v) * width;
-        for (int j = threadIdx.x; j < width; j += blockDim.x) {
-            const float g = a.dws[base + j];
-            dr[j + 2] = g;
-            db2 += g;
-        }
+        for (int e = threadIdx.x; e < 9 * kPP; e += kThreads) sm.sp[e] = 0u;
+        for (int e = threadIdx.x; e < kDrLen; e += kThreads) sm.dr[e] = 0.0f;
+        const int col = threadIdx.x;                        // staged column (local column col - 2)
+        const int jj = col - 2;
+        const bool stager = col < width + 4;
+        const bool valid = jj >= 0 && jj < width;
+        const size_t yrow = (size_t)a.squares[q].y_off_row * a.n + (size_t)v * width;
+        const size_t yplane = (size_t)a.n * width;
+        CentreWalk cw(a.p, a.pd);
         __syncthreads();
-        for (int tile = wave; tile < ntile; tile += kThreads / 64) {
-            const int col0 = tile * 16;
-            const int col = col0 + lr;
-            const bool cin = col < width;
-#pragma unroll 1
-            for (int a2 = 0; a2 < 5; ++a2) {
-                const f4v h = conv1_tile(sm.s_tile, a2, col0, toff, w1op);
-                float dh[4];
+        int offr[9];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int ch = 4 * lg + i;
-                    const float hv = h[i] + b1v[i];
-                    // the BF16 activation conv2 multiplied in the forward pass
-                    const float av = cin ? bf2f(f2bf(fmaxf(hv, 0.0f))) : 0.0f;
-                    // A(col) feeds R(col - b + 2): dA = sum_b W2[ch][a2][b] dR(col - b + 2)
-                    float da = 0.0f;
-#pragma unroll
-                    for (int bb = 0; bb < 5; ++bb) {
-                        const float g = dr[col - bb + 4];
-                        da = fmaf(w2f[ch * 25 + a2 * 5 + bb], g, da);
-                        const float s = sum16(av * g);        // dW2[ch][a2][bb] over the 16 columns
-                        if (lr == 0) atomicAdd(&gw2[ch * 25 + a2 * 5 + bb], s);
-                    }
-                    dh[i] = (cin && hv > 0.0f) ? da : 0.0f;
-                    const float sb = sum16(dh[i]);
-                    if (lr == 0) atomicAdd(&gb1[ch], sb);
-                    trw[ch * 17 + lr] = dh[i];               // dH[ch][col] for the transpose
-                }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                // B operand: lane holds dH[pos = 4 lg + i][ch = lr]
-                s4v dhop;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) dhop[i] = (short)f2bf(trw[lr * 17 + 4 * lg + i]);
-                const uint16_t* xb = sm.s_tile + a2 * kSP + col0 + 4 * lg;
-#pragma unroll
-                for (int tt = 0; tt < 2; ++tt) {
-                    // A operand: lane holds X[tap = 16 tt + lr][pos = 4 lg + i]
-                    s4v xop;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) xop[i] = (short)xb[xoff[tt] + i];
-                    gw1[tt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xop, dhop, gw1[tt], 0, 0, 0);
-                }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                __builtin_amdgcn_wave_barrier();
+        for (int t = 0; t < 9; ++t) offr[t] = __builtin_amdgcn_readfirstlane(sm.off_tab[t]);
+        for (int m = 0; m < a.pd; ++m) {
+            {
+                float x0[9], x1[9], ph[9];
+                s_fetch_rows<STORE>(a, sm.o_tab, v, cw.c, jj, valid, offr, x0, x1, ph);
+                if (stager) s_stage_pairs(sm.sp, col, x0, x1, ph);
+                cw.next();
             }
-        }
-        __syncthreads();
-    }
-    // flush: dW1^T tiles (lane holds taps 16 tt + 4 lg + i of channel lr)
+            if (col < width) {
+                const float g = a.dws[yrow + (size_t)m * yplane + col];
+                sm.dr[kDrPad + col] = g;
+                gb2 += g;
+            }
+            __syncthreads();
+            for (int tile = wave; tile < ntile; tile += kThreads / 64) {
+                const int col0 = tile * 16;
+                // dR operands of the tile (shared by the five angles):
+                // G^T[b = lr][col0 + 4 g + j] and G[col0 + lr][b = 4 t + g]
+                float gt[4], gc[2];
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt)
+                for (int j = 0; j < 4; ++j) gt[j] = sm.dr[kDrPad + col0 + 4 * lg + j - lr + 2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) gc[t] = sm.dr[kDrPad + col0 + lr - (4 * t + lg) + 2];
+                bool cin[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) cin[i] = col0 + 4 * lg + i < width;
+                const uint32_t* ph = sm.sp + col0 + op.hoff;
+                const uint32_t* pv = sm.sp + col0 + op.voff;
+#pragma unroll
+                for (int a2 = 0; a2 < 5; ++a2) {
+                    typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+                    const u4v d = {ph[a2 * kPP], ph[a2 * kPP + 2], pv[a2 * kPP], pv[a2 * kPP + kPP]};
+                    const f4v b1v = {b1l, b1l, b1l, b1l};
+                    // H[col0 + 4 g + i][ch = lr], bias included
+                    const f4v h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, d), op.w1, b1v,
+                                                                           0, 0, 0);
+                    // A = ReLU(H) rounded to BF16 (the value conv2 multiplies), zero outside [0, W)
+                    float av[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) av[i] = cin[i] ? bf2f(f2bf(fmaxf(h[i], 0.0f))) : 0.0f;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        gw2[a2] = __builtin_amdgcn_mfma_f32_16x16x4f32(gt[j], av[j], gw2[a2], 0, 0, 0);
+                    f4v da = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+                        da = __builtin_amdgcn_mfma_f32_16x16x4f32(gc[t], w2b[a2][t], da, 0, 0, 0);
+                    float dh[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        dh[i] = (cin[i] && h[i] > 0.0f) ? da[i] : 0.0f;
+                        gb1 += dh[i];
+                    }
+                    // B operand of dW1: dH[col0 + 4 g + i][ch = lr] in BF16
+                    const s4v dhop = {(short)f2bf(dh[0]), (short)f2bf(dh[1]), (short)f2bf(dh[2]),
+                                      (short)f2bf(dh[3])};
+#pragma unroll
+                    for (int mt = 0; mt < 2; ++mt) {
+                        // A operand: S of tap lr + 16 mt at columns col0 + 4 g .. + 3 (pair
+                        // entries x and x + 2 hold staged columns x .. x + 3)
+                        const int e = a2 * kPP + col0 + xoff[mt];
+                        const uint32_t lo = sm.sp[e], hi = sm.sp[e + 2];
+                        typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+                        const s4v xop = __builtin_bit_cast(s4v, (u2v){lo, hi});
+                        gw1[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(xop, dhop, gw1[mt], 0, 0, 0);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // flush the wave's partials: dW1^T[tap = 4 g + i + 16 mt][ch = lr],
+    // dW2^T[b = 4 g + i][ch = lr] per angle, db1 of channel lr, db2
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int tap = 16 * tt + 4 * lg + i;
-            if (tap < 25) atomicAdd(&a.grad[kOffW1 + lr * 25 + tap], gw1[tt][i]);
+            const int tap = 16 * mt + 4 * lg + i;
+            if (tap < 25) atomicAdd(&a.grad[kOffW1 + lr * 25 + tap], gw1[mt][i]);
         }
-    // db2: wave sums, then one atomic per wave
-    float s = db2;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) atomicAdd(&gb2, s);
-    __syncthreads();
-    for (int e = threadIdx.x; e < 400; e += blockDim.x) atomicAdd(&a.grad[kOffW2 + e], gw2[e]);
-    if (threadIdx.x < 16) atomicAdd(&a.grad[kOffB1 + threadIdx.x], gb1[threadIdx.x]);
-    if (threadIdx.x == 0) atomicAdd(&a.grad[kOffB2], gb2);
+    for (int a2 = 0; a2 < 5; ++a2)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int b = 4 * lg + i;
+            if (b < 5) atomicAdd(&a.grad[kOffW2 + lr * 25 + a2 * 5 + b], gw2[a2][i]);
+        }
+    gb1 += __shfl_xor(gb1, 16, 64);
+    gb1 += __shfl_xor(gb1, 32, 64);
+    if (lg == 0) atomicAdd(&a.grad[kOffB1 + lr], gb1);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) gb2 += __shfl_xor(gb2, off, 64);
+    if (lane == 0) atomicAdd(&a.grad[kOffB2], gb2);
 }
 
 // Transpose of the backprojection of decimated data (training): for every
@@ -808,12 +779,19 @@ hipError_t launch_learned_fwd(const LearnedArgs& a, int max_width, int dfac, int
     return hipGetLastError();
 }
 
+// Workgroups of the backward pass: a grid stride over the tasks, a multiple of
+// the XCD count (so a workgroup's tasks stay on its XCD's rows), about four
+// per compute unit.
+constexpr unsigned kBwdGrid = 1024;
+
 hipError_t launch_learned_bwd(const LearnedArgs& a, int store, hipStream_t st) {
     hipLaunchKernelGGL(k_fill, dim3(4), dim3(256), 0, st, a.grad, (int64_t)kLearnedParams, 0.0f);
+    const unsigned ntot = fwd_grid(a);
+    const dim3 grid(ntot < kBwdGrid ? ntot : kBwdGrid);
     switch (store) {
-        case 0: hipLaunchKernelGGL(k_learned_bwd<0>, dim3(a.ntasks), dim3(kThreads), 0, st, a); break;
-        case 1: hipLaunchKernelGGL(k_learned_bwd<1>, dim3(a.ntasks), dim3(kThreads), 0, st, a); break;
-        default: hipLaunchKernelGGL(k_learned_bwd<2>, dim3(a.ntasks), dim3(kThreads), 0, st, a); break;
+        case 0: hipLaunchKernelGGL(k_learned_bwd<0>, grid, dim3(kThreads), 0, st, a); break;
+        case 1: hipLaunchKernelGGL(k_learned_bwd<1>, grid, dim3(kThreads), 0, st, a); break;
+        default: hipLaunchKernelGGL(k_learned_bwd<2>, grid, dim3(kThreads), 0, st, a); break;
     }
     return hipGetLastError();
 }
