@@ -77,10 +77,11 @@ fdkod_status fdkod_reconstruct_adjoint(fdkod_plan_t pl, const float* resid, floa
     a.squares = pl->d_sq;
     a.grid = pl->d_grid;
     a.trig = pl->d_trig_m;
+    a.tiles = pl->d_tiles;
+    a.ntiles = pl->ntiles;
     a.n = pl->n;
     a.nz = pl->nz;
     a.pd = pl->pd;
-    a.sq_side = 1 << pl->s;
     a.r = (float)pl->r;
     a.cu = (float)((pl->n - 1) / 2.0);
     a.cv = a.cu;

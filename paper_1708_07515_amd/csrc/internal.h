@@ -186,8 +186,9 @@ struct AdjArgs {
     const SquareDesc* squares;
     const int2* grid;
     const float2* trig;      // cos, sin of beta'_m, [pd]
+    const BpTile* tiles;     // 16 x 16 (x, y) tiles of the squares
+    int ntiles;
     int n, nz, pd;
-    int sq_side;             // 2^s
     float r, cu, cv, cz;
     float scale;             // pi / P'
     int64_t ws_elems;

@@ -658,57 +658,110 @@ __global__ __launch_bounds__(kThreads) void k_learned_bwd(LearnedArgs a) {
 }
 
 // Transpose of the backprojection of decimated data (training): for every
-// voxel and decimated angle, scatter the residual with the bilinear weights
-// and (pi / P') U^-2 into dY (FP32, workspace layout).
+// voxel and decimated angle, the residual is scattered with the bilinear
+// weights and (pi / P') U^-2 into dY (FP32, workspace layout).  One workgroup
+// per 16 x 16 (x, y) tile of a square and slab of 32 slices (the
+// backprojection's blocks).  Per angle, the block's contributions are summed
+// in an LDS tile over its detector footprint, whose origin the block's
+// corners bound (the column is linear-fractional in x and y, the row linear
+// in z), and the tile is then added to dY with one FP32 global atomic per
+// non-zero entry.  A sample outside the tile (not expected) goes to dY
+// directly, so the result does not depend on the bound.  The block's
+// residuals sit in LDS, and in step k lane l takes slice (k + l) mod 32, so
+// the lanes of one LDS atomic fall on different rows and columns of the tile
+// (with one slice per step they would share a row and, several at a time, a
+// column, and the atomics would serialize).
+constexpr int kAdjZR = 32, kAdjTW = 40, kAdjTH = 48;
+
 __global__ __launch_bounds__(256) void k_bp_adjoint(AdjArgs a) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nvox = (int64_t)a.n * a.n * a.nz;
-    if (idx >= nvox) return;
-    const int i = (int)(idx % a.n);
-    const int j = (int)((idx / a.n) % a.n);
-    const int l = (int)(idx / ((int64_t)a.n * a.n));
-    const float res = a.resid[idx];
-    if (res == 0.0f) return;
-    // square of column i / row j: near-equal blocks, larger first
-    const int parts = a.sq_side;
-    const int base = a.n / parts, extra = a.n % parts;
-    const int cut = extra * (base + 1);
-    const int bx = i < cut ? i / (base + 1) : extra + (i - cut) / base;
-    const int by = j < cut ? j / (base + 1) : extra + (j - cut) / base;
-    const int q = by * parts + bx;
-    const SquareDesc sq = a.squares[q];
-    const int2 gd = a.grid[q];
+    __shared__ float acc[kAdjTH * kAdjTW];
+    __shared__ float rs[kAdjZR][256];          // residual of slice l0 + k, voxel threadIdx.x
+    const int tile = (int)(blockIdx.x % (unsigned)a.ntiles), zt = (int)(blockIdx.x / (unsigned)a.ntiles);
+    const BpTile tl = a.tiles[tile];
+    const SquareDesc sq = a.squares[tl.sq];
+    const int2 gd = a.grid[tl.sq];
     const int u0 = gd.x, width = gd.y;
-    const float dx = (float)i - a.cu - sq.xc, dy = (float)j - a.cu - sq.yc;
-    const float z = (float)l - a.cz;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int ix1 = min(tl.x0 + 15, sq.x1 - 1), iy1 = min(tl.y0 + 15, sq.y1 - 1);
+    const int i = tl.x0 + tx, j = tl.y0 + ty;
+    const bool own = i <= ix1 && j <= iy1;
+    const int l0 = zt * kAdjZR, l1 = min(l0 + kAdjZR, a.nz) - 1;
+    const float dx = (float)min(i, ix1) - a.cu - sq.xc, dy = (float)min(j, iy1) - a.cu - sq.yc;
+    const float bx[2] = {(float)tl.x0 - a.cu - sq.xc, (float)ix1 - a.cu - sq.xc};
+    const float by[2] = {(float)tl.y0 - a.cu - sq.yc, (float)iy1 - a.cu - sq.yc};
+    const float z0 = (float)l0 - a.cz, z1 = (float)l1 - a.cz;
+    // the block's residuals (slices l0 .. l0 + 31; zero outside the square or volume)
+#pragma unroll 8
+    for (int k = 0; k < kAdjZR; ++k) {
+        const int l = l0 + k;
+        rs[k][threadIdx.x] = own && l <= l1 ? a.resid[((size_t)l * a.n + j) * a.n + i] : 0.0f;
+    }
+    const int skew = threadIdx.x & 63;
     for (int m = 0; m < a.pd; ++m) {
         const float2 t = a.trig[m];
         const float dc = a.r + sq.xc * t.x + sq.yc * t.y;
         const float lc = sq.yc * t.x - sq.xc * t.y;
         const float rdc = 1.0f / dc;
-        const float tau = rel_column(dx, dy, t.x, t.y, a.r, dc, lc, rdc) + a.cu - (float)u0;
-        const float d = dc + dx * t.x + dy * t.y;
-        const float invu = a.r / d;
-        const float w = a.scale * invu * invu * res;
-        const float vv = fmaf(z, invu, a.cv);
-        const float vf = floorf(vv), fv = vv - vf;
-        const float tf = floorf(tau), fu = tau - tf;
-        const int iu = min(max((int)tf, 0), width - 2);
-        const int iv = (int)vf;
-        const size_t plane = (size_t)sq.y_off_row * a.n + (size_t)m * a.n * width;
+        // footprint origin: the least column and row over the block's corners, less a margin
+        float tlo = INFINITY, vlo = INFINITY;
 #pragma unroll
-        for (int dv = 0; dv < 2; ++dv) {
-            const int row = iv + dv;
-            if ((unsigned)row >= (unsigned)a.n) continue;
-            const float wv = dv ? fv : 1.0f - fv;
-            float* p = a.dws + plane + (size_t)row * width + iu;
-            atomicAdd(p, w * wv * (1.0f - fu));
-            atomicAdd(p + 1, w * wv * fu);
+        for (int c = 0; c < 4; ++c) {
+            const float cx = bx[c & 1], cy = by[c >> 1];
+            tlo = fminf(tlo, rel_column(cx, cy, t.x, t.y, a.r, dc, lc, rdc) + a.cu - (float)u0);
+            const float iuc = a.r / (dc + cx * t.x + cy * t.y);
+            vlo = fminf(vlo, fminf(z0 * iuc, z1 * iuc) + a.cv);
         }
+        const int c0 = (int)floorf(tlo) - 1, r0 = (int)floorf(vlo) - 1;
+        const size_t plane = (size_t)sq.y_off_row * a.n + (size_t)m * a.n * width;
+        for (int e = threadIdx.x; e < kAdjTH * kAdjTW; e += 256) acc[e] = 0.0f;
+        __syncthreads();
+        if (own) {
+            const float tau = rel_column(dx, dy, t.x, t.y, a.r, dc, lc, rdc) + a.cu - (float)u0;
+            const float d = dc + dx * t.x + dy * t.y;
+            const float invu = a.r / d;
+            const float wgt = a.scale * invu * invu;
+            const float tf = floorf(tau), fu = tau - tf;
+            const int iu = min(max((int)tf, 0), width - 2);
+            const int cl = iu - c0;
+            const bool cin = cl >= 0 && cl + 1 < kAdjTW;
+#pragma unroll 4
+            for (int k = 0; k < kAdjZR; ++k) {
+                const int sl = (k + skew) & (kAdjZR - 1);
+                const float rv = rs[sl][threadIdx.x];
+                if (rv == 0.0f) continue;
+                const float vv = fmaf((float)(l0 + sl) - a.cz, invu, a.cv);
+                const float vf = floorf(vv), fv = vv - vf;
+                const int iv = (int)vf;
+                const float w = wgt * rv;
+#pragma unroll
+                for (int dv = 0; dv < 2; ++dv) {
+                    const int row = iv + dv;
+                    if ((unsigned)row >= (unsigned)a.n) continue;
+                    const float wv = w * (dv ? fv : 1.0f - fv);
+                    const int rl = row - r0;
+                    if (cin && rl >= 0 && rl < kAdjTH) {
+                        atomicAdd(&acc[rl * kAdjTW + cl], wv * (1.0f - fu));
+                        atomicAdd(&acc[rl * kAdjTW + cl + 1], wv * fu);
+                    } else {
+                        float* p = a.dws + plane + (size_t)row * width + iu;
+                        atomicAdd(p, wv * (1.0f - fu));
+                        atomicAdd(p + 1, wv * fu);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // non-zero entries lie at rows in [0, N) and columns in [0, W): only
+        // such samples were added
+        for (int e = threadIdx.x; e < kAdjTH * kAdjTW; e += 256) {
+            const float val = acc[e];
+            if (val != 0.0f)
+                atomicAdd(&a.dws[plane + (size_t)(r0 + e / kAdjTW) * width + (c0 + e % kAdjTW)], val);
+        }
+        __syncthreads();
     }
 }
 
-// r = 2 (f - ref), loss += sum (f - ref)^2 (FP64).
 __global__ __launch_bounds__(256) void k_residual(const float* f, const float* ref, float* r, double* loss,
                                                    int64_t count) {
     __shared__ double part[4];
@@ -798,8 +851,9 @@ hipError_t launch_learned_bwd(const LearnedArgs& a, int store, hipStream_t st) {
 
 hipError_t launch_bp_adjoint(const AdjArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, st, a.dws, a.ws_elems, 0.0f);
-    const int64_t nvox = (int64_t)a.n * a.n * a.nz;
-    hipLaunchKernelGGL(k_bp_adjoint, dim3((unsigned)((nvox + 255) / 256)), dim3(256), 0, st, a);
+    const int64_t nblk = (int64_t)a.ntiles * ((a.nz + kAdjZR - 1) / kAdjZR);
+    if (nblk <= 0 || nblk > (int64_t)1 << 31) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bp_adjoint, dim3((unsigned)nblk), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
