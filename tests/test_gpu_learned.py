@@ -212,7 +212,13 @@ def test_learned_gradient_matches_oracle(case):
     plan.close()
 
 
-@pytest.mark.parametrize("case", CASES[1:])
+# a close source (R = 100 for N = 64): a 16 x 16 x 32 block's detector footprint
+# is about 50 columns by 60 rows, wider than the adjoint's LDS tile, so its
+# direct path is exercised as well
+ADJ_CASES = CASES[1:] + [(64, 48, 100.0, 2, 0)]
+
+
+@pytest.mark.parametrize("case", ADJ_CASES)
 def test_adjoint_identity_and_oracle(case):
     n, p, r, s, k = case
     plan = pkg.Plan(n, p, r, s=s, skip=k)
