@@ -670,7 +670,9 @@ __global__ __launch_bounds__(kThreads) void k_learned_bwd(LearnedArgs a) {
 // residuals sit in LDS, and in step k lane l takes slice (k + l) mod 32, so
 // the lanes of one LDS atomic fall on different rows and columns of the tile
 // (with one slice per step they would share a row and, several at a time, a
-// column, and the atomics would serialize).
+// column, and the atomics would serialize).  A thread sums each detector
+// row of its column pair in registers and adds it once, about one row per
+// slice instead of two.
 constexpr int kAdjZR = 32, kAdjTW = 40, kAdjTH = 48;
 
 __global__ __launch_bounds__(256) void k_bp_adjoint(AdjArgs a) {
@@ -724,31 +726,56 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(AdjArgs a) {
             const int iu = min(max((int)tf, 0), width - 2);
             const int cl = iu - c0;
             const bool cin = cl >= 0 && cl + 1 < kAdjTW;
-#pragma unroll 4
+            // one detector row's sum (columns iu and iu + 1 by the fixed split
+            // 1 - fu, fu) into the tile, or into dY when outside it; rows
+            // outside the detector are dropped
+            auto flush_row = [&](int row, float val) {
+                if (val == 0.0f || (unsigned)row >= (unsigned)a.n) return;
+                const int rl = row - r0;
+                if (cin && rl >= 0 && rl < kAdjTH) {
+                    atomicAdd(&acc[rl * kAdjTW + cl], val * (1.0f - fu));
+                    atomicAdd(&acc[rl * kAdjTW + cl + 1], val * fu);
+                } else {
+                    float* p = a.dws + plane + (size_t)row * width + iu;
+                    atomicAdd(p, val * (1.0f - fu));
+                    atomicAdd(p + 1, val * fu);
+                }
+            };
+            // the slices in order (from the lane's skew, wrapping once) move
+            // the row down monotonically: rows rc and rc + 1 are summed in
+            // registers and written once the slices have passed them
+            int rc = INT_MIN / 2;
+            float s0 = 0.0f, s1 = 0.0f;
             for (int k = 0; k < kAdjZR; ++k) {
                 const int sl = (k + skew) & (kAdjZR - 1);
+                if (sl == 0 && k > 0) {              // the wrap back to slice 0
+                    flush_row(rc, s0);
+                    flush_row(rc + 1, s1);
+                    s0 = s1 = 0.0f;
+                    rc = INT_MIN / 2;
+                }
                 const float rv = rs[sl][threadIdx.x];
                 if (rv == 0.0f) continue;
                 const float vv = fmaf((float)(l0 + sl) - a.cz, invu, a.cv);
                 const float vf = floorf(vv), fv = vv - vf;
                 const int iv = (int)vf;
-                const float w = wgt * rv;
-#pragma unroll
-                for (int dv = 0; dv < 2; ++dv) {
-                    const int row = iv + dv;
-                    if ((unsigned)row >= (unsigned)a.n) continue;
-                    const float wv = w * (dv ? fv : 1.0f - fv);
-                    const int rl = row - r0;
-                    if (cin && rl >= 0 && rl < kAdjTH) {
-                        atomicAdd(&acc[rl * kAdjTW + cl], wv * (1.0f - fu));
-                        atomicAdd(&acc[rl * kAdjTW + cl + 1], wv * fu);
+                if (iv != rc) {
+                    flush_row(rc, s0);
+                    if (iv == rc + 1) {
+                        s0 = s1;
                     } else {
-                        float* p = a.dws + plane + (size_t)row * width + iu;
-                        atomicAdd(p, wv * (1.0f - fu));
-                        atomicAdd(p + 1, wv * fu);
+                        flush_row(rc + 1, s1);
+                        s0 = 0.0f;
                     }
+                    s1 = 0.0f;
+                    rc = iv;
                 }
+                const float w = wgt * rv;
+                s0 = fmaf(w, 1.0f - fv, s0);
+                s1 = fmaf(w, fv, s1);
             }
+            flush_row(rc, s0);
+            flush_row(rc + 1, s1);
         }
         __syncthreads();
         // non-zero entries lie at rows in [0, N) and columns in [0, W): only
