@@ -42,19 +42,15 @@ namespace fdkod {
 typedef short s4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-constexpr int kSP = 16 * ((kLearnedMaxWidth + 15) / 16) + 4;  // LDS pitch of S and Q rows
+constexpr int kSP = 16 * ((kLearnedMaxWidth + 15) / 16) + 4;  // LDS pitch of the Q rows (general forward)
 constexpr int kOffW1 = 0, kOffB1 = 400, kOffW2 = 416, kOffB2 = 816;
 constexpr int kThreads = 256;
 static_assert(kLearnedMaxWidth + 4 <= kThreads, "one thread per staged column");
-
-typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
 // FP32 -> BF16, round to nearest even (hardware conversion)
 __device__ __forceinline__ uint16_t f2bf(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
-
-__device__ __forceinline__ s4v f2bf4(f4v v) { return __builtin_bit_cast(s4v, __builtin_convertvector(v, bf4v)); }
 
 // c(m) = floor(m P / P' + 1/2) = floor((2 m P + P') / (2 P')), walked in m
 // with an integer quotient and remainder (c(m) < P for m < P').
