@@ -339,14 +339,17 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd(LearnedArgs a) {
 // Row reuse.  When D divides P and D >= 4 (so d = D / 4), c(m) = m D and the
 // nine S rows of angle m are the rows u = 4m .. 4m + 8 of the sequence
 // p(u) = (u - 4) d mod P: consecutive angles share five rows.  The rows live
-// in a ring of 16 LDS slots, row u in slot u mod 16, with slots 0..8 mirrored
-// at 16..24 so that every window of nine is contiguous.  Each angle fetches
+// in a ring of 16 LDS slots, row u in slot u mod 16; windows start at slots
+// 0, 4, 8 and 12, so mirroring slots 0..4 at 16..20 makes every window of
+// nine contiguous.  Each angle fetches
 // its successor's four new rows and stages them while its own products run
 // (their slots, and mirrors, lie outside its window), and the Q tile
 // alternates between two buffers, so one barrier per angle orders the whole
-// pipeline.  PW: the widest square's tiles (128 or 256 columns).
+// pipeline.  PW: the widest square's tiles (128, 224 or 256 columns; 224
+// keeps five workgroups per compute unit within the LDS).
 constexpr int kRing = 16;
-constexpr int kRingSlots = kRing + 9;
+constexpr int kRingMirror = 5;
+constexpr int kRingSlots = kRing + kRingMirror;
 
 template <int PW>
 struct RingSmem {
@@ -385,7 +388,7 @@ __device__ __forceinline__ void ring_stage(uint32_t* sp, int slot, int x, float 
     const uint16_t val = f2bf(fmaf(ph, x1 - x0, x0));
     h[2 * (slot * PP + x)] = val;
     if (x > 0) h[2 * (slot * PP + x - 1) + 1] = val;
-    if (slot < 9) {
+    if (slot < kRingMirror) {
         h[2 * ((slot + kRing) * PP + x)] = val;
         if (x > 0) h[2 * ((slot + kRing) * PP + x - 1) + 1] = val;
     }
@@ -833,6 +836,8 @@ void launch_fwd_ring(const LearnedArgs& a, int max_width, hipStream_t st) {
     const size_t dyn = sizeof(float) * (size_t)a.p;
     if (max_width <= 128)
         hipLaunchKernelGGL((k_learned_fwd_ring<STORE, 128>), dim3(fwd_grid(a)), dim3(kThreads), dyn, st, a);
+    else if (max_width <= 224)
+        hipLaunchKernelGGL((k_learned_fwd_ring<STORE, 224>), dim3(fwd_grid(a)), dim3(kThreads), dyn, st, a);
     else
         hipLaunchKernelGGL((k_learned_fwd_ring<STORE, 256>), dim3(fwd_grid(a)), dim3(kThreads), dyn, st, a);
 }

@@ -118,11 +118,17 @@ def test_learned_forward_matches_oracle(case):
     plan.close()
 
 
-def test_learned_forward_wide_squares():
-    """Squares 122..148 columns wide (the wider tile pitch of the row-reusing
-    kernel, tiles shared unevenly by the waves), D = 4 | P; checked on a few
+# wide squares for the row-reusing kernel's tile pitches: widths 122..148
+# (across 128) and 216..236 (across 224)
+WIDE = [((320, 48, 640.0, 2, 0), 128), ((600, 48, 2400.0, 2, 0), 224)]
+
+
+@pytest.mark.parametrize("case,split", WIDE)
+def test_learned_forward_wide_squares(case, split):
+    """Squares on both sides of a tile-pitch boundary of the row-reusing
+    kernel (tiles shared unevenly by the waves), D = 4 | P; checked on a few
     detector rows against the oracle."""
-    n, p, r, s, k = 320, 48, 640.0, 2, 0
+    n, p, r, s, k = case
     net = random_net(5)
     proj = scan(n, p, r, 6, 29)
     with pkg.Plan(n, p, r, s=s, skip=k) as plan:
@@ -135,8 +141,8 @@ def test_learned_forward_wide_squares():
         widths = [int(w) for w in plan.get_bounds()["width"]]
         got_y = square_views(plan, _as(plan, ws_l))
         got_t = square_views(plan, _as(plan, ws_plain))
-    assert max(widths) > 128 and min(widths) < 128
-    rows = np.array([0, 101, 160, 247, n - 1])
+    assert max(widths) > split and min(widths) < split
+    rows = np.array([0, 101, n // 2, n - 73, n - 1])
     sqs, betas, betas_dec = ofdkod.plan(n, p, r, s, k)
     frows = ofdk.filter_rows(proj.numpy().astype(np.float64), r, rows)
     d_factor = ofdkod.decimation_factor(s, k)
