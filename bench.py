@@ -160,6 +160,9 @@ def run_learned(torch, pkg, wl, res, steps):
     if plan.s == 0 or plan.info.max_width > 252 or plan.p > 2048:
         return None
     proj, filt, ws, vol = res["proj"], res["filt"], res["ws"], res["vol"]
+    # the triangle step's volume, the target of the timed training steps (the
+    # random weights make the residual non-zero); volumes up to 1024^3 only
+    train_target = vol.clone() if wl.n <= 1024 else None
     net = pkg.LearnedDecimation("cuda:0", seed=0)
     net.load(torch.randn(pkg.LEARNED_PARAMS, generator=torch.Generator().manual_seed(1)) * 0.05)
     stages = [("bounds", lambda: plan.bounds()),
@@ -170,11 +173,23 @@ def run_learned(torch, pkg, wl, res, steps):
     log("[bench] FDK-OD with the learned filter, per stage (ms): "
         + ", ".join(f"{a}={b:.3f}" for a, b in per.items()))
     updates_eq = wl.n * wl.n * wl.nzv * wl.p
+    train = None
+    if train_target is not None:
+        resid = torch.empty_like(vol)
+        dws = torch.empty(plan.workspace_elems, dtype=torch.float32, device=vol.device)
+        tstages = [("train_step", lambda: net.train_step(plan, filt, ws, vol, train_target, resid, dws))]
+        _, train_ms, _ = timed_steps(torch, tstages, 3, 1)
+        log(f"[bench] learned filter, one AdamW step on the volume: {train_ms:.3f} ms")
+        train = {"ms_per_step": round(train_ms, 3), "steps": 3,
+                 "step": "learned decomposition, backprojection, squared residual against the "
+                         "triangle step's volume, transpose of the backprojection, weight gradient, AdamW"}
+        del resid, dws, train_target
     return {"ms_per_step": round(step_ms, 4),
             "gvups": round(updates_eq / (step_ms * 1e-3) / 1e9, 3),
             "stage_ms": {a: round(b, 4) for a, b in per.items()},
             "decompose_triangle_ms": round(res["per"]["decompose"], 4),
-            "weights": "817 BF16 parameters, seeded random"}
+            "weights": "817 BF16 parameters, seeded random",
+            "training_step": train}
 
 
 def _rel_rmse_regions(torch, vol, ref, regions, chunk=32):
