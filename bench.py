@@ -79,6 +79,30 @@ def timed_steps(torch, stages, steps, warmup):
     return per, total, wall
 
 
+def measure_copy_peak(torch, reps=5):
+    """Device-to-device copy of a 1 GiB FP32 buffer (1 GiB read + 1 GiB
+    written), timed with HIP events: the HBM bandwidth a plain streaming
+    kernel reaches, the practical ceiling of the HBM-bound stages."""
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 2 * a.numel() * a.element_size()
+    del a, b
+    torch.cuda.empty_cache()
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    log(f"[bench] device copy: {ms:.3f} ms per 2 GiB moved, {gbs:.0f} GB/s")
+    return {"value": round(gbs, 1), "unit": "GB/s", "ms": round(ms, 4), "bytes": nbytes,
+            "what": "device copy of a 1 GiB FP32 buffer (read + write)"}
+
+
 def make_scan(torch, wl, dev):
     from synth import phantom
     ell = phantom.random_ellipsoids(wl.ellipsoids, wl.seed)
@@ -413,6 +437,7 @@ def main():
         torch.cuda.synchronize()
         log("[bench] copy calibration: 1 GiB read + 1 GiB written")
         del a, b
+    copy_peak = measure_copy_peak(torch)
 
     wl = configs.ALL[args.workload]
     s = args.s if args.s is not None else max(wl.s)
@@ -488,6 +513,7 @@ def main():
         "large_workload": large,
         "batch_workload": batch,
         "learned_decimation": learned,
+        "copy_peak": copy_peak,
         "cone_decimation": cone,
     }
     print(json.dumps(out), flush=True)
