@@ -308,7 +308,8 @@ fdkod_status fdkod_learned_backward(fdkod_plan_t plan, const void* filt, const f
  * overwritten) receives, for every voxel with value resid and every decimated
  * angle, resid * (pi / P') U^-2 spread over the four samples of its bilinear
  * interpolation.  resid: float32 [N_z][N][N].  Uses float atomics, so the
- * summation order (and the last bits) vary from run to run. */
+ * summation order (and the last bits) vary from run to run.  Plans with
+ * cone-corrected rows (FDKOD_ROWS_CONE) return FDKOD_E_UNSUPPORTED. */
 fdkod_status fdkod_reconstruct_adjoint(fdkod_plan_t plan, const float* resid, float* dws,
                                        fdkod_stream_t stream);
 

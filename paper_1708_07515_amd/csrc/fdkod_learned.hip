@@ -71,6 +71,8 @@ fdkod_status fdkod_reconstruct_adjoint(fdkod_plan_t pl, const float* resid, floa
                                        fdkod_stream_t stream) {
     if (!pl || !resid || !dws) return fail(FDKOD_E_ARG, "NULL argument");
     if (pl->s == 0) return fail(FDKOD_E_UNSUPPORTED, "the adjoint is defined for s > 0");
+    if (pl->cone)
+        return fail(FDKOD_E_UNSUPPORTED, "the adjoint samples detector rows, not cone-corrected rows");
     AdjArgs a;
     a.resid = resid;
     a.dws = dws;

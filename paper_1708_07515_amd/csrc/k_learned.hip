@@ -456,9 +456,10 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd_ring(LearnedArgs a) {
         const uint32_t* win = sm.sp + ((4 * m) & (kRing - 1)) * PP;
         float* qt = sm.qb[m & 1];
         // a fixed number of tile slots per wave (no inner loop: the prefetched
-        // rows stay in flight across the products)
+        // rows stay in flight across the products); PW / 16 tiles over four
+        // waves, rounded up (PW = 224: 14 tiles, four slots per wave)
 #pragma unroll
-        for (int k = 0; k < PW / 64; ++k) {
+        for (int k = 0; k < (PW / 16 + 3) / 4; ++k) {
             const int tile = wave + 4 * k;
             if (tile < ntile) fwd_tile<PP, QP>(win, qt, tile * 16, width, op);
         }

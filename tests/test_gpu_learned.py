@@ -16,7 +16,10 @@ pytestmark = pytest.mark.gpu
 # decimated angles fall on original ones: the row-reusing kernel); the third
 # does not (the general kernel).  N = 37 and 36 leave detector rows over for
 # the last XCD's share of the task order.
-CASES = [(32, 48, 128.0, 2, 0), (40, 64, 160.0, 3, 0), (37, 50, 150.0, 3, 1), (36, 96, 144.0, 3, 1)]
+CASES = [(32, 48, 128.0, 2, 0), (40, 64, 160.0, 3, 0), (37, 50, 150.0, 3, 1), (36, 96, 144.0, 3, 1),
+         (128, 64, 512.0, 4, 0)]
+# The last has D = 16, so the angle dilation is d = 4 (the decimation of the
+# N = 2000, P = 720, s = 4 workload), again with D | P.
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -118,20 +121,69 @@ def test_learned_forward_matches_oracle(case):
     plan.close()
 
 
-# wide squares for the row-reusing kernel's tile pitches: widths 122..148
-# (across 128) and 216..236 (across 224)
-WIDE = [((320, 48, 640.0, 2, 0), 128), ((600, 48, 2400.0, 2, 0), 224)]
+# Wide squares for the row-reusing kernel's tile pitches (128, 224 and 256
+# columns; the 224 form takes squares of 193..224 columns in 14 tiles, four
+# slots per wave): widths 122..148 (across 128), 194..212 (all inside the 224
+# form, as the N = 2000, s = 4 squares of 179..212 columns), 216..236 (across
+# 224); and the N = 2000, s = 4 geometry itself with D = 16 (d = 4) at fewer
+# angles, widths 173..201, in BF16 storage.  (case, store, (lo, hi)): the
+# widths must reach below lo and above hi, or, with lo = hi = None, lie in
+# (192, 224].
+WIDE = [((320, 48, 640.0, 2, 0), "f32", (128, 128)), ((540, 48, 2160.0, 2, 0), "f32", (None, None)),
+        ((540, 48, 2160.0, 2, 0), "bf16", (None, None)), ((600, 48, 2400.0, 2, 0), "f32", (224, 224)),
+        ((2000, 96, 8000.0, 4, 0), "bf16", (192, 192))]
 
 
-@pytest.mark.parametrize("case,split", WIDE)
-def test_learned_forward_wide_squares(case, split):
-    """Squares on both sides of a tile-pitch boundary of the row-reusing
-    kernel (tiles shared unevenly by the waves), D = 4 | P; checked on a few
-    detector rows against the oracle."""
+def _wide_rows(n):
+    return np.array([0, 101, n // 2, n - 73, n - 1])
+
+
+def _rows_of(plan, ws, rows):
+    """Per-square [P', len(rows), W_q] FP64 arrays of detector rows ``rows`` of
+    a device workspace (selected on the device, so only they are copied)."""
+    typed = ws.view(plan.store_torch_dtype())[:plan.workspace_elems]
+    idx = torch.as_tensor(rows, device=ws.device)
+    return [v.index_select(1, idx).double().cpu().numpy() for v in square_views(plan, typed)]
+
+
+def _check_widths(widths, span):
+    lo, hi = span
+    if lo is None:
+        assert min(widths) > 192 and max(widths) <= 224, (min(widths), max(widths))
+    else:
+        assert min(widths) < lo and max(widths) > hi, (min(widths), max(widths))
+
+
+def _wide_squares(sqs, widths, limit=40):
+    """Square indices to check: every square if few, else the widest and the
+    narrowest ones plus an even spread (all tile counts of the launch)."""
+    if len(sqs) <= limit:
+        return list(range(len(sqs)))
+    order = np.argsort(widths)
+    pick = set(order[:8].tolist()) | set(order[-16:].tolist())
+    pick |= set(np.linspace(0, len(sqs) - 1, limit - len(pick)).astype(int).tolist())
+    return sorted(pick)
+
+
+def _oracle_rows(proj, n, p, r, s, k, rows, store):
+    sqs, betas, betas_dec = ofdkod.plan(n, p, r, s, k)
+    frows = ofdk.filter_rows(proj.numpy().astype(np.float64), r, rows)
+    if store != "f32":
+        frows.data = storage.ROUNDERS[store](frows.data)
+    return sqs, betas, betas_dec, frows
+
+
+@pytest.mark.parametrize("case,store,span", WIDE)
+def test_learned_forward_wide_squares(case, store, span):
+    """Squares on both sides of, or inside, a tile pitch of the row-reusing
+    kernel (tiles shared unevenly by the waves), D | P; checked on a few
+    detector rows against the oracle (BF16 storage: against the oracle that
+    rounds the filtered rows, T and T + R to BF16 as the GPU stores them)."""
     n, p, r, s, k = case
     net = random_net(5)
-    proj = scan(n, p, r, 6, 29)
-    with pkg.Plan(n, p, r, s=s, skip=k) as plan:
+    log(f"learned forward, wide squares: case {case} store {store}")
+    proj = scan(n, p, r, 6, 29, on_gpu=n > 1000)
+    with pkg.Plan(n, p, r, s=s, skip=k, store=store) as plan:
         filt = plan.empty_filtered()
         plan.filter(proj.to(DEV), filt)
         ws_plain, ws_l = plan.empty_workspace(), plan.empty_workspace()
@@ -139,22 +191,72 @@ def test_learned_forward_wide_squares(case, split):
         plan.learned_decompose(filt, ws_l, device_weights(net))
         torch.cuda.synchronize()
         widths = [int(w) for w in plan.get_bounds()["width"]]
-        got_y = square_views(plan, _as(plan, ws_l))
-        got_t = square_views(plan, _as(plan, ws_plain))
-    assert max(widths) > split and min(widths) < split
-    rows = np.array([0, 101, n // 2, n - 73, n - 1])
-    sqs, betas, betas_dec = ofdkod.plan(n, p, r, s, k)
-    frows = ofdk.filter_rows(proj.numpy().astype(np.float64), r, rows)
+        rows = _wide_rows(n)
+        got_y = _rows_of(plan, ws_l, rows)
+        got_t = _rows_of(plan, ws_plain, rows)
+        del filt, ws_plain, ws_l
+    _check_widths(widths, span)
+    sqs, betas, betas_dec, frows = _oracle_rows(proj, n, p, r, s, k, rows, store)
     d_factor = ofdkod.decimation_factor(s, k)
+    tri = ofdkod.triangle_weights(p, len(betas_dec))
+    rnd = storage.ROUNDERS[store] if store != "f32" else (lambda x: x)
     errs = []
-    for q, sq in enumerate(sqs):
+    for q in _wide_squares(sqs, widths):
+        sq = sqs[q]
         assert sq.width == widths[q]
         sub = np.moveaxis(ofdkod.crop_shift(frows, sq, betas, r, n), 0, 1)     # [rows, P, W]
         r_or, _ = learned.forward(sub, net, d_factor, len(betas_dec), bf16=True)
-        gr = (got_y[q] - got_t[q]).numpy()[:, rows, :].transpose(1, 0, 2)
-        errs.append(metrics.rel_rmse(gr, r_or))
-    log(f"learned forward, wide squares {widths[0]}..{max(widths)}: R rel-RMSE max {max(errs):.2e}")
-    assert max(errs) <= 1e-3
+        gy = got_y[q].transpose(1, 0, 2)
+        if store == "f32":
+            errs.append(metrics.rel_rmse(gy - got_t[q].transpose(1, 0, 2), r_or))
+        else:
+            t_or = np.moveaxis(np.tensordot(sub, tri.T, axes=(1, 0)), -1, 1)
+            errs.append(metrics.rel_rmse(gy, rnd(rnd(t_or) + r_or)))
+        # every column of the square, the last tiles' included, carries R
+        assert np.abs(gy - got_t[q].transpose(1, 0, 2))[..., -16:].max() > 0.0
+    log(f"learned forward, wide squares {min(widths)}..{max(widths)} ({store}): "
+        f"rel-RMSE max {max(errs):.2e} over {len(errs)} squares")
+    assert max(errs) <= (1e-3 if store == "f32" else 2e-3)
+
+
+def test_learned_gradient_wide_d16_bf16():
+    """Weight gradient at the N = 2000, s = 4 geometry (D = 16, d = 4, squares
+    of 173..201 columns, BF16 storage) with dL/dY non-zero on five detector
+    rows only, against the oracle's BF16-form backward on those rows."""
+    n, p, r, s, k = WIDE[-1][0]
+    net = random_net(8)
+    proj = scan(n, p, r, 6, 29, on_gpu=True)
+    rows = _wide_rows(n)
+    with pkg.Plan(n, p, r, s=s, skip=k, store="bf16") as plan:
+        filt = plan.empty_filtered()
+        plan.filter(proj.to(DEV), filt)
+        gen = torch.Generator().manual_seed(9)
+        dws = torch.zeros(plan.workspace_elems, dtype=torch.float32, device=DEV)
+        idx = torch.as_tensor(rows, device=DEV)
+        d_rows = []
+        for v in square_views(plan, dws):
+            g = torch.randn((v.shape[0], len(rows), v.shape[2]), generator=gen)
+            v.index_copy_(1, idx, g.to(DEV))
+            d_rows.append(g.double().numpy())
+        grad = torch.zeros(pkg.LEARNED_PARAMS, dtype=torch.float32, device=DEV)
+        plan.learned_backward(filt, dws, device_weights(net), grad)
+        torch.cuda.synchronize()
+        got = unflat(grad.double().cpu().numpy())
+        del filt, dws
+    sqs, betas, betas_dec, frows = _oracle_rows(proj, n, p, r, s, k, rows, "bf16")
+    d_factor = ofdkod.decimation_factor(s, k)
+    ref = {key: np.zeros_like(val) for key, val in net.items()}
+    for q, sq in enumerate(sqs):
+        sub = np.moveaxis(ofdkod.crop_shift(frows, sq, betas, r, n), 0, 1)
+        _, cache = learned.forward(sub, net, d_factor, len(betas_dec), bf16=True)
+        d_r = d_rows[q].transpose(1, 0, 2)
+        g = learned.backward(sub, net, d_factor, len(betas_dec), d_r, cache, bf16=True)
+        for key in ref:
+            ref[key] += g[key]
+    for key in ("w1", "b1", "w2", "b2"):
+        err = metrics.rel_rmse(got[key], ref[key])
+        log(f"gradient N=2000 D=16 bf16 {key}: rel-RMSE {err:.2e}")
+        assert err <= 2e-3, key
 
 
 def test_zero_second_layer_is_plain_decimation():
@@ -188,7 +290,7 @@ def test_learned_forward_half_storage(store):
     plan.close()
 
 
-@pytest.mark.parametrize("case", CASES[:2])
+@pytest.mark.parametrize("case", CASES[:2] + CASES[4:])
 def test_learned_gradient_matches_oracle(case):
     n, p, r, s, k = case
     net = random_net(4)
@@ -221,7 +323,7 @@ def test_learned_gradient_matches_oracle(case):
 # a close source (R = 100 for N = 64): a 16 x 16 x 32 block's detector footprint
 # is about 50 columns by 60 rows, wider than the adjoint's LDS tile, so its
 # direct path is exercised as well
-ADJ_CASES = CASES[1:] + [(64, 48, 100.0, 2, 0)]
+ADJ_CASES = CASES[1:4] + [(64, 48, 100.0, 2, 0)]
 
 
 @pytest.mark.parametrize("case", ADJ_CASES)
@@ -300,6 +402,13 @@ def test_learned_rejects_unsupported_plans():
         with pytest.raises(pkg.FdkodError) as ei:
             plan.learned_decompose(filt, torch.empty(256, dtype=torch.uint8, device=DEV),
                                    device_weights(random_net(0)))
+        assert ei.value.code == "E_UNSUPPORTED"
+    # the transpose of the backprojection samples detector rows; a plan with
+    # cone-corrected rows reads warped rows, so its transpose is refused
+    with pkg.Plan(32, 48, 128.0, s=2, rows="cone") as plan:
+        dws = torch.zeros(plan.workspace_elems, dtype=torch.float32, device=DEV)
+        with pytest.raises(pkg.FdkodError) as ei:
+            plan.reconstruct_adjoint(torch.zeros((plan.nz, 32, 32), device=DEV), dws)
         assert ei.value.code == "E_UNSUPPORTED"
 
 

@@ -126,3 +126,62 @@ def test_bf16_form_rounds_inputs_and_weights():
     r64, _ = learned.forward(s_sub, net, 4, 8)
     assert not np.array_equal(r32, r64)
     assert np.max(np.abs(r32 - r64)) < 0.05 * np.max(np.abs(r64))
+
+
+def _bf(x):
+    """BF16 rounding (nearest even) of an FP32 value, by torch's cast."""
+    return float(torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64))
+
+
+def _direct_bf16_grads(s_sub, net, d_factor, pd, d_r):
+    """Gradients of sum R dR in the BF16 form, by plain loops over the
+    definition: conv1 takes BF16 S, conv2 the BF16 activation, the gradients
+    hold those roundings fixed (dW2 from the rounded activation, dA passed
+    through the rounding, db1 from dH, dW1 from BF16 dH times BF16 S)."""
+    p, w = s_sub.shape
+    d = learned.dilation(d_factor)
+    sb = [[_bf(s_sub[pp, jj]) for jj in range(w)] for pp in range(p)]
+    sv = lambda pp, jj: sb[pp % p][jj] if 0 <= jj < w else 0.0  # noqa: E731
+    g = {k: np.zeros_like(v) for k, v in net.items()}
+    for m in range(pd):
+        c = int(((2 * m * p + pd) // (2 * pd)) % p)
+        for j in range(w):
+            g["b2"][0] += d_r[m, j]
+        for a2 in range(5):
+            pa = (c + (a2 - 2) * d) % p
+            for jj in range(w):                    # activation column
+                for k in range(16):
+                    hk = net["b1"][k]
+                    for a1 in range(5):
+                        for b1 in range(5):
+                            hk += net["w1"][k, a1, b1] * sv(pa + (a1 - 2) * d, jj + b1 - 2)
+                    act = _bf(max(hk, 0.0))
+                    da = 0.0
+                    for b2 in range(5):             # A[jj] feeds R[jj - b2 + 2]
+                        j = jj - b2 + 2
+                        if 0 <= j < w:
+                            g["w2"][k, a2, b2] += d_r[m, j] * act
+                            da += net["w2"][k, a2, b2] * d_r[m, j]
+                    dh = da if hk > 0.0 else 0.0
+                    g["b1"][k] += dh
+                    dhb = _bf(dh)
+                    for a1 in range(5):
+                        for b1 in range(5):
+                            g["w1"][k, a1, b1] += dhb * sv(pa + (a1 - 2) * d, jj + b1 - 2)
+    return g
+
+
+@pytest.mark.parametrize("d_factor,p,pd", [(4, 24, 6), (2, 11, 6)])
+def test_bf16_backward_matches_direct_loops(d_factor, p, pd):
+    rng = np.random.default_rng(10 + d_factor)
+    s_sub = rng.standard_normal((p, 6))
+    net = learned.rounded(_random_net(7))
+    d_r = rng.standard_normal((pd, 6))
+    _, cache = learned.forward(s_sub, net, d_factor, pd, bf16=True)
+    got = learned.backward(s_sub, net, d_factor, pd, d_r, cache, bf16=True)
+    want = _direct_bf16_grads(s_sub, net, d_factor, pd, d_r)
+    for key in ("w1", "b1", "w2", "b2"):
+        assert np.allclose(got[key], want[key], rtol=1e-10, atol=1e-12), key
+    # the BF16 form differs from the FP64 form (the roundings are placed)
+    g64 = learned.backward(s_sub, net, d_factor, pd, d_r, learned.forward(s_sub, net, d_factor, pd)[1])
+    assert not np.allclose(g64["w1"], want["w1"], rtol=1e-6)
