@@ -1,14 +1,16 @@
 """Benchmark: FDK-OD against direct FDK on one MI355X, in GVUPS.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cone512_p360] [--s 3]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cone2000_p720] [--s 4]
 
 A step is one pass of the whole hot path over one scan already resident in
 HBM: bounds kernel (eq. (1) at the square vertices), ramp filter, crop + shift
 + angular decimation, backprojection of every square.  GVUPS (voxel-angle
 updates per second) counts the direct-equivalent work N*N*N_z*P per step, so
-FDK-OD and direct FDK are on the same scale.  The main line is the 512^3,
-P = 360 workload; the N = 2000, P = 720 workload is reported beside it
-(``large_workload``).  Prints one JSON line.
+FDK-OD and direct FDK are on the same scale.  The main line is the paper's
+headline size, N = 2000, P = 720 (volume 2000^3), s = 4, no skipped stage,
+FP32 storage; BF16 storage, s = 5 and one skipped decimation stage are
+reported beside it (``variants``), and the 512^3 workload as
+``small_workload``.  Prints one JSON line.
 """
 
 import argparse
@@ -21,12 +23,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "GVUPS FDK-OD vs direct FDK on 1 MI355X at stated rel-RMSE vs FP64 oracle"
-# FP32 VALU peak without packed FP32: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2
+# FP32 VALU peak without packed FP32 (the library is built without packed
+# FP32 instructions): 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 flops per FMA
 VALU_PEAK_TFLOPS = 78.6
-# algorithmic FP32 work of one voxel-angle update: row coordinate (FMA = 2),
-# its fraction (1), three linear interpolations (sub + FMA = 3 each), weighted
-# accumulation (FMA = 2)
-FLOPS_PER_UPDATE = 14
+# the published FP32 vector figure, which counts packed FP32 (reported beside)
+VALU_PACKED_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+# LDS: 128 bytes per clock per compute unit, 256 CUs at 2.4 GHz
+LDS_PEAK_GBS = 128 * 256 * 2.4
+# algorithmic FP32 work of one voxel-angle update of the backprojection: three
+# linear interpolations (a subtraction and an FMA each, counted as one flop
+# and two) and the weighted accumulation (one FMA): 3 x 2 + 2 = 8
+FLOPS_PER_UPDATE = 8
+# on-chip bytes of one update: the two detector rows' (value, difference)
+# pairs of the bilinear sample, FP32 (one 16-byte LDS read)
+LDS_BYTES_PER_UPDATE = 16
+# the workers of the CPU oracle baseline: the machine's CPU share for one GPU
+CPU_WORKERS_MAX = 16
 
 
 def parse():
@@ -34,19 +47,20 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cone512_p360")
+    ap.add_argument("--workload", default="cone2000_p720")
     ap.add_argument("--s", type=int, default=None)
     ap.add_argument("--skip", type=int, default=None)
     ap.add_argument("--store", default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-direct", action="store_true", help="skip timing direct FDK")
-    ap.add_argument("--no-large", action="store_true", help="skip the N=2000 workload")
+    ap.add_argument("--no-small", action="store_true", help="skip the 512^3 workload")
+    ap.add_argument("--no-variants", action="store_true", help="skip the BF16 / s / k variants")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-filter step")
     ap.add_argument("--no-streamed", action="store_true", help="skip the low-memory slab mode run")
     ap.add_argument("--no-cone", action="store_true", help="skip the cone-corrected decimation run")
     ap.add_argument("--slab", type=int, default=64, help="slices per slab in the slab mode")
-    ap.add_argument("--cpu-slices", type=int, default=12)
+    ap.add_argument("--cpu-workers", type=int, default=0, help="oracle worker processes (0: all, at most 16)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy (for HBM counter calibration)")
     return ap.parse_args()
@@ -376,47 +390,208 @@ def run_batch(torch, pkg, bw, steps):
     }
 
 
-def measured_traffic(wl, s, store):
-    """HBM bytes per backprojection launch from the committed rocprofv3 counter
-    summary, or None when the kernel source or the workload differs from the
-    one that was profiled."""
+def measured_traffic(kernel, wl, s, k, store):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration),
+    or None when the kernel's source or the workload differs from the one that
+    was profiled."""
     import hashlib
     try:
         with open(os.path.join(ROOT, "profiles", "hbm_traffic.json")) as f:
-            rec = json.load(f)["k_backproject"]
-        with open(os.path.join(ROOT, "paper_1708_07515_amd", "csrc", "k_backproject.hip"), "rb") as f:
+            rec = json.load(f)[kernel]
+        with open(os.path.join(ROOT, "paper_1708_07515_amd", "csrc", rec["source"]), "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
     except (OSError, KeyError, ValueError):
         return None
-    if sha != rec["source_sha256"] or (rec["workload"], rec["s"], rec["store"]) != (wl.name, s, store):
+    if sha != rec["source_sha256"] or (rec["workload"], rec["s"], rec["k"], rec["store"]) != (wl.name, s, k, store):
         return None
     return rec["read_bytes"] + rec["write_bytes"]
 
 
-def cpu_baseline(proj_cpu, wl, s, k, gpu_vol, count):
-    """Time the FP64 oracle (one thread) on ``count`` sampled slices of the same
-    workload, and compare those slices with the GPU result."""
-    from threadpoolctl import threadpool_limits
-    from oracle import fdk as ofdk, fdkod as ofdkod, metrics
+def kernel_rooflines(wl, s, k, store, res):
+    """Per-kernel rooflines of one FDK-OD step from the stage times (HIP events
+    on the launch stream, averaged over the timed steps) and the algorithmic
+    work of each stage: the ramp filter and the decimation against HBM (each
+    input read once, each output written once), the backprojection against
+    the FP32 VALU (8 flops per update) with its LDS and HBM rates beside."""
+    plan, per = res["plan"], res["per"]
+    n, p, nz = wl.n, wl.p, wl.nzv
+    bs = {"f32": 4, "f16": 2, "bf16": 2}[store]
+    ws_bytes = plan.workspace_bytes
+    vol_bytes = 4 * n * n * nz
 
-    sl = list(metrics.sampled_slices(wl.nzv, count))
-    arr = proj_cpu.numpy()
+    def hbm(kernel, name, nbytes, what):
+        ms = per[name]
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return {"kernel": kernel, "bound": "hbm", "avg_ms": round(ms, 4), "algorithmic_bytes": nbytes,
+                "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes": what,
+                "traffic": measured_traffic(kernel, wl, s, k, store)}
+
+    out = {
+        "filter": hbm("k_filter", "filter", n * n * p * (4 + bs),
+                      "projections read once (FP32) + filtered rows written once (store type)"),
+        "decompose": hbm("k_decimate", "decompose", n * n * p * bs + ws_bytes,
+                         "filtered rows read once + decimated sub-sinograms written once"),
+    }
+    ms = per["reconstruct"]
+    ups = plan.updates / (ms * 1e-3)
+    tflops = FLOPS_PER_UPDATE * ups / 1e12
+    out["reconstruct"] = {
+        "kernel": "k_backproject", "bound": "alu", "avg_ms": round(ms, 4), "updates": plan.updates,
+        "updates_per_s": round(ups, 1), "flops_per_update": FLOPS_PER_UPDATE,
+        "achieved": round(tflops, 3), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+        "frac": round(tflops / VALU_PEAK_TFLOPS, 4),
+        "frac_of_packed_peak": round(tflops / VALU_PACKED_PEAK_TFLOPS, 4),
+        "lds": {"bytes_per_update": LDS_BYTES_PER_UPDATE,
+                "achieved": round(LDS_BYTES_PER_UPDATE * ups / 1e9, 1), "peak": round(LDS_PEAK_GBS, 1),
+                "unit": "GB/s", "frac": round(LDS_BYTES_PER_UPDATE * ups / 1e9 / LDS_PEAK_GBS, 4)},
+        "hbm": {"algorithmic_bytes": ws_bytes + vol_bytes,
+                "achieved": round((ws_bytes + vol_bytes) / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "bytes": "decimated sub-sinograms read once + volume written once"},
+        "traffic": measured_traffic("k_backproject", wl, s, k, store),
+    }
+    return out
+
+
+def host_description():
+    """CPU model, the cores this process may run on, and the BLAS pools."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [{"api": i.get("internal_api"), "threads": i.get("num_threads")} for i in threadpool_info()]
+    except Exception:           # threadpoolctl missing: report nothing
+        blas = []
+    return {"cpu_model": model, "affinity_cores": len(os.sched_getaffinity(0)), "blas_pools": blas}
+
+
+# State the oracle's worker processes read: set before the pool forks, so the
+# projections are shared with the children (copy on write), never pickled.
+_ORACLE = {}
+
+
+def _oracle_task(task):
+    from threadpoolctl import threadpool_limits
+    from oracle import fdk as ofdk, fdkod as ofdkod
+    c = _ORACLE
+    kind, what = task
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        if s == 0:
-            ref = ofdk.fdk(arr, wl.r, slices=sl)
+        if kind == "slice":
+            if c["s"] == 0:
+                ref = ofdk.fdk(c["proj"], c["r"], slices=[what], nz=c["nz"])[0]
+            else:
+                ref = ofdkod.fdkod(c["proj"], c["r"], c["s"], c["k"], slices=[what], nz=c["nz"])[0]
         else:
-            ref = ofdkod.fdkod(arr, wl.r, s, k, slices=sl)
-        dt = time.perf_counter() - t0
-    got = gpu_vol[sl].cpu().double().numpy()
-    err = metrics.rel_rmse(got, ref)
-    mx, mxr = metrics.max_abs(got, ref)
-    gv = wl.n * wl.n * len(sl) * wl.p / dt / 1e9
-    return (dict(value=gv, unit="GVUPS", cores=1, kind="oracle",
-                 sample=f"{len(sl)} sampled slices (incl. top and bottom) of {wl.name}, "
-                        f"s={s}, k={k}, FP64 NumPy, one thread: {dt:.1f} s",
-                 seconds=round(dt, 2)),
-            dict(rel_rmse=err, max_abs=mx, max_abs_rel=mxr, slices=[int(x) for x in sl]))
+            ref = ofdkod.fdkod_points(c["proj"], c["r"], c["s"], c["k"], what, nz=c["nz"])
+        return ref, time.perf_counter() - t0
+
+
+def voxel_clusters(n, nz):
+    """4 x 4 (x, y) patches on two slices at the top slice (centre), the bottom
+    slice (an edge), the centre slice (a corner) and a third of the way up:
+    where the cone angle is largest and where the squares meet the border."""
+    import numpy as np
+    groups = []
+    for (l, j, i) in [(0, n // 2 - 2, n // 2 - 2), (nz - 1, 3, n - 7), (nz // 2, n - 5, 2),
+                      (nz // 3, n // 4, 3 * n // 4)]:
+        g = [(min(l + dl, nz - 1), j + dj, i + di) for dl in (0, 1) for dj in range(4) for di in range(4)]
+        groups.append(np.array(g))
+    return groups
+
+
+def cpu_baseline(proj_cpu, wl, s, k, store, gpu_vol, workers):
+    """The FP64 oracle timed on the host's cores (one worker process per core,
+    one thread each): each worker reconstructs one slice near the centre of
+    the volume (the rows eq. (9) maps them to are few, so the time is the
+    oracle's decomposition and backprojection), while four more workers
+    compute voxel clusters at the top and bottom slices for the parity
+    record.  The GPU result is compared with both."""
+    import multiprocessing as mp
+    import numpy as np
+    from oracle import metrics
+
+    host = host_description()
+    cores = max(1, min(workers or host["affinity_cores"], CPU_WORKERS_MAX, host["affinity_cores"]))
+    groups = voxel_clusters(wl.n, wl.nzv)
+    nsl = max(1, cores - len(groups)) if cores > len(groups) else cores
+    sl = sorted(set(int(x) for x in np.round(np.linspace(0.45 * (wl.nzv - 1), 0.55 * (wl.nzv - 1), nsl))))
+    _ORACLE.update(proj=proj_cpu.numpy(), r=wl.r, s=s, k=k, nz=wl.nzv)
+    tasks = [("slice", l) for l in sl] + [("points", g) for g in groups]
+    log(f"[bench] CPU oracle: {len(sl)} slices and {len(groups)} voxel clusters on {cores} worker processes")
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(processes=cores) as pool:
+        out = pool.map(_oracle_task, tasks, chunksize=1)
+    wall = time.perf_counter() - t0
+    _ORACLE.clear()
+    refs = [o[0] for o in out]
+    times = [o[1] for o in out]
+    slice_t = max(times[:len(sl)])
+    gpu_sl = gpu_vol[sl].cpu().double().numpy()
+    ref_sl = np.stack(refs[:len(sl)])
+    idx = np.concatenate(groups)
+    gpu_pts = gpu_vol[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().double().numpy()
+    ref_pts = np.concatenate(refs[len(sl):])
+    err_sl = metrics.rel_rmse(gpu_sl, ref_sl)
+    mx_sl, mxr_sl = metrics.max_abs(gpu_sl, ref_sl)
+    err_pt = metrics.rel_rmse(gpu_pts, ref_pts)
+    mx_pt, mxr_pt = metrics.max_abs(gpu_pts, ref_pts)
+    updates = wl.n * wl.n * len(sl) * wl.p
+    gv = updates / slice_t / 1e9
+    conc = min(len(sl), cores)
+    log(f"[bench] CPU oracle: {len(sl)} slices in {slice_t:.1f} s ({gv:.3f} GVUPS on {conc} cores), "
+        f"all tasks {wall:.1f} s; parity slices {err_sl:.2e}, clusters {err_pt:.2e}")
+    cpu = dict(value=round(gv, 5), unit="GVUPS", cores=conc, kind="oracle",
+               sample=f"{len(sl)} slices of {wl.name} near the centre (l = {sl[0]}..{sl[-1]}), s={s}, k={k}, "
+                      f"FP64 NumPy, one slice per worker process, one thread each; "
+                      f"the longest took {slice_t:.1f} s",
+               seconds=round(slice_t, 2), threads_per_worker=1, host=host)
+    parity = dict(bar=1e-4 if store == "f32" else 2e-3, store=store, rel_rmse=err_sl, max_abs=mx_sl, max_abs_rel=mxr_sl, slices=sl,
+                  clusters=dict(rel_rmse=err_pt, max_abs=mx_pt, max_abs_rel=mxr_pt, voxels=int(len(idx)),
+                                where="4x4x2 voxel patches at the top slice (centre), the bottom slice (edge), "
+                                      "the centre slice (corner) and a third of the way up"),
+                  oracle="FP64 FDK-OD of the same (s, k), plain storage")
+    return cpu, parity
+
+
+def run_variant(torch, pkg, wl, s, k, store, base, steps, direct_ms):
+    """Time FDK-OD steps of another (s, k, store) on the main scan; the direct
+    FDK time of the main run serves as the reference (the same kernel at s = 0)."""
+    proj = base["proj"]
+    plan = pkg.Plan(wl.n, wl.p, wl.r, s=s, skip=k, nz=wl.nzv, store=store)
+    same = {"f32": 0, "f16": 1, "bf16": 2}[store] == base["plan"].store
+    filt = base["filt"] if same else plan.empty_filtered()
+    ws = plan.empty_workspace()
+    vol = base["vol"]
+    stages = [("bounds", lambda: plan.bounds()),
+              ("filter", lambda: plan.filter(proj, filt)),
+              ("decompose", lambda: plan.decompose(filt, ws)),
+              ("reconstruct", lambda: plan.reconstruct(filt, ws, vol))]
+    per, step_ms, _ = timed_steps(torch, stages, steps, 1)
+    log(f"[bench] variant s={s} k={k} store={store}, per stage (ms): "
+        + ", ".join(f"{a}={b:.3f}" for a, b in per.items()))
+    updates_eq = wl.n * wl.n * wl.nzv * wl.p
+    paper_ms = per["bounds"] + per["decompose"] + per["reconstruct"]
+    out = {"s": s, "k": k, "store": store, "p_dec": plan.p_dec, "ms_per_step": round(step_ms, 4),
+           "gvups": round(updates_eq / (step_ms * 1e-3) / 1e9, 3),
+           "gvups_paper_scope": round(updates_eq / (paper_ms * 1e-3) / 1e9, 3),
+           "stage_ms": {a: round(b, 4) for a, b in per.items()},
+           "speedup_vs_direct": None if direct_ms is None else round(direct_ms["step"] / step_ms, 3),
+           "speedup_vs_direct_paper_scope": None if direct_ms is None else
+               round(direct_ms["reconstruct"] / paper_ms, 3),
+           "steps": steps}
+    del ws, filt
+    plan.close()
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -446,36 +621,47 @@ def main():
     res = run_workload(torch, pkg, wl, s, k, store, args.steps, args.warmup,
                        direct=not args.no_direct)
     main_sum = summarise(wl, s, k, store, res)
-    plan = res["plan"]
-    rec_ms = res["per"]["reconstruct"]
-    achieved = FLOPS_PER_UPDATE * plan.updates / (rec_ms * 1e-3) / 1e12
-    roofline = dict(bound="alu", kernel="k_backproject", achieved=round(achieved, 3),
-                    peak=VALU_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / VALU_PEAK_TFLOPS, 4),
-                    traffic=measured_traffic(wl, s, store),
-                    flops_per_update=FLOPS_PER_UPDATE, updates=plan.updates,
-                    avg_ms=round(rec_ms, 4))
+    kernels = kernel_rooflines(wl, s, k, store, res)
+    bp = kernels["reconstruct"]
+    roofline = dict(bound="alu", kernel="k_backproject", achieved=bp["achieved"], peak=VALU_PEAK_TFLOPS,
+                    unit="TFLOP/s", frac=bp["frac"], traffic=bp["traffic"],
+                    flops_per_update=FLOPS_PER_UPDATE, updates=bp["updates"], avg_ms=bp["avg_ms"])
+    direct_ms = None
+    if res["direct"] is not None:
+        direct_ms = {"step": res["direct"]["ms_per_step"], "reconstruct": res["direct"]["stage_ms"]["reconstruct"]}
 
     cpu = parity = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a bounded sample")
-        cpu, parity = cpu_baseline(res["proj"].cpu(), wl, s, k, res["vol"], args.cpu_slices)
-    learned = None if args.no_learned else run_learned(torch, pkg, wl, res, max(1, min(args.steps, 5)))
-    cone = None if args.no_cone else run_cone(torch, pkg, wl, s, k, store, res, max(1, min(args.steps, 5)))
-    del res
+        cpu, parity = cpu_baseline(res["proj"].cpu(), wl, s, k, store, res["vol"], args.cpu_workers)
 
-    large = None
-    if not args.no_large and wl.name != "cone2000_p720":
-        torch.cuda.empty_cache()
-        lw = configs.C5
-        lres = run_workload(torch, pkg, lw, max(lw.s), lw.k, lw.store[0], 2, 1,
+    variants = None
+    if not args.no_variants and s > 0:
+        variants = []
+        alt_store = "bf16" if store == "f32" else "f32"
+        for (vs, vk, vst) in [(s, k, alt_store), (s + 1, k, store), (s, k + 1, store), (s + 1, k + 1, store)]:
+            if (1 << vs) > wl.n:
+                continue
+            variants.append(run_variant(torch, pkg, wl, vs, vk, vst, res, max(1, min(args.steps, 3)), direct_ms))
+        # the main volume again (parity and the extensions below compare with it)
+        res["plan"].decompose(res["filt"], res["ws"])
+        res["plan"].reconstruct(res["filt"], res["ws"], res["vol"])
+        torch.cuda.synchronize()
+
+    learned = None if args.no_learned else run_learned(torch, pkg, wl, res, max(1, min(args.steps, 5)))
+    cone = None if args.no_cone else run_cone(torch, pkg, wl, s, k, store, res, max(1, min(args.steps, 3)))
+    streamed = None if args.no_streamed else run_streamed(torch, res, args.slab)
+    del res
+    torch.cuda.empty_cache()
+
+    small = None
+    if not args.no_small and wl.name != "cone512_p360":
+        sw = configs.C2
+        sres = run_workload(torch, pkg, sw, max(sw.s), sw.k, sw.store[0], max(1, min(args.steps, 10)), 2,
                             direct=not args.no_direct)
-        large = summarise(lw, max(lw.s), lw.k, lw.store[0], lres)
-        if not args.no_cone:
-            large["cone_decimation"] = run_cone(torch, pkg, lw, max(lw.s), lw.k, lw.store[0], lres, 2)
-        if not args.no_streamed:
-            large["streamed"] = run_streamed(torch, lres, args.slab)
-        del lres
+        small = summarise(sw, max(sw.s), sw.k, sw.store[0], sres)
+        small["kernels"] = kernel_rooflines(sw, max(sw.s), sw.k, sw.store[0], sres)
+        del sres
         torch.cuda.empty_cache()
 
     batch = None
@@ -509,12 +695,15 @@ def main():
         "speedup_vs_direct_paper_scope": main_sum["speedup_vs_direct_paper_scope"],
         "parity": parity,
         "roofline": roofline,
+        "kernels": kernels,
         "cpu_baseline": cpu,
-        "large_workload": large,
-        "batch_workload": batch,
+        "variants": variants,
         "learned_decimation": learned,
-        "copy_peak": copy_peak,
         "cone_decimation": cone,
+        "streamed": streamed,
+        "small_workload": small,
+        "batch_workload": batch,
+        "copy_peak": copy_peak,
     }
     print(json.dumps(out), flush=True)
 

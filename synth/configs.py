@@ -48,7 +48,7 @@ C3 = Workload("cone1024_p720", n=1024, p=720, r=4096.0, s=(3,), ellipsoids=30, s
 
 # large case: N = 2000, P = 720, s = 4 (the paper's headline size)
 C5 = Workload("cone2000_p720", n=2000, p=720, r=8000.0, s=(4,), ellipsoids=30, seed=5000,
-              store=("bf16", "f32"),
+              store=("f32", "bf16"),
               note="detector 2000x2000, P=720, volume 2000^3, s=4, 30 ellipsoids")
 
 
