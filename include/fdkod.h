@@ -383,6 +383,30 @@ fdkod_status fdkod_reconstruct_streamed(fdkod_plan_t plan, const float* host_pro
                                         int32_t nzs, void* work, int64_t work_bytes, fdkod_stream_t stream,
                                         fdkod_stream_t copy_stream);
 
+/* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).
+ *
+ * fdkod_backproject_noalloc is fdkod_backproject with the workspace taken
+ * from a fixed device array inside the library instead of a caller buffer:
+ * the same decimation and backprojection kernels, the same result.  The array
+ * holds FDKOD_NOALLOC_SCRATCH_BYTES bytes on every GPU the library runs on,
+ * from the time the library's device code is loaded there until the process
+ * ends.  The call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine); the caller passes the filtered projections and the volume
+ * as for fdkod_backproject.  Plans whose workspace (fdkod_plan_info
+ * workspace_bytes) exceeds the array return FDKOD_E_UNSUPPORTED.  s = 0
+ * (direct FDK) needs no workspace.  All calls on one GPU share its array and
+ * keep the last call's contents: calls that overlap in time on one GPU (on
+ * several streams or host threads) race and give undefined results.  The
+ * first call on a device looks up the array's device address (synchronously,
+ * with that device made current and the caller's current device restored).
+ * ------------------------------------------------------------------------- */
+#define FDKOD_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+fdkod_status fdkod_backproject_noalloc(fdkod_plan_t plan, const void* filt, float* vol,
+                                       fdkod_stream_t stream);
+
 /* Static text for a status code. */
 const char* fdkod_status_str(fdkod_status st);
 

@@ -5,10 +5,11 @@ of the reconstruction runs in the library's HIP kernels; this package only
 marshals arguments.  Torch tensors supply device memory and streams.
 """
 
-from ._lib import (DECIM_TYPES, INTERP_TYPES, LEARNED_PARAMS, ROWS_TYPES, Batch, FdkodError, Plan,  # noqa: F401
-                   STORE_TYPES,
+from ._lib import (DECIM_TYPES, INTERP_TYPES, LEARNED_PARAMS, NOALLOC_SCRATCH_BYTES, ROWS_TYPES,  # noqa: F401
+                   Batch, FdkodError, Plan, STORE_TYPES,
                    adamw_step, library_path, load_library, sq_residual, validate)
 from .learned import LearnedDecimation  # noqa: F401
 
 __all__ = ["Plan", "Batch", "FdkodError", "validate", "load_library", "library_path", "STORE_TYPES",
-           "DECIM_TYPES", "ROWS_TYPES", "INTERP_TYPES", "LEARNED_PARAMS", "sq_residual", "adamw_step", "LearnedDecimation"]
+           "DECIM_TYPES", "ROWS_TYPES", "INTERP_TYPES", "LEARNED_PARAMS", "NOALLOC_SCRATCH_BYTES", "sq_residual", "adamw_step",
+           "LearnedDecimation"]

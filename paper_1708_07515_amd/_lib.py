@@ -13,6 +13,7 @@ _LIB = None
 
 STORE_TYPES = {"f32": 0, "f16": 1, "bf16": 2}
 _STORE_BYTES = {0: 4, 1: 2, 2: 2}
+NOALLOC_SCRATCH_BYTES = 256 << 20     # FDKOD_NOALLOC_SCRATCH_BYTES of the C header
 
 FDKOD_OK = 0
 STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_GEOMETRY", 3: "E_UNSUPPORTED", 4: "E_NOMEM",
@@ -67,6 +68,7 @@ EXPORTS = {
     "fdkod_backproject": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p]),
     "fdkod_get_bounds": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 7),
+    "fdkod_backproject_noalloc": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "fdkod_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning)]),
     "fdkod_set_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning)]),
     "fdkod_tune": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(Tuning)]),
@@ -341,6 +343,16 @@ class Plan:
         _check(self._lib.fdkod_backproject(
             self._h, ctypes.c_void_p(filt.data_ptr()), ctypes.c_void_p(vol.data_ptr()),
             ctypes.c_void_p(ws.data_ptr() if ws is not None else 0), _stream_ptr(stream)))
+
+    def backproject_noalloc(self, filt, vol, stream=None):
+        """fdkod_backproject with the library's fixed device array as the
+        workspace (nothing is allocated; plans whose workspace exceeds
+        NOALLOC_SCRATCH_BYTES raise E_UNSUPPORTED)."""
+        import torch
+        self._chk(filt, (self.p, self.n, self.n), self.store_torch_dtype(), "filt")
+        self._chk(vol, (self.nz, self.n, self.n), torch.float32, "vol")
+        _check(self._lib.fdkod_backproject_noalloc(
+            self._h, ctypes.c_void_p(filt.data_ptr()), ctypes.c_void_p(vol.data_ptr()), _stream_ptr(stream)))
 
     # learned decimation ---------------------------------------------------
     @property
