@@ -324,20 +324,26 @@ def run_streamed(torch, res, slab):
             "bitwise_equal_sampled_slices": same}
 
 
-def batch_volumes(bw):
-    """The batched workload's volumes: sizes drawn with the workload's seed."""
+def batch_volumes(bw, pkg):
+    """The batched workload's volumes: sizes drawn with the workload's seed,
+    s per volume from the cost model (eq. (8) over the exact counts, with the
+    MI355X cost constants)."""
     import numpy as np
     rng = np.random.default_rng(bw.seed)
     sizes = rng.choice(np.array(bw.sizes), bw.count)
-    return [dict(n=int(n), p=int(round(bw.p_per_n * n)), r=float(bw.r_per_n * n),
-                 s=int(bw.levels[int(n)])) for n in sizes]
+    out = []
+    for n in sizes:
+        n, p, r = int(n), int(round(bw.p_per_n * n)), float(bw.r_per_n * n)
+        s, _ = pkg.choose_s(n, p, r, s_max=bw.s_max, store="bf16")
+        out.append(dict(n=n, p=p, r=r, s=s))
+    return out
 
 
 def run_batch(torch, pkg, bw, steps):
     """Time the batched workload: one captured hipGraph replay per step, after
     the autotuner; and, for comparison, the same volumes one plan at a time."""
     from synth import phantom
-    vols = batch_volumes(bw)
+    vols = batch_volumes(bw, pkg)
     log(f"[bench] batch {bw.name}: {len(vols)} volumes, sizes {sorted(v['n'] for v in vols)}")
     b = pkg.Batch(vols, store="bf16")
     projs = []
@@ -380,6 +386,8 @@ def run_batch(torch, pkg, bw, steps):
     return {
         "workload": bw.name, "volumes": len(vols), "store": "bf16",
         "sizes": {str(n): sum(1 for v in vols if v["n"] == n) for n in bw.sizes},
+        "s_by_size": {str(v["n"]): v["s"] for v in vols},
+        "s_rule": "cost model (eq. (8) over the exact counts), MI355X cost constants",
         "updates_eq": info["updates_eq"], "work_items": info["items"],
         "persistent_blocks": info["blocks"], "tuning": {k: (round(x, 4) if isinstance(x, float) else x)
                                                          for k, x in tuning.items()},

@@ -214,6 +214,23 @@ fdkod_status fdkod_set_tuning(fdkod_plan_t plan, const fdkod_tuning* t);
 fdkod_status fdkod_tune(fdkod_plan_t plan, const void* filt, void* ws, float* vol,
                         fdkod_stream_t stream, fdkod_tuning* out);
 
+/* ---------------------------------------------------------------- cost model
+ * Sec. 2.2 prices FDK-OD as reconstruction C1 N^4 / 2^s (eq. (6)) plus
+ * decomposition C2 N^3 2^s (eq. (7)), with the optimum 2^s = sqrt(C1 N / C2)
+ * (eq. (8)).  The library counts both terms exactly for a parameter set (host
+ * arithmetic in FP64, no device): the voxel-angle updates N^2 N_z P' of the
+ * reconstruction (N^2 N_z P for s = 0) and the cropped samples
+ * (sum_q W_q) P N of the decomposition, W_q the squares' local grid widths
+ * from eq. (1) at their vertices (0 for s = 0).                              */
+fdkod_status fdkod_cost_counts(const fdkod_params* prm, int64_t* cropped, int64_t* updates);
+
+/* The s in [0, s_max] (skip clipped to s) whose predicted time
+ * c1_ms * updates + c2_ms * cropped is least, and that time (ms_out may be
+ * NULL): eq. (8)'s optimum, taken over the exact counts; c1_ms / c2_ms are a
+ * device's measured cost per update / per cropped sample. */
+fdkod_status fdkod_choose_s(const fdkod_params* prm, int32_t s_max, double c1_ms, double c2_ms, int32_t* s_out,
+                            double* ms_out);
+
 /* ------------------------------------------------------------------ batches
  * Many volumes of different sizes reconstructed together (the decomposition of
  * Sec. 2.1 applied to every volume): one grouped decimation launch over all
@@ -313,10 +330,33 @@ fdkod_status fdkod_learned_backward(fdkod_plan_t plan, const void* filt, const f
 fdkod_status fdkod_reconstruct_adjoint(fdkod_plan_t plan, const float* resid, float* dws,
                                        fdkod_stream_t stream);
 
+/* The learned filter on a band of detector rows (the slab mode below; a band
+ * holds the rows eq. (9) maps a slab of slices to), for training on slabs:
+ * the same results, row for row, as the whole-volume calls on those rows.
+ * Buffers: filt_band store type [P][nrows][N]; ws_band / dws_band the
+ * workspace blocks [P'][nrows][W_q] of square q from element offset
+ * nrows P' sum_{q' < q} W_q' (store type / float32); resid_slab float32
+ * [nzs][N][N], slices [z0, z0 + nzs).  fdkod_reconstruct_adjoint_slab is the
+ * transpose of fdkod_reconstruct_slab: FDKOD_E_ARG when the band misses a row
+ * the slab samples. */
+fdkod_status fdkod_learned_decompose_band(fdkod_plan_t plan, const void* filt_band, int32_t v0, int32_t nrows,
+                                          void* ws_band, const uint16_t* weights, fdkod_stream_t stream);
+fdkod_status fdkod_learned_backward_band(fdkod_plan_t plan, const void* filt_band, int32_t v0, int32_t nrows,
+                                         const float* dws_band, const uint16_t* weights, float* grad,
+                                         fdkod_stream_t stream);
+fdkod_status fdkod_reconstruct_adjoint_slab(fdkod_plan_t plan, const float* resid_slab, int32_t v0, int32_t nrows,
+                                            int32_t z0, int32_t nzs, float* dws_band, fdkod_stream_t stream);
+
 /* Squared-error residual on the current device: resid = 2 (f - ref) and
  * *loss = sum (f - ref)^2 (float64, on the device), over count floats. */
 fdkod_status fdkod_sq_residual(const float* f, const float* ref, float* resid, double* loss,
                                int64_t count, fdkod_stream_t stream);
+
+/* The same with a weight w: resid = 2 w (f - ref), *loss = w sum (f - ref)^2
+ * (training on slabs of different energy weights each slab's squared error,
+ * e.g. by the inverse of its target's energy). */
+fdkod_status fdkod_sq_residual_weighted(const float* f, const float* ref, float* resid, double* loss,
+                                        int64_t count, float weight, fdkod_stream_t stream);
 
 /* One AdamW step on the current device over count float32 master weights
  * (bias-corrected moments m1, m2; decoupled weight decay), then their BF16
@@ -406,6 +446,19 @@ fdkod_status fdkod_reconstruct_streamed(fdkod_plan_t plan, const float* host_pro
 
 fdkod_status fdkod_backproject_noalloc(fdkod_plan_t plan, const void* filt, float* vol,
                                        fdkod_stream_t stream);
+
+/* Checked builds (the library compiled with FDKOD_CHECKS defined): counts of
+ * events that the plan's geometry is meant to rule out, per kind, summed over
+ * every launch on the current device since the last reset:
+ *   [0] backprojection z runs whose detector rows fall outside the block's
+ *       staged footprint (they contribute zero)
+ *   [1] backprojection columns outside the staged footprint (clamped)
+ *   [2] decimation reads beyond the staged row segment
+ *   [3] reserved (zero)
+ * counts: host array of n (1..4) int64 values; reset != 0 clears the counters
+ * after reading.  Synchronises the current device.  Unchecked builds return
+ * FDKOD_E_UNSUPPORTED. */
+fdkod_status fdkod_check_counts(int64_t* counts, int32_t n, int32_t reset);
 
 /* Static text for a status code. */
 const char* fdkod_status_str(fdkod_status st);

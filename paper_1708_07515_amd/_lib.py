@@ -69,6 +69,11 @@ EXPORTS = {
                                          ctypes.c_void_p, ctypes.c_void_p]),
     "fdkod_get_bounds": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 7),
     "fdkod_backproject_noalloc": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "fdkod_check_counts": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, ctypes.c_int32]),
+    "fdkod_cost_counts": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int64)]),
+    "fdkod_choose_s": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "fdkod_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning)]),
     "fdkod_set_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(Tuning)]),
     "fdkod_tune": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(Tuning)]),
@@ -87,7 +92,13 @@ EXPORTS = {
     "fdkod_learned_decompose": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "fdkod_learned_backward": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "fdkod_reconstruct_adjoint": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "fdkod_learned_decompose_band": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP]),
+    "fdkod_learned_backward_band": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP,
+                                                   _VP]),
+    "fdkod_reconstruct_adjoint_slab": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                      ctypes.c_int32, _VP, _VP]),
     "fdkod_sq_residual": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int64, _VP]),
+    "fdkod_sq_residual_weighted": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int64, ctypes.c_float, _VP]),
     "fdkod_adamw_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32]
                          + [ctypes.c_float] * 5 + [_VP]),
     "fdkod_band_rows": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
@@ -156,6 +167,43 @@ def validate(n, p, r, s=0, skip=0, nz=0, store="f32", decim="triangle", taps=0, 
 LEARNED_PARAMS = 817
 
 
+# Cost constants of the FP32 kernels on one MI355X, ms per voxel-angle update
+# of the reconstruction and per cropped sample of the decomposition (fitted
+# by study.py's time split; see cost_counts and choose_s).
+MI355X_COSTS = (3.7e-10, 3.7e-10)
+
+
+def cost_counts(n, p, r, s=0, skip=0, nz=0, **kw):
+    """(cropped samples, voxel-angle updates) of one reconstruction, the two
+    counts of the cost model (eq. (6)-(7))."""
+    lib = load_library()
+    prm = _params(n, p, r, s, skip, nz, **kw)
+    cropped, updates = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib.fdkod_cost_counts(ctypes.byref(prm), ctypes.byref(cropped), ctypes.byref(updates)))
+    return cropped.value, updates.value
+
+
+def choose_s(n, p, r, skip=0, nz=0, s_max=6, costs=MI355X_COSTS, **kw):
+    """The s with the least predicted time (eq. (8) over the exact counts)
+    and that time in ms."""
+    lib = load_library()
+    prm = _params(n, p, r, 0, 0, nz, **kw)
+    prm.skip = int(skip)
+    s_out, ms = ctypes.c_int32(), ctypes.c_double()
+    _check(lib.fdkod_choose_s(ctypes.byref(prm), int(s_max), float(costs[0]), float(costs[1]),
+                              ctypes.byref(s_out), ctypes.byref(ms)))
+    return s_out.value, ms.value
+
+
+def check_counts(reset=True):
+    """Event counts of a checked build (list of 4 ints, see fdkod.h); raises
+    E_UNSUPPORTED on an unchecked build."""
+    lib = load_library()
+    arr = (ctypes.c_int64 * 4)()
+    _check(lib.fdkod_check_counts(arr, 4, 1 if reset else 0))
+    return [int(x) for x in arr]
+
+
 def _dev_tensor(t, dtype, name, numel=None):
     if t is None or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
         raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
@@ -172,6 +220,18 @@ def sq_residual(f, ref, resid, loss, stream=None):
     _check(load_library().fdkod_sq_residual(
         ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(ref.data_ptr()),
         ctypes.c_void_p(resid.data_ptr()), ctypes.c_void_p(loss.data_ptr()), f.numel(),
+        _stream_ptr(stream)))
+
+
+def sq_residual_weighted(f, ref, resid, loss, weight, stream=None):
+    """resid = 2 w (f - ref), loss[0] = w sum (f - ref)^2."""
+    import torch
+    for t, nm in ((f, "f"), (ref, "ref"), (resid, "resid")):
+        _dev_tensor(t, torch.float32, nm, f.numel())
+    _dev_tensor(loss, torch.float64, "loss", 1)
+    _check(load_library().fdkod_sq_residual_weighted(
+        ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(ref.data_ptr()),
+        ctypes.c_void_p(resid.data_ptr()), ctypes.c_void_p(loss.data_ptr()), f.numel(), float(weight),
         _stream_ptr(stream)))
 
 
@@ -441,6 +501,37 @@ class Plan:
             self._h, ctypes.c_void_p(filt_band.data_ptr() if filt_band is not None else 0),
             ctypes.c_void_p(ws_band.data_ptr() if ws_band is not None else 0), int(v0), int(nrows), int(z0),
             nzs, ctypes.c_void_p(vol_slab.data_ptr()), _stream_ptr(stream)))
+
+    # the learned filter on bands (training on slabs) ---------------------
+    def learned_decompose_band(self, filt_band, v0, ws_band, weights, stream=None):
+        nr = filt_band.shape[1]
+        self._chk(filt_band, (self.p, nr, self.n), self.store_torch_dtype(), "filt_band")
+        if ws_band.numel() * ws_band.element_size() < self.band_workspace_elems(nr) * _STORE_BYTES[self.store]:
+            raise ValueError("workspace band too small")
+        self._chk_weights(weights)
+        _check(self._lib.fdkod_learned_decompose_band(
+            self._h, ctypes.c_void_p(filt_band.data_ptr()), int(v0), nr, ctypes.c_void_p(ws_band.data_ptr()),
+            ctypes.c_void_p(weights.data_ptr()), _stream_ptr(stream)))
+
+    def learned_backward_band(self, filt_band, v0, dws_band, weights, grad, stream=None):
+        import torch
+        nr = filt_band.shape[1]
+        self._chk(filt_band, (self.p, nr, self.n), self.store_torch_dtype(), "filt_band")
+        self._chk(dws_band, (self.band_workspace_elems(nr),), torch.float32, "dws_band")
+        self._chk_weights(weights)
+        self._chk(grad, (LEARNED_PARAMS,), torch.float32, "grad")
+        _check(self._lib.fdkod_learned_backward_band(
+            self._h, ctypes.c_void_p(filt_band.data_ptr()), int(v0), nr, ctypes.c_void_p(dws_band.data_ptr()),
+            ctypes.c_void_p(weights.data_ptr()), ctypes.c_void_p(grad.data_ptr()), _stream_ptr(stream)))
+
+    def reconstruct_adjoint_slab(self, resid_slab, v0, nrows, z0, dws_band, stream=None):
+        import torch
+        nzs = resid_slab.shape[0]
+        self._chk(resid_slab, (nzs, self.n, self.n), torch.float32, "resid_slab")
+        self._chk(dws_band, (self.band_workspace_elems(nrows),), torch.float32, "dws_band")
+        _check(self._lib.fdkod_reconstruct_adjoint_slab(
+            self._h, ctypes.c_void_p(resid_slab.data_ptr()), int(v0), int(nrows), int(z0), nzs,
+            ctypes.c_void_p(dws_band.data_ptr()), _stream_ptr(stream)))
 
     def streamed_bytes(self, nzs):
         b = ctypes.c_int64()

@@ -14,6 +14,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfdkod.so")
+# the checked build: the same sources with FDKOD_CHECKS defined (kernels count
+# the events the host's planning should rule out; see fdkod_check_counts)
+LIB_CHECKED = os.path.join(HERE, "libfdkod_checked.so")
 
 # Per-file options.  The learned convolutions keep their MFMA accumulators in
 # ordinary VGPRs (no AGPR copies), which lowers their register count to five
@@ -28,14 +31,18 @@ def hipcc():
     return "hipcc"
 
 
-def build(verbose=False, jobs=8):
+def build(verbose=False, jobs=8, checked=False):
+    """Compile every .hip file of csrc/ and link libfdkod.so (checked=True:
+    libfdkod_checked.so with FDKOD_CHECKS defined); returns its path."""
     srcs = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
-    objdir = os.path.join(HERE, "_build")
+    objdir = os.path.join(HERE, "_build_checked" if checked else "_build")
     os.makedirs(objdir, exist_ok=True)
     flags = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-command-line-argument",
              "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+    if checked:
+        flags.append("-DFDKOD_CHECKS")
     procs, objs = [], []
     for src in srcs:
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
@@ -48,13 +55,14 @@ def build(verbose=False, jobs=8):
             _wait(procs)
             procs = []
     _wait(procs)
-    tmp = LIB + ".tmp"
+    lib = LIB_CHECKED if checked else LIB
+    tmp = lib + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
     if out.returncode != 0:
         raise RuntimeError("link failed:\n" + out.stdout.decode())
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 def _wait(procs):
@@ -71,4 +79,4 @@ def _wait(procs):
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, checked="--checked" in sys.argv))

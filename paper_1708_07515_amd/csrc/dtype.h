@@ -23,6 +23,11 @@ template <> struct Store<0> {
     static __device__ __forceinline__ void put_raw(__amdgpu_buffer_rsrc_t r, int off, float v) {
         __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
     }
+    // the stored bits, unconverted (zero when out of range), and their value
+    static __device__ __forceinline__ uint32_t raw_bits(__amdgpu_buffer_rsrc_t r, int off) {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+    }
+    static __device__ __forceinline__ float from_bits(uint32_t b) { return __uint_as_float(b); }
 };
 
 template <> struct Store<1> {
@@ -36,6 +41,12 @@ template <> struct Store<1> {
     }
     static __device__ __forceinline__ void put_raw(__amdgpu_buffer_rsrc_t r, int off, float v) {
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r, off, 0, 0);
+    }
+    static __device__ __forceinline__ uint32_t raw_bits(__amdgpu_buffer_rsrc_t r, int off) {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+    }
+    static __device__ __forceinline__ float from_bits(uint32_t b) {
+        return (float)__builtin_bit_cast(_Float16, (unsigned short)b);
     }
 };
 
@@ -60,6 +71,10 @@ template <> struct Store<2> {
     static __device__ __forceinline__ void put_raw(__amdgpu_buffer_rsrc_t r, int off, float v) {
         __builtin_amdgcn_raw_buffer_store_b16((unsigned short)enc(v), r, off, 0, 0);
     }
+    static __device__ __forceinline__ uint32_t raw_bits(__amdgpu_buffer_rsrc_t r, int off) {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+    }
+    static __device__ __forceinline__ float from_bits(uint32_t b) { return __uint_as_float(b << 16); }
 };
 
 inline int store_bytes(int s) { return s == 0 ? 4 : 2; }

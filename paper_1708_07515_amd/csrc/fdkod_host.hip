@@ -282,11 +282,27 @@ DecimVol decim_args_band(const fdkod_plan_s* pl, const void* filt, void* ws, int
     a.nsq = pl->nsq;
     a.v0 = v0;
     a.nv = nv;
-    a.tasks_per_sq = dec_tasks_per_sq(pl->wmax, chunks);
-    const int rpt = decim_rows_per_task(pl->cone != 0, pl->cubic != 0, chunks);
+    const int ch = chunks > 0 ? chunks : 1;
+    a.tasks_per_sq = dec_tasks_per_sq(pl->wmax, ch);
+    const int rpt = decim_rows_per_task(pl->cone != 0, pl->cubic != 0, ch);
     a.ntasks = pl->nsq * ((nv + rpt - 1) / rpt) * a.tasks_per_sq;
-    a.chunks = chunks;
+    a.chunks = ch;
+    a.bside = pl->s > 0 ? 1 << (pl->s - 1) : 0;
+    a.blo = pl->d_blo;
+    a.sqoff = pl->d_sqoff;
     return a;
+}
+
+fdkod_status enqueue_decimate(const fdkod_plan_s* pl, const void* filt, void* ws, int v0, int nv,
+                              hipStream_t st) {
+    const DecimVol a = decim_args_band(pl, filt, ws, pl->dec_chunks, v0, nv);
+    if (pl->dec_chunks == 0) {
+        HIP_TRY(launch_decimate_staged(a, pl->staged_cpt, pl->staged_segc, pl->store, st),
+                "row-staged decimation kernel launch");
+    } else {
+        HIP_TRY(launch_decimate(a, pl->dec_chunks, pl->store, st), "decimate kernel launch");
+    }
+    return FDKOD_OK;
 }
 
 FilterArgs filter_args(const fdkod_plan_s* pl, const float* proj, void* filt, int v0, int nv) {
@@ -347,6 +363,54 @@ BpVol bp_vol_band(const fdkod_plan_s* pl, const void* filt, const void* ws, floa
 
 namespace {
 
+// Shape of the row-staged decimation for a plan, or none (staged_cpt = 0):
+// it takes the paper's plain decimation (detector rows, triangle, linear
+// shift) with s >= 1 and squares at most 256 columns wide.  A staged segment
+// must hold, at every schedule step, every local column of the four squares
+// of a 2 x 2 block from the least of their crop offsets: the spread of the
+// offsets (read back from the bounds kernel's crop table) plus 64 cpt
+// columns and the interpolation's second sample.
+fdkod_status staged_shape(fdkod_plan_s* pl) {
+    pl->staged_cpt = pl->staged_segc = 0;
+    if (pl->s < 1 || pl->cone || pl->sinc || pl->cubic) return FDKOD_OK;
+    int cpt = 1;
+    while (cpt < 4 && 64 * cpt < pl->wmax) cpt <<= 1;
+    if (64 * cpt < pl->wmax) return FDKOD_OK;
+    std::vector<int2> crop((size_t)pl->nsq * pl->nsched);
+    HIP_TRY(hipMemcpy(crop.data(), pl->d_crop, sizeof(int2) * crop.size(), hipMemcpyDeviceToHost),
+            "hipMemcpy crop table");
+    const int side = 1 << pl->s, bside = side / 2;
+    std::vector<int> blo((size_t)bside * bside * pl->nsched);
+    std::vector<int2> sqoff(crop.size());
+    int spread = 0;
+    for (int by = 0; by < bside; ++by)
+        for (int bx = 0; bx < bside; ++bx) {
+            const int q0 = (2 * by) * side + 2 * bx;
+            const int qs[4] = {q0, q0 + 1, q0 + side, q0 + side + 1};
+            for (int e = 0; e < pl->nsched; ++e) {
+                int lo = crop[(size_t)qs[0] * pl->nsched + e].x, hi = lo;
+                for (int i = 1; i < 4; ++i) {
+                    const int o = crop[(size_t)qs[i] * pl->nsched + e].x;
+                    lo = std::min(lo, o);
+                    hi = std::max(hi, o);
+                }
+                spread = std::max(spread, hi - lo);
+                blo[(size_t)(by * bside + bx) * pl->nsched + e] = lo;
+                for (int i = 0; i < 4; ++i) {
+                    const int2 c = crop[(size_t)qs[i] * pl->nsched + e];
+                    sqoff[(size_t)qs[i] * pl->nsched + e] = make_int2(c.x - lo, c.y);
+                }
+            }
+        }
+    const int segc = (spread + 64 * cpt + 1 + 63) / 64;
+    if (!staged_shape_exists(cpt, segc)) return FDKOD_OK;
+    fdkod_status st = upload(pl, &pl->d_blo, blo);
+    if (st == FDKOD_OK) st = upload(pl, &pl->d_sqoff, sqoff);
+    if (st != FDKOD_OK) return st;
+    pl->staged_cpt = cpt;
+    pl->staged_segc = segc;
+    return FDKOD_OK;
+}
 
 std::string tune_key(const fdkod_plan_s* pl) {
     std::ostringstream k;
@@ -431,6 +495,88 @@ const char* fdkod_status_str(fdkod_status st) {
 const char* fdkod_last_error(void) { return fdkod::g_last_error.c_str(); }
 
 int32_t fdkod_version(void) { return 100; }
+
+fdkod_status fdkod_cost_counts(const fdkod_params* prm, int64_t* cropped, int64_t* updates) {
+    fdkod_status st = fdkod_validate(prm);
+    if (st != FDKOD_OK) return st;
+    if (!cropped || !updates) return fail(FDKOD_E_ARG, "NULL argument");
+    const int n = prm->n, nz = prm->nz ? prm->nz : prm->n, s = prm->s;
+    const int d = 1 << (prm->s - prm->skip);
+    const int pd = (int)ceildiv(prm->p, d);
+    *updates = (int64_t)n * n * nz * (s == 0 ? prm->p : pd);
+    *cropped = 0;
+    if (s == 0) return FDKOD_OK;
+    // the local grid of every square as the bounds kernel forms it, in FP64:
+    // eq. (1) at the vertices relative to the centre trajectory, extremes over
+    // the decimated angles
+    const double c = (n - 1) / 2.0, r = prm->r;
+    const auto bl = blocks(n, 1 << s);
+    int64_t sum_w = 0;
+    for (auto& by : bl)
+        for (auto& bx : bl) {
+            const double xc = 0.5 * ((bx.first - c) + (bx.second - 1 - c));
+            const double yc = 0.5 * ((by.first - c) + (by.second - 1 - c));
+            const double vx[2] = {bx.first - c, bx.second - 1 - c}, vy[2] = {by.first - c, by.second - 1 - c};
+            double emin = 1e300, emax = -1e300;
+            for (int m = 0; m < pd; ++m) {
+                const double b = 2.0 * M_PI * m / pd, cs = std::cos(b), sn = std::sin(b);
+                const double ac = r * (yc * cs - xc * sn) / (r + xc * cs + yc * sn);
+                for (int k = 0; k < 4; ++k) {
+                    const double x = vx[k & 1], y = vy[k >> 1];
+                    const double e = r * (y * cs - x * sn) / (r + x * cs + y * sn) - ac;
+                    emin = std::min(emin, e);
+                    emax = std::max(emax, e);
+                }
+            }
+            const int u0 = (int)std::floor(emin + c);
+            sum_w += (int64_t)((int)std::floor(emax + c) - u0 + 2);
+        }
+    *cropped = sum_w * prm->p * n;
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_choose_s(const fdkod_params* prm, int32_t s_max, double c1_ms, double c2_ms, int32_t* s_out,
+                            double* ms_out) {
+    if (!prm || !s_out) return fail(FDKOD_E_ARG, "NULL argument");
+    if (!(c1_ms > 0.0) || !(c2_ms >= 0.0) || s_max < 0) return fail(FDKOD_E_ARG, "invalid cost constants or s_max");
+    double best = 1e300;
+    int best_s = -1;
+    for (int s = 0; s <= s_max && (1 << s) <= prm->n; ++s) {
+        fdkod_params q = *prm;
+        q.s = s;
+        q.skip = std::min(prm->skip, s);
+        if (fdkod_validate(&q) != FDKOD_OK) continue;
+        int64_t cropped = 0, updates = 0;
+        fdkod_status st = fdkod_cost_counts(&q, &cropped, &updates);
+        if (st != FDKOD_OK) return st;
+        const double t = c1_ms * (double)updates + c2_ms * (double)cropped;
+        if (t < best) {
+            best = t;
+            best_s = s;
+        }
+    }
+    if (best_s < 0) return fail(FDKOD_E_GEOMETRY, "no valid s for these parameters");
+    *s_out = best_s;
+    if (ms_out) *ms_out = best;
+    g_last_error.clear();
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_check_counts(int64_t* counts, int32_t n, int32_t reset) {
+    if (!counts || n < 1 || n > kCheckKinds) return fail(FDKOD_E_ARG, "counts must hold 1..4 values");
+#ifdef FDKOD_CHECKS
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    unsigned long long sum[kCheckKinds] = {};
+    HIP_TRY(checks_read_backproject(sum, reset != 0), "reading the backprojection's check counters");
+    HIP_TRY(checks_read_decimate(sum, reset != 0), "reading the decimation's check counters");
+    for (int k = 0; k < n; ++k) counts[k] = (int64_t)sum[k];
+    return FDKOD_OK;
+#else
+    (void)reset;
+    for (int k = 0; k < n; ++k) counts[k] = 0;
+    return fail(FDKOD_E_UNSUPPORTED, "not a checked build (FDKOD_CHECKS undefined)");
+#endif
+}
 
 fdkod_status fdkod_validate(const fdkod_params* prm) {
     if (!prm) return fail(FDKOD_E_ARG, "params is NULL");
@@ -589,13 +735,15 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
         if (e != hipSuccess) return bail(hip_fail(e, "hipMemcpy squares"));
     }
 
-    // default kernel shapes: 64 * chunks local columns per decimation wavefront
-    // (the smallest power of two covering the widest square, at most 8), and
-    // the longest z run whose block footprint fits an LDS tile, two angles per
-    // stage
+    // default kernel shapes: the row-staged decimation where it applies (the
+    // paper's plain decimation), else 64 * chunks local columns per
+    // decimation wavefront (the smallest power of two covering the widest
+    // square, at most 8); the longest z run whose block footprint fits an LDS
+    // tile, one angle per stage
+    if ((st = staged_shape(pl)) != FDKOD_OK) return bail(st);
     int ch = 1;
     while (ch < max_chunks(pl) && 64 * ch < pl->wmax) ch <<= 1;
-    pl->dec_chunks = ch;
+    pl->dec_chunks = pl->staged_cpt ? 0 : ch;
     pl->bp_ok = false;
     for (int zr : {32, 16, 64}) {
         int tw = 0, th = 0;
@@ -611,7 +759,7 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
         BpVariant cv{};
         int cc = 0;
         if (pl->bp_ok && tune_cache_lookup(pl, &cv, &cc) && variant_holds(pl, cv) &&
-            (cc == 1 || cc == 2 || cc == 4 || cc == 8) && cc <= max_chunks(pl)) {
+            ((cc == 0 && pl->staged_cpt) || cc == 1 || cc == 2 || cc == 4 || cc == 8) && cc <= max_chunks(pl)) {
             pl->bpv = cv;
             pl->dec_chunks = cc;
         }
@@ -626,6 +774,12 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
     if ((int64_t)pl->ntiles * bp_zslabs(pl->nz, 16) > (int64_t)1 << 30)
         return bail(fail(FDKOD_E_UNSUPPORTED, "volume too large for one launch"));
     if ((st = upload(pl, &pl->d_tiles, tiles)) != FDKOD_OK) return bail(st);
+    // the learned filter's backward pass sums its workgroups' partial
+    // gradients in a fixed order (a plan the filter applies to only)
+    if (pl->s > 0 && !pl->cone && !pl->sinc && !pl->cubic && pl->wmax <= kLearnedMaxWidth && pl->p <= kLearnedMaxP &&
+        (st = dev_alloc(pl->allocs, (void**)&pl->d_lpartials,
+                        sizeof(float) * (size_t)kLearnedBwdGrid * kLearnedParams)) != FDKOD_OK)
+        return bail(st);
 
     (void)hipSetDevice(prev);
     *out = pl;
@@ -686,9 +840,7 @@ fdkod_status fdkod_decompose(fdkod_plan_t pl, const void* filt, void* ws, fdkod_
     if (!pl || !filt) return fail(FDKOD_E_ARG, "NULL argument");
     if (pl->s == 0) return FDKOD_OK;
     if (!ws) return fail(FDKOD_E_ARG, "workspace is NULL");
-    const DecimVol a = decim_args(pl, filt, ws, pl->dec_chunks);
-    HIP_TRY(launch_decimate(a, pl->dec_chunks, pl->store, (hipStream_t)stream), "decimate kernel launch");
-    return FDKOD_OK;
+    return enqueue_decimate(pl, filt, ws, 0, pl->n, (hipStream_t)stream);
 }
 
 fdkod_status fdkod_reconstruct(fdkod_plan_t pl, const void* filt, const void* ws, float* vol,
@@ -771,7 +923,10 @@ fdkod_status fdkod_set_tuning(fdkod_plan_t pl, const fdkod_tuning* t) {
     if (!variant_holds(pl, v))
         return fail(FDKOD_E_UNSUPPORTED, "backprojection variant missing or too small for this geometry");
     const int c = t->decim_chunks;
-    if (!(c == 1 || c == 2 || c == 4 || c == 8)) return fail(FDKOD_E_UNSUPPORTED, "decim_chunks must be 1, 2, 4 or 8");
+    if (c == 0 && !pl->staged_cpt)
+        return fail(FDKOD_E_UNSUPPORTED, "the row-staged decimation does not apply to this plan");
+    if (!(c == 0 || c == 1 || c == 2 || c == 4 || c == 8))
+        return fail(FDKOD_E_UNSUPPORTED, "decim_chunks must be 0, 1, 2, 4 or 8");
     if (c > max_chunks(pl))
         return fail(FDKOD_E_UNSUPPORTED, "decim_chunks above 4 with more than two decimation windows");
     pl->bpv = v;
@@ -791,8 +946,8 @@ fdkod_status fdkod_tune(fdkod_plan_t pl, const void* filt, void* ws, float* vol,
     if (pl->s > 0) {
         float best = 1e30f;
         int bestc = pl->dec_chunks;
-        for (int c : {1, 2, 4, 8}) {
-            if (c > max_chunks(pl)) continue;
+        for (int c : {0, 1, 2, 4, 8}) {
+            if (c > max_chunks(pl) || (c == 0 && !pl->staged_cpt)) continue;
             pl->dec_chunks = c;
             float ms = 0.0f;
             r = time_ms(st, 3, [&] { return fdkod_decompose(pl, filt, ws, stream); }, &ms);

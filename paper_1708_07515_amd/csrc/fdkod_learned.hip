@@ -22,7 +22,7 @@ fdkod_status learned_check(const fdkod_plan_s* pl) {
 }
 
 LearnedArgs learned_args(const fdkod_plan_s* pl, const void* filt, void* ws, const float* dws,
-                         const uint16_t* w, float* grad) {
+                         const uint16_t* w, float* grad, int nv) {
     LearnedArgs a;
     a.filt = filt;
     a.ws = ws;
@@ -32,13 +32,47 @@ LearnedArgs learned_args(const fdkod_plan_s* pl, const void* filt, void* ws, con
     a.ac_p = pl->d_ac_p;
     a.w = w;
     a.grad = grad;
+    a.partials = pl->d_lpartials;
     a.n = pl->n;
     a.p = pl->p;
     a.pd = pl->pd;
     a.nsq = pl->nsq;
     a.d = pl->d / 4 > 1 ? pl->d / 4 : 1;
-    a.ntasks = pl->nsq * pl->n;
+    a.nv = nv;
+    a.ntasks = pl->nsq * nv;
     return a;
+}
+
+AdjArgs adjoint_args(const fdkod_plan_s* pl, const float* resid, float* dws, int v0, int nv, int zbase,
+                     int nzs) {
+    AdjArgs a;
+    a.resid = resid;
+    a.dws = dws;
+    a.squares = pl->d_sq;
+    a.grid = pl->d_grid;
+    a.trig = pl->d_trig_m;
+    a.tiles = pl->d_tiles;
+    a.ntiles = pl->ntiles;
+    a.n = pl->n;
+    a.nz = nzs;
+    a.pd = pl->pd;
+    a.v0 = v0;
+    a.nv = nv;
+    a.zbase = zbase;
+    a.r = (float)pl->r;
+    a.cu = (float)((pl->n - 1) / 2.0);
+    a.cv = a.cu;
+    a.cz = (float)((pl->nz - 1) / 2.0);
+    a.scale = (float)(M_PI / pl->pd);
+    a.ws_elems = pl->ws_row_elems * nv;
+    return a;
+}
+
+fdkod_status adjoint_check(const fdkod_plan_s* pl) {
+    if (pl->s == 0) return fail(FDKOD_E_UNSUPPORTED, "the adjoint is defined for s > 0");
+    if (pl->cone)
+        return fail(FDKOD_E_UNSUPPORTED, "the adjoint samples detector rows, not cone-corrected rows");
+    return FDKOD_OK;
 }
 
 }  // namespace
@@ -51,7 +85,20 @@ fdkod_status fdkod_learned_decompose(fdkod_plan_t pl, const void* filt, void* ws
     fdkod_status st = learned_check(pl);
     if (st != FDKOD_OK) return st;
     if ((st = fdkod_decompose(pl, filt, ws, stream)) != FDKOD_OK) return st;
-    const LearnedArgs a = learned_args(pl, filt, ws, nullptr, weights, nullptr);
+    const LearnedArgs a = learned_args(pl, filt, ws, nullptr, weights, nullptr, pl->n);
+    HIP_TRY(launch_learned_fwd(a, pl->wmax, pl->d, pl->store, (hipStream_t)stream),
+            "learned decimation kernel launch");
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_learned_decompose_band(fdkod_plan_t pl, const void* filt_band, int32_t v0, int32_t nrows,
+                                          void* ws_band, const uint16_t* weights, fdkod_stream_t stream) {
+    if (!pl || !filt_band || !ws_band || !weights) return fail(FDKOD_E_ARG, "NULL argument");
+    fdkod_status st = learned_check(pl);
+    if (st != FDKOD_OK) return st;
+    if ((st = check_band(pl, v0, nrows)) != FDKOD_OK) return st;
+    if ((st = fdkod_decompose_band(pl, filt_band, v0, nrows, ws_band, stream)) != FDKOD_OK) return st;
+    const LearnedArgs a = learned_args(pl, filt_band, ws_band, nullptr, weights, nullptr, nrows);
     HIP_TRY(launch_learned_fwd(a, pl->wmax, pl->d, pl->store, (hipStream_t)stream),
             "learned decimation kernel launch");
     return FDKOD_OK;
@@ -62,7 +109,19 @@ fdkod_status fdkod_learned_backward(fdkod_plan_t pl, const void* filt, const flo
     if (!pl || !filt || !dws || !weights || !grad) return fail(FDKOD_E_ARG, "NULL argument");
     fdkod_status st = learned_check(pl);
     if (st != FDKOD_OK) return st;
-    const LearnedArgs a = learned_args(pl, filt, nullptr, dws, weights, grad);
+    const LearnedArgs a = learned_args(pl, filt, nullptr, dws, weights, grad, pl->n);
+    HIP_TRY(launch_learned_bwd(a, pl->store, (hipStream_t)stream), "learned gradient kernel launch");
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_learned_backward_band(fdkod_plan_t pl, const void* filt_band, int32_t v0, int32_t nrows,
+                                         const float* dws_band, const uint16_t* weights, float* grad,
+                                         fdkod_stream_t stream) {
+    if (!pl || !filt_band || !dws_band || !weights || !grad) return fail(FDKOD_E_ARG, "NULL argument");
+    fdkod_status st = learned_check(pl);
+    if (st != FDKOD_OK) return st;
+    if ((st = check_band(pl, v0, nrows)) != FDKOD_OK) return st;
+    const LearnedArgs a = learned_args(pl, filt_band, nullptr, dws_band, weights, grad, nrows);
     HIP_TRY(launch_learned_bwd(a, pl->store, (hipStream_t)stream), "learned gradient kernel launch");
     return FDKOD_OK;
 }
@@ -70,26 +129,21 @@ fdkod_status fdkod_learned_backward(fdkod_plan_t pl, const void* filt, const flo
 fdkod_status fdkod_reconstruct_adjoint(fdkod_plan_t pl, const float* resid, float* dws,
                                        fdkod_stream_t stream) {
     if (!pl || !resid || !dws) return fail(FDKOD_E_ARG, "NULL argument");
-    if (pl->s == 0) return fail(FDKOD_E_UNSUPPORTED, "the adjoint is defined for s > 0");
-    if (pl->cone)
-        return fail(FDKOD_E_UNSUPPORTED, "the adjoint samples detector rows, not cone-corrected rows");
-    AdjArgs a;
-    a.resid = resid;
-    a.dws = dws;
-    a.squares = pl->d_sq;
-    a.grid = pl->d_grid;
-    a.trig = pl->d_trig_m;
-    a.tiles = pl->d_tiles;
-    a.ntiles = pl->ntiles;
-    a.n = pl->n;
-    a.nz = pl->nz;
-    a.pd = pl->pd;
-    a.r = (float)pl->r;
-    a.cu = (float)((pl->n - 1) / 2.0);
-    a.cv = a.cu;
-    a.cz = (float)((pl->nz - 1) / 2.0);
-    a.scale = (float)(M_PI / pl->pd);
-    a.ws_elems = pl->ws_elems;
+    fdkod_status st = adjoint_check(pl);
+    if (st != FDKOD_OK) return st;
+    const AdjArgs a = adjoint_args(pl, resid, dws, 0, pl->n, 0, pl->nz);
+    HIP_TRY(launch_bp_adjoint(a, (hipStream_t)stream), "adjoint kernel launch");
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_reconstruct_adjoint_slab(fdkod_plan_t pl, const float* resid_slab, int32_t v0, int32_t nrows,
+                                            int32_t z0, int32_t nzs, float* dws_band, fdkod_stream_t stream) {
+    if (!pl || !resid_slab || !dws_band) return fail(FDKOD_E_ARG, "NULL argument");
+    fdkod_status st = adjoint_check(pl);
+    if (st != FDKOD_OK) return st;
+    if ((st = check_band(pl, v0, nrows)) != FDKOD_OK) return st;
+    if ((st = check_slab(pl, v0, nrows, z0, nzs)) != FDKOD_OK) return st;
+    const AdjArgs a = adjoint_args(pl, resid_slab, dws_band, v0, nrows, z0, nzs);
     HIP_TRY(launch_bp_adjoint(a, (hipStream_t)stream), "adjoint kernel launch");
     return FDKOD_OK;
 }
@@ -98,7 +152,15 @@ fdkod_status fdkod_sq_residual(const float* f, const float* ref, float* resid, d
                                fdkod_stream_t stream) {
     if (!f || !ref || !resid || !loss) return fail(FDKOD_E_ARG, "NULL argument");
     if (count < 0) return fail(FDKOD_E_ARG, "negative count");
-    HIP_TRY(launch_residual(f, ref, resid, loss, count, (hipStream_t)stream), "residual kernel launch");
+    HIP_TRY(launch_residual(f, ref, resid, loss, count, 1.0f, (hipStream_t)stream), "residual kernel launch");
+    return FDKOD_OK;
+}
+
+fdkod_status fdkod_sq_residual_weighted(const float* f, const float* ref, float* resid, double* loss, int64_t count,
+                                        float weight, fdkod_stream_t stream) {
+    if (!f || !ref || !resid || !loss) return fail(FDKOD_E_ARG, "NULL argument");
+    if (count < 0 || !(weight >= 0.0f)) return fail(FDKOD_E_ARG, "negative count or weight");
+    HIP_TRY(launch_residual(f, ref, resid, loss, count, weight, (hipStream_t)stream), "residual kernel launch");
     return FDKOD_OK;
 }
 

@@ -11,7 +11,7 @@
 
 using namespace fdkod;
 
-namespace {
+namespace fdkod {
 
 // Detector rows [v0, v0 + nv) that the voxels of slices [z0, z0 + nzs) sample
 // at any angle: b = z R / depth (eq. (9)) over depth in [R - c sqrt2, R + c sqrt2]
@@ -50,6 +50,10 @@ fdkod_status check_slab(const fdkod_plan_s* pl, int v0, int nv, int z0, int nzs)
         return fail(FDKOD_E_ARG, "the band does not hold every row the slab samples (see fdkod_band_rows)");
     return FDKOD_OK;
 }
+
+}  // namespace fdkod
+
+namespace {
 
 struct StreamLayout {
     int slab = 0, maxnv = 0;
@@ -138,9 +142,7 @@ fdkod_status fdkod_decompose_band(fdkod_plan_t pl, const void* filt_band, int32_
     if ((st = check_rows_are_detector_rows(pl)) != FDKOD_OK) return st;
     if (pl->s == 0) return FDKOD_OK;
     if (!ws_band) return fail(FDKOD_E_ARG, "workspace is NULL");
-    const DecimVol a = decim_args_band(pl, filt_band, ws_band, pl->dec_chunks, v0, nrows);
-    HIP_TRY(launch_decimate(a, pl->dec_chunks, pl->store, (hipStream_t)stream), "decimate kernel launch");
-    return FDKOD_OK;
+    return enqueue_decimate(pl, filt_band, ws_band, v0, nrows, (hipStream_t)stream);
 }
 
 fdkod_status fdkod_reconstruct_slab(fdkod_plan_t pl, const void* filt_band, const void* ws_band, int32_t v0,

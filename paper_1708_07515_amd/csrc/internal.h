@@ -84,6 +84,9 @@ struct DecimVol {
     int tasks_per_sq;       // column groups per square
     int ntasks;             // nsq * ceil(nv / rows per task) * tasks_per_sq
     int chunks;             // 64-column chunks per wave (1, 2, 4 or 8)
+    int bside;              // 2^(s-1): 2 x 2 blocks of squares per side (row-staged kernel)
+    const int* blo;         // [bside^2][nsched] least crop offset of a block's squares (row-staged)
+    const int2* sqoff;      // [nsq][nsched] crop offset - block's least, bits of the fraction (row-staged)
 };
 
 // Many volumes in one launch: volume b owns tasks [start_b, start_b + ntasks_b)
@@ -150,6 +153,10 @@ struct BpVariant {
 hipError_t launch_bounds(const BoundsArgs& a, hipStream_t st);
 hipError_t launch_filter(const FilterArgs& a, int logm, int store, hipStream_t st);
 hipError_t launch_decimate(const DecimVol& a, int chunks, int store, hipStream_t st);
+// row-staged decimation (plain rows, triangle, linear shift): cpt 64-column
+// chunks per lane, segc 64-sample chunks per staged row segment
+bool staged_shape_exists(int cpt, int segc);
+hipError_t launch_decimate_staged(const DecimVol& a, int cpt, int segc, int store, hipStream_t st);
 hipError_t launch_decimate_batch(const DecimBatchArgs& a, int chunks, int store, hipStream_t st);
 hipError_t launch_backproject(const BpArgs& a, const BpVariant& var, int store, hipStream_t st);
 hipError_t launch_backproject_batch(const BpBatchArgs& a, const BpVariant& var, int store,
@@ -164,6 +171,7 @@ hipError_t launch_reset_counter(unsigned* counter, hipStream_t st);
 constexpr int kLearnedParams = 817;
 constexpr int kLearnedMaxWidth = 252;   // widest square (local columns) it takes
 constexpr int kLearnedMaxP = 2048;      // most projections it takes
+constexpr int kLearnedBwdGrid = 1024;   // workgroups of the backward pass (most)
 
 struct LearnedArgs {
     const void* filt;        // [P][N][N] store type
@@ -174,9 +182,11 @@ struct LearnedArgs {
     const float* ac_p;       // [nsq][P] a_c(beta_p)
     const uint16_t* w;       // BF16 parameters
     float* grad;             // [817] FP32 (backward, overwritten)
+    float* partials;         // [kLearnedBwdGrid][817] per-workgroup partial gradients (backward)
     int n, p, pd, nsq;
+    int nv;                  // detector rows held by filt / ws / dws (a band of them: N in the whole-volume calls)
     int d;                   // angle dilation max(1, D / 4)
-    int ntasks;              // nsq * n
+    int ntasks;              // nsq * nv
 };
 
 // Transpose of the per-square backprojection (training).
@@ -188,7 +198,9 @@ struct AdjArgs {
     const float2* trig;      // cos, sin of beta'_m, [pd]
     const BpTile* tiles;     // 16 x 16 (x, y) tiles of the squares
     int ntiles;
-    int n, nz, pd;
+    int n, nz, pd;           // nz: slices of resid (a slab of them: N_z in the whole-volume call)
+    int v0, nv;              // detector rows [v0, v0 + nv) held by dws
+    int zbase;               // volume slice of resid's slice 0
     float r, cu, cv, cz;
     float scale;             // pi / P'
     int64_t ws_elems;
@@ -208,9 +220,32 @@ struct AdamArgs {
 hipError_t launch_learned_fwd(const LearnedArgs& a, int max_width, int dfac, int store, hipStream_t st);
 hipError_t launch_learned_bwd(const LearnedArgs& a, int store, hipStream_t st);
 hipError_t launch_bp_adjoint(const AdjArgs& a, hipStream_t st);
-hipError_t launch_residual(const float* f, const float* ref, float* r, double* loss, int64_t count,
+hipError_t launch_residual(const float* f, const float* ref, float* r, double* loss, int64_t count, float weight,
                            hipStream_t st);
 hipError_t launch_adamw(const AdamArgs& a, hipStream_t st);
+
+// Checked builds (-DFDKOD_CHECKS).  Some kernel paths exist only to stay in
+// bounds when the host's planning has gone wrong (a backprojection z run
+// outside the staged detector rows contributes zero, a column outside the
+// staged footprint is clamped, a decimation read beyond the staged segment);
+// a checked build counts each such event in a device counter per kind, so
+// tests can require that none occurs.  Unchecked builds compile the counting
+// away.
+enum CheckKind { kCheckBpRows = 0, kCheckBpCols = 1, kCheckDecimSegment = 2, kCheckKinds = 4 };
+#ifdef FDKOD_CHECKS
+#define FDKOD_CHECK_EVENT(counters, kind, cond)            \
+    do {                                                   \
+        if (cond) atomicAdd(&(counters)[(kind)], 1u);      \
+    } while (0)
+#else
+#define FDKOD_CHECK_EVENT(counters, kind, cond) \
+    do {                                        \
+    } while (0)
+#endif
+// Each kernel file that counts keeps its own counters on the device; these
+// read (and optionally clear) them on the current device, adding to out.
+hipError_t checks_read_backproject(unsigned long long* out, bool reset);
+hipError_t checks_read_decimate(unsigned long long* out, bool reset);
 
 // Limits the host checks before choosing a backprojection variant.
 constexpr int kTileXY = 16;      // voxels per tile side in x and y

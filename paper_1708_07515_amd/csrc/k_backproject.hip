@@ -23,6 +23,21 @@
 
 namespace fdkod {
 
+// event counters of a checked build (see CheckKind)
+static __device__ unsigned g_checks_bp[kCheckKinds];
+
+hipError_t checks_read_backproject(unsigned long long* out, bool reset) {
+    unsigned h[kCheckKinds] = {};
+    hipError_t e = hipMemcpyFromSymbol(h, HIP_SYMBOL(g_checks_bp), sizeof(h), 0, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    for (int k = 0; k < kCheckKinds; ++k) out[k] += h[k];
+    if (reset) {
+        const unsigned z[kCheckKinds] = {};
+        e = hipMemcpyToSymbol(HIP_SYMBOL(g_checks_bp), z, sizeof(z), 0, hipMemcpyHostToDevice);
+    }
+    return e;
+}
+
 typedef float f2v __attribute__((ext_vector_type(2)));
 
 typedef __attribute__((address_space(3))) const char* lds_cptr;
@@ -129,42 +144,54 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
             sm.mgeo2[slot][threadIdx.x] = make_float2(v.r * rdc, kq - (float)c0);
         }
     };
-    // detector samples of the footprints of [m0, m0 + G) into registers, in
-    // the storage type (converted when staged, so no load is waited for
-    // early); columns outside [0, width) and rows outside the detector are
-    // zero.  Footprints of more than 16 samples per thread are loaded after
-    // the arithmetic instead (their registers would cost occupancy).
+    // detector samples of the footprints of [m0, m0 + G) into registers, as
+    // raw bits of the storage type (converted when staged, so no load is
+    // waited for early).  One buffer resource spans the angle's plane of the
+    // data: rows outside the buffer fall outside it and read zero (a row above
+    // the first wraps to a huge unsigned offset), and a column outside
+    // [0, width) gets an offset beyond every plane, so its samples read zero
+    // too.  A lane's samples are RSTEP rows apart, so each costs one add.
+    // Footprints of more than 16 samples per thread are loaded after the
+    // arithmetic instead (their registers would cost occupancy).
     constexpr bool kPrefetch = G * NR <= 16;
-    T pre[G][NR];
+    constexpr int ES = (int)sizeof(T);
+    const uint32_t plane_bytes = (uint32_t)(plane * ES);
+    const int rstep_bytes = RSTEP * row_stride * ES;
+    uint32_t pre[G][NR];
     auto fetch_one = [&](int slot, int m0, int g) {
         {
             const bool gok = m0 + g < v.pd;
             const int4 mt = gok ? sm.meta[slot][g] : make_int4(0, 0, 0, 0);
-            const T* pl = data + (size_t)(gok ? m0 + g : 0) * plane;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                uniform_ptr(data + (size_t)(gok ? m0 + g : 0) * plane), (short)0, (int)plane_bytes, 0x00020000);
             const int col = mt.x + scol;
-            const bool cok = (unsigned)col < (unsigned)width;
+            const int row = mt.y + srow - v.v0;           // row within the buffer
+            const int off0 = (unsigned)col < (unsigned)width ? (row * row_stride + col) * ES : (int)0x80000000;
+            // (each offset in its own register, never folded into the
+            // instruction's constant offset: the range check must see the
+            // whole offset of every sample)
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
-                const int rr = srow + r * RSTEP;
-                const int row = mt.y + rr - v.v0;        // row within the buffer
-                pre[g][r] = (rr < mt.z && cok && (unsigned)row < (unsigned)v.nv)
-                                ? pl[(size_t)row * row_stride + col] : (T)0;
+                int off = off0 + r * rstep_bytes;
+                asm volatile("" : "+v"(off));
+                pre[g][r] = S::raw_bits(rs, off);
             }
         }
     };
     // pairs (Y[c], Y[c+1] - Y[c]) into LDS; the last column's pair is never
     // read (the column index is at most TW - 2), so the lane that receives
-    // the next footprint row's first sample writes an unused pair
+    // the next footprint row's first sample writes an unused pair.  Rows
+    // below the footprint's last are written too: they lie inside the tile
+    // and are never read.
     auto stage_one = [&](int slot, int m0, int g) {
-        {
-            const int rows = m0 + g < v.pd ? sm.meta[slot][g].z : 0;
+        (void)slot;
+        (void)m0;
 #pragma unroll
-            for (int r = 0; r < NR; ++r) {
-                const int rr = srow + r * RSTEP;
-                const float y0 = S::cvt(pre[g][r]);
-                const float y1 = from_next_lane(y0);
-                if (rr < rows) tile[g][rr * TWP + scol] = make_float2(y0, y1 - y0);
-            }
+        for (int r = 0; r < NR; ++r) {
+            const int rr = srow + r * RSTEP;
+            const float y0 = S::from_bits(pre[g][r]);
+            const float y1 = from_next_lane(y0);
+            tile[g][rr * TWP + scol] = make_float2(y0, y1 - y0);
         }
     };
 
@@ -214,11 +241,13 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
             const float tf = floorf(tau);
             const float fu = tau - tf;
             const int ci = min(max((int)tf, 0), TW - 2);
+            FDKOD_CHECK_EVENT(g_checks_bp, kCheckBpCols, own && ((int)tf < 0 || (int)tf > TW - 2));
             float v0 = fmaf(z0, vstep, v.cv - (float)mt.y);
             // the row index is monotone in z: check the run's ends once; a
             // run outside the staged rows (never expected) contributes zero
             const float vend = fmaf((float)(ZR - 1), vstep, v0);
             if (!(v0 >= 0.0f && vend < (float)(mt.z - 1))) {
+                FDKOD_CHECK_EVENT(g_checks_bp, kCheckBpRows, own);
                 w = 0.0f;
                 v0 = 0.5f;
                 vstep = 0.0f;

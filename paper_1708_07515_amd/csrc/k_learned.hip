@@ -92,7 +92,7 @@ __device__ __forceinline__ void s_fetch_rows(const LearnedArgs& a, const float* 
         const float o = o_tab[p];
         const float of = floorf(o);
         ph[t] = o - of;
-        const __amdgpu_buffer_rsrc_t rs = row_rsrc((const T*)a.filt + ((size_t)p * a.n + v) * a.n, a.n);
+        const __amdgpu_buffer_rsrc_t rs = row_rsrc((const T*)a.filt + ((size_t)p * a.nv + v) * a.n, a.n);
         const int off0 = valid ? ((int)of + jj) * ES : -4 * ES;
         int off1 = off0 + ES;
         asm volatile("" : "+v"(off1));   // two separately range-checked loads, never one wider load
@@ -256,11 +256,11 @@ __device__ __forceinline__ bool fwd_task(const LearnedArgs& a, int& q, int& v) {
     const int x = (int)blockIdx.x % kXcds, i = (int)blockIdx.x / kXcds;
     q = i % a.nsq;
     v = (i / a.nsq) * kXcds + x;
-    return v < a.n;
+    return v < a.nv;
 }
 
 __host__ __device__ inline unsigned fwd_grid(const LearnedArgs& a) {
-    return (unsigned)a.nsq * kXcds * ((a.n + kXcds - 1) / kXcds);
+    return (unsigned)a.nsq * kXcds * ((a.nv + kXcds - 1) / kXcds);
 }
 
 // Forward (inference): Y(m) += R(m) for every decimated angle of one
@@ -294,8 +294,8 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd(LearnedArgs a) {
     const bool stager = col < width + 4;
     const bool valid = jj >= 0 && jj < width;
     T* ws = (T*)a.ws;
-    const size_t yrow = (size_t)a.squares[q].y_off_row * a.n + (size_t)v * width;   // + m n W + j
-    const size_t yplane = (size_t)a.n * width;
+    const size_t yrow = (size_t)a.squares[q].y_off_row * a.nv + (size_t)v * width;   // + m n W + j
+    const size_t yplane = (size_t)a.nv * width;
     const int j = threadIdx.x;                                           // output column
     CentreWalk cw(a.p, a.pd);
     __syncthreads();
@@ -372,7 +372,7 @@ __device__ __forceinline__ void ring_fetch(const LearnedArgs& a, const float* o_
     const float o = o_tab[p];
     const float of = floorf(o);
     ph = o - of;
-    const __amdgpu_buffer_rsrc_t rs = row_rsrc((const T*)a.filt + ((size_t)p * a.n + v) * a.n, a.n);
+    const __amdgpu_buffer_rsrc_t rs = row_rsrc((const T*)a.filt + ((size_t)p * a.nv + v) * a.n, a.n);
     const int off0 = valid ? ((int)of + jj) * ES : -4 * ES;
     int off1 = off0 + ES;
     asm volatile("" : "+v"(off1));   // two separately range-checked loads, never one wider load
@@ -418,8 +418,8 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd_ring(LearnedArgs a) {
     const bool stager = x < width + 4;
     const bool valid = jj >= 0 && jj < width;
     T* ws = (T*)a.ws;
-    const size_t yrow = (size_t)a.squares[q].y_off_row * a.n + (size_t)v * width;   // + m n W + j
-    const size_t yplane = (size_t)a.n * width;
+    const size_t yrow = (size_t)a.squares[q].y_off_row * a.nv + (size_t)v * width;   // + m n W + j
+    const size_t yplane = (size_t)a.nv * width;
     const int j = threadIdx.x;                                           // output column
     const int d = a.d;
     int pn = (a.p - (4 * d) % a.p) % a.p;      // p(0) = -4 d mod P
@@ -540,7 +540,7 @@ __global__ __launch_bounds__(kThreads) void k_learned_bwd(LearnedArgs a) {
     for (unsigned task = blockIdx.x; task < ntot; task += gridDim.x) {
         const int x8 = (int)(task % kXcds), i8 = (int)(task / kXcds);
         const int q = i8 % a.nsq, v = (i8 / a.nsq) * kXcds + x8;
-        if (v >= a.n) continue;                            // uniform over the workgroup
+        if (v >= a.nv) continue;                           // uniform over the workgroup
         const int2 gd = a.grid[q];
         const int u0 = gd.x, width = gd.y;
         const int ntile = (width + 15) >> 4;
@@ -556,8 +556,8 @@ __global__ __launch_bounds__(kThreads) void k_learned_bwd(LearnedArgs a) {
         const int jj = col - 2;
         const bool stager = col < width + 4;
         const bool valid = jj >= 0 && jj < width;
-        const size_t yrow = (size_t)a.squares[q].y_off_row * a.n + (size_t)v * width;
-        const size_t yplane = (size_t)a.n * width;
+        const size_t yrow = (size_t)a.squares[q].y_off_row * a.nv + (size_t)v * width;
+        const size_t yplane = (size_t)a.nv * width;
         CentreWalk cw(a.p, a.pd);
         __syncthreads();
         int offr[9];
@@ -633,28 +633,50 @@ __global__ __launch_bounds__(kThreads) void k_learned_bwd(LearnedArgs a) {
             __syncthreads();
         }
     }
-    // flush the wave's partials: dW1^T[tap = 4 g + i + 16 mt][ch = lr],
-    // dW2^T[b = 4 g + i][ch = lr] per angle, db1 of channel lr, db2
+    // the wave's partials: dW1^T[tap = 4 g + i + 16 mt][ch = lr],
+    // dW2^T[b = 4 g + i][ch = lr] per angle, db1 of channel lr, db2 -- each
+    // parameter held by exactly one lane of the wave.  They are summed over
+    // the four waves in a fixed order and written as the workgroup's partial
+    // gradient; k_grad_sum adds the workgroups' partials in a fixed order, so
+    // the gradient does not depend on scheduling.
+    __syncthreads();                                       // the last task's reads of sm are done
+    float* red = reinterpret_cast<float*>(&sm);            // [4][kLearnedParams]
+    static_assert(sizeof(BwdSmem) >= 4 * kLearnedParams * sizeof(float), "wave partials fit");
+    float* mine = red + wave * kLearnedParams;
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int tap = 16 * mt + 4 * lg + i;
-            if (tap < 25) atomicAdd(&a.grad[kOffW1 + lr * 25 + tap], gw1[mt][i]);
+            if (tap < 25) mine[kOffW1 + lr * 25 + tap] = gw1[mt][i];
         }
 #pragma unroll
     for (int a2 = 0; a2 < 5; ++a2)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int b = 4 * lg + i;
-            if (b < 5) atomicAdd(&a.grad[kOffW2 + lr * 25 + a2 * 5 + b], gw2[a2][i]);
+            if (b < 5) mine[kOffW2 + lr * 25 + a2 * 5 + b] = gw2[a2][i];
         }
     gb1 += __shfl_xor(gb1, 16, 64);
     gb1 += __shfl_xor(gb1, 32, 64);
-    if (lg == 0) atomicAdd(&a.grad[kOffB1 + lr], gb1);
+    if (lg == 0) mine[kOffB1 + lr] = gb1;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) gb2 += __shfl_xor(gb2, off, 64);
-    if (lane == 0) atomicAdd(&a.grad[kOffB2], gb2);
+    if (lane == 0) mine[kOffB2] = gb2;
+    __syncthreads();
+    for (int e = threadIdx.x; e < kLearnedParams; e += kThreads)
+        a.partials[(size_t)blockIdx.x * kLearnedParams + e] =
+            ((red[e] + red[kLearnedParams + e]) + red[2 * kLearnedParams + e]) + red[3 * kLearnedParams + e];
+}
+
+// grad[e] = sum over the backward pass's workgroups of their partials, in
+// workgroup order.
+__global__ __launch_bounds__(256) void k_grad_sum(const float* partials, int nblocks, float* grad) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kLearnedParams) return;
+    float acc = 0.0f;
+    for (int b = 0; b < nblocks; ++b) acc += partials[(size_t)b * kLearnedParams + e];
+    grad[e] = acc;
 }
 
 // Transpose of the backprojection of decimated data (training): for every
@@ -691,7 +713,7 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(AdjArgs a) {
     const float dx = (float)min(i, ix1) - a.cu - sq.xc, dy = (float)min(j, iy1) - a.cu - sq.yc;
     const float bx[2] = {(float)tl.x0 - a.cu - sq.xc, (float)ix1 - a.cu - sq.xc};
     const float by[2] = {(float)tl.y0 - a.cu - sq.yc, (float)iy1 - a.cu - sq.yc};
-    const float z0 = (float)l0 - a.cz, z1 = (float)l1 - a.cz;
+    const float z0 = (float)(a.zbase + l0) - a.cz, z1 = (float)(a.zbase + l1) - a.cz;
     // the block's residuals (slices l0 .. l0 + 31; zero outside the square or volume)
 #pragma unroll 8
     for (int k = 0; k < kAdjZR; ++k) {
@@ -714,7 +736,7 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(AdjArgs a) {
             vlo = fminf(vlo, fminf(z0 * iuc, z1 * iuc) + a.cv);
         }
         const int c0 = (int)floorf(tlo) - 1, r0 = (int)floorf(vlo) - 1;
-        const size_t plane = (size_t)sq.y_off_row * a.n + (size_t)m * a.n * width;
+        const size_t plane = (size_t)sq.y_off_row * a.nv + (size_t)m * a.nv * width;
         for (int e = threadIdx.x; e < kAdjTH * kAdjTW; e += 256) acc[e] = 0.0f;
         __syncthreads();
         if (own) {
@@ -730,13 +752,13 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(AdjArgs a) {
             // 1 - fu, fu) into the tile, or into dY when outside it; rows
             // outside the detector are dropped
             auto flush_row = [&](int row, float val) {
-                if (val == 0.0f || (unsigned)row >= (unsigned)a.n) return;
+                if (val == 0.0f || (unsigned)(row - a.v0) >= (unsigned)a.nv) return;
                 const int rl = row - r0;
                 if (cin && rl >= 0 && rl < kAdjTH) {
                     atomicAdd(&acc[rl * kAdjTW + cl], val * (1.0f - fu));
                     atomicAdd(&acc[rl * kAdjTW + cl + 1], val * fu);
                 } else {
-                    float* p = a.dws + plane + (size_t)row * width + iu;
+                    float* p = a.dws + plane + (size_t)(row - a.v0) * width + iu;
                     atomicAdd(p, val * (1.0f - fu));
                     atomicAdd(p + 1, val * fu);
                 }
@@ -756,7 +778,7 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(AdjArgs a) {
                 }
                 const float rv = rs[sl][threadIdx.x];
                 if (rv == 0.0f) continue;
-                const float vv = fmaf((float)(l0 + sl) - a.cz, invu, a.cv);
+                const float vv = fmaf((float)(a.zbase + l0 + sl) - a.cz, invu, a.cv);
                 const float vf = floorf(vv), fv = vv - vf;
                 const int iv = (int)vf;
                 if (iv != rc) {
@@ -778,32 +800,32 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(AdjArgs a) {
             flush_row(rc + 1, s1);
         }
         __syncthreads();
-        // non-zero entries lie at rows in [0, N) and columns in [0, W): only
-        // such samples were added
+        // non-zero entries lie at rows in [v0, v0 + nv) and columns in
+        // [0, W): only such samples were added
         for (int e = threadIdx.x; e < kAdjTH * kAdjTW; e += 256) {
             const float val = acc[e];
             if (val != 0.0f)
-                atomicAdd(&a.dws[plane + (size_t)(r0 + e / kAdjTW) * width + (c0 + e % kAdjTW)], val);
+                atomicAdd(&a.dws[plane + (size_t)(r0 - a.v0 + e / kAdjTW) * width + (c0 + e % kAdjTW)], val);
         }
         __syncthreads();
     }
 }
 
 __global__ __launch_bounds__(256) void k_residual(const float* f, const float* ref, float* r, double* loss,
-                                                   int64_t count) {
+                                                   int64_t count, float weight) {
     __shared__ double part[4];
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x) {
         const float dlt = f[i] - ref[i];
-        r[i] = 2.0f * dlt;
+        r[i] = (2.0f * weight) * dlt;
         acc += (double)dlt * (double)dlt;
     }
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(loss, part[0] + part[1] + part[2] + part[3]);
+    if (threadIdx.x == 0) atomicAdd(loss, (double)weight * (part[0] + part[1] + part[2] + part[3]));
 }
 
 __global__ void k_fill(float* p, int64_t count, float v) {
@@ -864,10 +886,10 @@ hipError_t launch_learned_fwd(const LearnedArgs& a, int max_width, int dfac, int
 // Workgroups of the backward pass: a grid stride over the tasks, a multiple of
 // the XCD count (so a workgroup's tasks stay on its XCD's rows), about four
 // per compute unit.
-constexpr unsigned kBwdGrid = 1024;
+constexpr unsigned kBwdGrid = kLearnedBwdGrid;
 
 hipError_t launch_learned_bwd(const LearnedArgs& a, int store, hipStream_t st) {
-    hipLaunchKernelGGL(k_fill, dim3(4), dim3(256), 0, st, a.grad, (int64_t)kLearnedParams, 0.0f);
+    if (!a.partials) return hipErrorInvalidValue;
     const unsigned ntot = fwd_grid(a);
     const dim3 grid(ntot < kBwdGrid ? ntot : kBwdGrid);
     switch (store) {
@@ -875,6 +897,8 @@ hipError_t launch_learned_bwd(const LearnedArgs& a, int store, hipStream_t st) {
         case 1: hipLaunchKernelGGL(k_learned_bwd<1>, grid, dim3(kThreads), 0, st, a); break;
         default: hipLaunchKernelGGL(k_learned_bwd<2>, grid, dim3(kThreads), 0, st, a); break;
     }
+    hipLaunchKernelGGL(k_grad_sum, dim3((kLearnedParams + 255) / 256), dim3(256), 0, st, a.partials,
+                       (int)grid.x, a.grad);
     return hipGetLastError();
 }
 
@@ -886,10 +910,10 @@ hipError_t launch_bp_adjoint(const AdjArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_residual(const float* f, const float* ref, float* r, double* loss, int64_t count,
+hipError_t launch_residual(const float* f, const float* ref, float* r, double* loss, int64_t count, float weight,
                            hipStream_t st) {
     hipLaunchKernelGGL(k_fill_d, dim3(1), dim3(64), 0, st, loss, (int64_t)1);
-    hipLaunchKernelGGL(k_residual, dim3(1024), dim3(256), 0, st, f, ref, r, loss, count);
+    hipLaunchKernelGGL(k_residual, dim3(1024), dim3(256), 0, st, f, ref, r, loss, count, weight);
     return hipGetLastError();
 }
 

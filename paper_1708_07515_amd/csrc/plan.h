@@ -20,8 +20,11 @@ struct fdkod_plan_s {
     std::vector<fdkod::SquareDesc> sq;
     std::vector<int2> grid;
     int wmax = 0;
-    // decomposition kernel shape
+    // decomposition kernel shape: 64-column chunks per wavefront of k_decimate,
+    // or 0 for the row-staged kernel (whose shape is staged_cpt, staged_segc;
+    // staged_cpt = 0 when it does not apply to the plan)
     int dec_chunks = 1;
+    int staged_cpt = 0, staged_segc = 0;
     // backprojection kernel shape
     fdkod::BpVariant bpv{32, 32, 48, 1};
     bool bp_ok = false;     // some variant's LDS footprint holds a block's footprint
@@ -35,6 +38,9 @@ struct fdkod_plan_s {
     float2* d_trig_m = nullptr;
     float* d_ac_p = nullptr;
     int2* d_crop = nullptr;
+    int* d_blo = nullptr;       // row-staged decimation: [blocks][nsched] least crop offset of a 2 x 2 block
+    int2* d_sqoff = nullptr;    // row-staged decimation: [nsq][nsched] offset from it, fraction bits
+    float* d_lpartials = nullptr;  // learned backward: per-workgroup partial gradients (learned plans only)
     float* d_rscale = nullptr;  // [nsq][nsched] R / D_c (cone-corrected rows only)
     float* d_wext = nullptr;    // [nsched][nw - 2] weights of windows 2.. (nw > 2 only)
     float4* d_geo_m = nullptr;
@@ -80,6 +86,16 @@ BpVol bp_vol(const fdkod_plan_s* pl, const void* filt, const void* ws, float* vo
 BpVol bp_vol_band(const fdkod_plan_s* pl, const void* filt, const void* ws, float* vol, int v0, int nv,
                   int zbase, int nzs);
 FilterArgs filter_args(const fdkod_plan_s* pl, const float* proj, void* filt, int v0, int nv);
+// bands of detector rows and slabs of slices (eq. (9)): the rows a slab
+// samples, and argument checks of the band calls
+void band_for(const fdkod_plan_s* pl, int z0, int nzs, int* v0, int* nv);
+fdkod_status check_rows_are_detector_rows(const fdkod_plan_s* pl);
+fdkod_status check_band(const fdkod_plan_s* pl, int v0, int nv);
+fdkod_status check_slab(const fdkod_plan_s* pl, int v0, int nv, int z0, int nzs);
+// the plan's decimation kernel on detector rows [v0, v0 + nv) (filt and ws
+// hold those rows)
+fdkod_status enqueue_decimate(const fdkod_plan_s* pl, const void* filt, void* ws, int v0, int nv,
+                              hipStream_t st);
 
 }  // namespace fdkod
 

@@ -347,16 +347,171 @@ def knobs_vs_learned(torch, pkg, steps=600, cost_reps=5):
             "decompose_ms_512_p360_s3": cost}
 
 
+LEARNED_C5_WEIGHTS = os.path.join(ROOT, "paper_1708_07515_amd", "learned_c5_weights.txt")
+
+
+class SlabScans:
+    """Slabs of seeded phantoms at the N = 2000, P = 720 geometry: only the
+    detector rows a slab samples (eq. (9), the slab mode's band) are
+    projected and filtered; the target is the direct FDK reconstruction of
+    the slab from the same band."""
+
+    def __init__(self, torch, pkg, wl, s, nzs, ellipsoids):
+        self.torch, self.pkg, self.wl, self.nzs, self.ellipsoids = torch, pkg, wl, nzs, ellipsoids
+        n, p, r = wl.n, wl.p, wl.r
+        self.plan = pkg.Plan(n, p, r, s=s, store="f32")
+        self.direct = pkg.Plan(n, p, r, s=0, store="f32")
+        self.vol = torch.empty((nzs, n, n), device="cuda:0")
+        self.tgt = torch.empty_like(self.vol)
+        self.resid = torch.empty_like(self.vol)
+        self.zs = list(range(0, (wl.nz or wl.n) - nzs + 1, 32))
+        maxrows = max(self.plan.band_rows(z0, nzs)[1] for z0 in self.zs)
+        self.ws_all = self.plan.empty_band(maxrows)[2]
+        self.dws_all = torch.empty(self.plan.band_workspace_elems(maxrows), dtype=torch.float32, device="cuda:0")
+
+    def slab(self, seed, z0):
+        """(v0, rows, filtered band) of phantom ``seed`` for slices
+        [z0, z0 + nzs); self.tgt receives its direct FDK slab."""
+        from synth import phantom
+        n, p, r = self.wl.n, self.wl.p, self.wl.r
+        v0, nr = self.plan.band_rows(z0, self.nzs)
+        ell = phantom.random_ellipsoids(self.ellipsoids, seed)
+        pb = phantom.project(ell, n, p, r, device="cuda:0", rows=np.arange(v0, v0 + nr)).contiguous()
+        fb = self.torch.empty((p, nr, n), dtype=self.torch.float32, device="cuda:0")
+        self.plan.filter_band(pb, v0, fb)
+        self.direct.reconstruct_slab(fb, None, v0, nr, z0, self.tgt)
+        return v0, nr, fb
+
+    def ws(self, nr):
+        return self.ws_all[:self.plan.band_workspace_elems(nr)]
+
+    def dws(self, nr):
+        return self.dws_all[:self.plan.band_workspace_elems(nr)]
+
+    def energy(self, t):
+        """sum t^2 on the device (the library's squared residual against zero)."""
+        loss = self.torch.zeros(1, dtype=self.torch.float64, device="cuda:0")
+        self.pkg.sq_residual(t, self.torch.zeros_like(t), self.resid, loss)
+        return float(loss)
+
+    def close(self):
+        self.plan.close()
+        self.direct.close()
+
+
+def train_learned_slabs(torch, pkg, scans, steps, lr, seed0, rng_seed=7, log_every=64):
+    """AdamW on one slab per step (phantom seed0 + step, slab position drawn
+    with rng_seed), each slab's squared error weighted by the inverse of its
+    target's energy; returns the trained LearnedDecimation and the training
+    time split (ms of library kernels per step, seconds of data generation)."""
+    net = pkg.LearnedDecimation("cuda:0", seed=0, lr=lr)
+    rng = np.random.default_rng(rng_seed)
+    t_gen = t_train = 0.0
+    skipped = 0
+    for it in range(steps):
+        z0 = int(rng.choice(scans.zs))
+        t0 = time.time()
+        v0, nr, fb = scans.slab(seed0 + it, z0)
+        e = scans.energy(scans.tgt)
+        if e <= 0.0:                 # the slab misses the phantom
+            skipped += 1
+            continue
+        w = 1.0 / e
+        torch.cuda.synchronize()
+        t1 = time.time()
+        net.train_step_slab(scans.plan, fb, v0, scans.ws(nr), z0, scans.vol, scans.tgt, scans.resid,
+                            scans.dws(nr), weight=w)
+        torch.cuda.synchronize()
+        t2 = time.time()
+        t_gen += t1 - t0
+        t_train += t2 - t1
+        if it % log_every == 0 or it == steps - 1:
+            log(f"[study] learned c5 step {it}: slab z0={z0} ({nr} rows), weighted loss {float(net.loss):.4e}")
+    return net, {"train_ms_per_step": 1e3 * t_train / max(steps - skipped, 1), "data_seconds": t_gen,
+                 "empty_slabs_skipped": skipped}
+
+
+def held_out_slabs(torch, pkg, scans, net, seeds, positions):
+    """Relative error against direct FDK, per held-out slab, of the triangle,
+    the trained learned filter and the windowed sinc (6 taps) with the cubic
+    shift, all FDK-OD at the scans' s."""
+    wl = scans.wl
+    knob = pkg.Plan(wl.n, wl.p, wl.r, s=scans.plan.s, store="f32", decim="sinc", taps=6, interp="cubic")
+
+    def rel(a, b):
+        return float(torch.linalg.norm((a - b).double()) / torch.linalg.norm(b.double()))
+
+    out = {"triangle": [], "learned": [], "sinc6_cubic": [], "slabs": []}
+    for sd, z0 in zip(seeds, positions):
+        v0, nr, fb = scans.slab(sd, z0)
+        if scans.energy(scans.tgt) <= 0.0:
+            continue
+        ws = scans.ws(nr)
+        scans.plan.decompose_band(fb, v0, ws)
+        scans.plan.reconstruct_slab(fb, ws, v0, nr, z0, scans.vol)
+        out["triangle"].append(rel(scans.vol, scans.tgt))
+        if net is not None:
+            net.forward_slab(scans.plan, fb, v0, ws, z0, scans.vol)
+            out["learned"].append(rel(scans.vol, scans.tgt))
+        knob.decompose_band(fb, v0, ws)
+        knob.reconstruct_slab(fb, ws, v0, nr, z0, scans.vol)
+        out["sinc6_cubic"].append(rel(scans.vol, scans.tgt))
+        out["slabs"].append([int(sd), int(z0)])
+    knob.close()
+    out["mean"] = {k: float(np.mean(v)) for k, v in out.items() if k != "slabs" and v}
+    return out
+
+
+def learned_c5(torch, pkg, steps=512, lr=5e-4, nzs=32, held=16):
+    """The learned decimation at the N = 2000, P = 720, s = 4 workload (D = 16,
+    dilation 4): trained on ``steps`` seeded 30-ellipsoid phantoms (seeds
+    5000 + i), one slab of nzs slices each, and compared on ``held`` other
+    phantoms (seeds 9000 + i, slabs spread over the volume) with the
+    triangle, the windowed sinc + cubic shift and direct FDK.  Writes the
+    trained weights to paper_1708_07515_amd/learned_c5_weights.txt."""
+    from synth import configs
+    wl = configs.C5
+    scans = SlabScans(torch, pkg, wl, 4, nzs, wl.ellipsoids)
+    net, timing = train_learned_slabs(torch, pkg, scans, steps, lr, 5000)
+    # held-out slabs spread over the central three quarters of the volume
+    lo, hi = (wl.nz or wl.n) // 8, (wl.nz or wl.n) - (wl.nz or wl.n) // 8 - nzs
+    positions = [z for z in (int(x) // 32 * 32 for x in np.linspace(lo, hi, held))]
+    res = held_out_slabs(torch, pkg, scans, net, [9000 + i for i in range(held)], positions)
+    log("[study] learned c5 held-out mean rel-RMSE vs direct FDK: "
+        + ", ".join(f"{a} {b:.4f}" for a, b in res["mean"].items()))
+    w = net.master.detach().cpu().double().numpy()
+    with open(LEARNED_C5_WEIGHTS, "w") as f:
+        f.write("# learned decimation filter for N = 2000, P = 720, R = 8000, s = 4 (D = 16): 817 FP32 master\n"
+                f"# weights (W1 [16][5][5], b1 [16], W2 [16][5][5], b2), AdamW lr {lr}, {steps} slabs of "
+                f"{nzs} slices; written by study.py --learned-c5\n")
+        for x in w:
+            f.write(f"{x:.9e}\n")
+    scans.close()
+    return {"n": wl.n, "p": wl.p, "r": wl.r, "s": 4, "d": 16, "slab_slices": nzs, "train_phantoms": steps,
+            "held_out_phantoms": held, "lr": lr, "timing": timing, "held_out": res,
+            "weights_file": os.path.relpath(LEARNED_C5_WEIGHTS, ROOT)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true", help="smaller sizes (a few seconds)")
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--learned-c5", action="store_true",
+                    help="only train and evaluate the learned filter at N = 2000, P = 720, s = 4")
+    ap.add_argument("--c5-steps", type=int, default=512)
+    ap.add_argument("--c5-lr", type=float, default=5e-4)
     args = ap.parse_args()
     import torch
 
     import paper_1708_07515_amd as pkg
 
     t0 = time.time()
+    if args.learned_c5:
+        res = learned_c5(torch, pkg, steps=args.c5_steps, lr=args.c5_lr)
+        print(json.dumps({"study": "learned decimation at N = 2000, P = 720, s = 4 on one MI355X",
+                          "data": "synthetic", "learned_c5": res, "seconds": round(time.time() - t0, 1)}),
+              flush=True)
+        return
     if args.quick:
         sweep = quality_sweep(torch, pkg, 96, 120, 384.0, 3)
         split = time_split(torch, pkg, [(128, 180)], 3, 2)

@@ -8,7 +8,7 @@ the skipped decimation stages.  Where a workload description leaves R or the
 ellipsoid count open, the value chosen here keeps R / N = 4.
 """
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 
 @dataclass(frozen=True)
@@ -62,7 +62,7 @@ class BatchWorkload:
     r_per_n: float = 4.0
     ellipsoids: int = 10
     seed: int = 4
-    levels: dict = field(default_factory=lambda: {128: 2, 192: 2, 256: 3, 384: 3, 512: 3})
+    s_max: int = 5              # s per volume: the cost model's choice up to s_max
 
 
 C4 = BatchWorkload()

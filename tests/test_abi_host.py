@@ -112,3 +112,48 @@ def test_batch_validation_before_device():
     assert lib.fdkod_batch_destroy(None) == 0
     assert lib.fdkod_get_tuning(None, None) == 1
     assert lib.fdkod_tune(None, None, None, None, None, None) == 1
+
+
+def test_check_counts_on_unchecked_build():
+    # the ordinary library is not a checked build: the counters are refused
+    # (before any device call), and bad arguments are reported first
+    if os.environ.get("FDKOD_LIB"):
+        pytest.skip("another library is loaded")
+    lib = pkg.load_library()
+    arr = (ctypes.c_int64 * 4)()
+    assert lib.fdkod_check_counts(arr, 4, 1) == 3
+    assert lib.fdkod_check_counts(None, 4, 1) == 1
+    assert lib.fdkod_check_counts(arr, 5, 1) == 1
+
+
+@pytest.mark.parametrize("args", [dict(n=64, p=90, r=512.0, s=2), dict(n=37, p=50, r=150.0, s=3, skip=1),
+                                  dict(n=512, p=360, r=2048.0, s=3), dict(n=300, p=96, r=1200.0, s=2, skip=1),
+                                  dict(n=48, p=60, r=192.0, s=0, nz=20)])
+def test_cost_counts_match_the_oracle(args):
+    """The library's host count of the two cost terms of Sec. 2.2 (eq. (6),
+    eq. (7)) equals the oracle's, which counts them from its own plan."""
+    from oracle import fdkod as ofdkod
+    cropped, updates = pkg.cost_counts(**args)
+    n, p, r = args["n"], args["p"], args["r"]
+    want_c, want_u = ofdkod.cost_counts(n, args.get("nz") or n, p, r, args.get("s", 0), args.get("skip", 0))
+    if args.get("s", 0) == 0:
+        want_c, want_u = 0, n * n * (args.get("nz") or n) * p
+    assert (cropped, updates) == (want_c, want_u)
+
+
+def test_choose_s_minimises_the_predicted_time():
+    c1, c2 = 3.7e-10, 6e-10
+    for n, p in [(256, 360), (512, 360), (1024, 720), (2000, 720)]:
+        s, ms = pkg.choose_s(n, p, 4.0 * n, s_max=6, costs=(c1, c2))
+        times = {}
+        for cand in range(0, 7):
+            if (1 << cand) > n:
+                continue
+            c, u = pkg.cost_counts(n, p, 4.0 * n, s=cand)
+            times[cand] = c1 * u + c2 * c
+        assert s == min(times, key=times.get) and ms == pytest.approx(times[s])
+        # eq. (8): the optimum grows with N (2^s = sqrt(C1 N / C2) up to the
+        # squares' margins)
+    s_small, _ = pkg.choose_s(256, 360, 1024.0, costs=(c1, c2))
+    s_large, _ = pkg.choose_s(2000, 720, 8000.0, costs=(c1, c2))
+    assert s_large > s_small

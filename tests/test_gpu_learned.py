@@ -465,6 +465,33 @@ def test_residual_and_adamw_match_torch():
     assert torch.equal(w_bf16.cpu(), master.cpu().to(torch.bfloat16))
 
 
+def test_checkpoint_resume_takes_the_same_steps(tmp_path):
+    """Four AdamW steps in one run equal two steps, a checkpoint, a fresh
+    instance restored from it and two more steps, bit for bit (the same
+    gradients are fed to both)."""
+    gen = torch.Generator().manual_seed(11)
+    grads = [torch.randn(pkg.LEARNED_PARAMS, generator=gen).to(DEV) for _ in range(4)]
+    run = pkg.LearnedDecimation(DEV, seed=2, lr=1e-2, weight_decay=0.01)
+    part = pkg.LearnedDecimation(DEV, seed=2, lr=1e-2, weight_decay=0.01)
+    for g in grads:
+        run.grad.copy_(g)
+        run.apply()
+    for g in grads[:2]:
+        part.grad.copy_(g)
+        part.apply()
+    part.save_checkpoint(tmp_path / "ck.npz")
+    resumed = pkg.LearnedDecimation(DEV, seed=5)
+    resumed.load_checkpoint(tmp_path / "ck.npz")
+    for g in grads[2:]:
+        resumed.grad.copy_(g)
+        resumed.apply()
+    torch.cuda.synchronize()
+    assert resumed.step_count == run.step_count == 4
+    for a, b in ((run.master, resumed.master), (run.m1, resumed.m1), (run.m2, resumed.m2),
+                 (run.weights, resumed.weights)):
+        assert torch.equal(a.cpu(), b.cpu())
+
+
 def test_learned_rejects_unsupported_plans():
     with pkg.Plan(32, 48, 128.0, s=0) as plan:
         filt = plan.empty_filtered()
@@ -537,3 +564,76 @@ def test_training_beats_plain_decimation_on_held_out_phantoms():
     assert np.isfinite(trained) and trained <= 0.98 * plain
     for pl in (plan, direct):
         pl.close()
+
+
+def test_learned_band_calls_match_whole_volume_rows():
+    """The band forms (training on slabs): the forward on a band equals the
+    whole-volume forward on those rows bit for bit; the gradient of a band
+    and the slab adjoint equal the whole-volume calls on the same data (dY
+    and the residual zero outside the band and slab) to FP32 summation order."""
+    n, p, r, s, k = 64, 64, 256.0, 3, 0
+    net = random_net(21)
+    proj = scan(n, p, r, 6, 91)
+    w = device_weights(net)
+    with pkg.Plan(n, p, r, s=s, skip=k) as plan:
+        z0, nzs = 32, 16
+        v0, nrows = plan.band_rows(z0, nzs)
+        assert 0 < nrows < n
+        filt = plan.empty_filtered()
+        plan.filter(proj.to(DEV), filt)
+        ws = plan.empty_workspace()
+        plan.learned_decompose(filt, ws, w)
+        pb = proj[:, v0:v0 + nrows, :].contiguous().to(DEV)
+        _, fb, wb = plan.empty_band(nrows)
+        plan.filter_band(pb, v0, fb)
+        plan.learned_decompose_band(fb, v0, wb, w)
+        torch.cuda.synchronize()
+        rows = np.arange(v0, v0 + nrows)
+        whole = [x.numpy() for x in square_views(plan, _as(plan, ws))]
+        band_views = []
+        off = 0
+        for q, wq in enumerate(plan.get_bounds()["width"]):
+            size = plan.p_dec * nrows * int(wq)
+            band_views.append(wb[:plan.band_workspace_elems(nrows)][off:off + size]
+                              .reshape(plan.p_dec, nrows, int(wq)).double().cpu().numpy())
+            off += size
+        for q in range(len(whole)):
+            assert np.array_equal(whole[q][:, rows, :], band_views[q]), q
+        # gradient: dY random on the band's rows only
+        gen = torch.Generator().manual_seed(22)
+        dws_band = torch.randn(plan.band_workspace_elems(nrows), generator=gen)
+        dws = torch.zeros(plan.workspace_elems, dtype=torch.float32)
+        off_b = 0
+        for q, v in enumerate(square_views(plan, dws)):
+            wq = v.shape[2]
+            size = plan.p_dec * nrows * wq
+            v[:, v0:v0 + nrows, :] = dws_band[off_b:off_b + size].reshape(plan.p_dec, nrows, wq)
+            off_b += size
+        g_whole = torch.zeros(pkg.LEARNED_PARAMS, dtype=torch.float32, device=DEV)
+        g_band = torch.zeros_like(g_whole)
+        plan.learned_backward(filt, dws.to(DEV), w, g_whole)
+        plan.learned_backward_band(fb, v0, dws_band.to(DEV), w, g_band)
+        # adjoint of a residual on the slab's slices only
+        res = torch.zeros((plan.nz, n, n))
+        res[z0:z0 + nzs] = torch.randn((nzs, n, n), generator=gen)
+        d_whole = torch.empty(plan.workspace_elems, dtype=torch.float32, device=DEV)
+        d_band = torch.empty(plan.band_workspace_elems(nrows), dtype=torch.float32, device=DEV)
+        plan.reconstruct_adjoint(res.to(DEV), d_whole)
+        plan.reconstruct_adjoint_slab(res[z0:z0 + nzs].contiguous().to(DEV), v0, nrows, z0, d_band)
+        torch.cuda.synchronize()
+        eg = metrics.rel_rmse(g_band.double().cpu().numpy(), g_whole.double().cpu().numpy())
+        dw = square_views(plan, d_whole.cpu().double())
+        num = den = 0.0
+        off_b = 0
+        for q, v in enumerate(dw):
+            wq = v.shape[2]
+            size = plan.p_dec * nrows * wq
+            b = d_band.cpu().double()[off_b:off_b + size].reshape(plan.p_dec, nrows, wq)
+            num += float(((v[:, v0:v0 + nrows, :] - b) ** 2).sum())
+            den += float((v[:, v0:v0 + nrows, :] ** 2).sum())
+            # the slab's voxels touch no row outside the band
+            assert float(v[:, :v0, :].abs().max()) == 0.0 and float(v[:, v0 + nrows:, :].abs().max()) == 0.0
+            off_b += size
+        ea = (num / den) ** 0.5
+        log(f"band gradient rel-RMSE {eg:.2e}, slab adjoint rel-RMSE {ea:.2e}")
+        assert eg <= 1e-5 and ea <= 1e-6
