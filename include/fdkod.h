@@ -317,16 +317,26 @@ fdkod_status fdkod_learned_decompose(fdkod_plan_t plan, const void* filt, void* 
 /* Training: grad (float32 [FDKOD_LEARNED_PARAMS], overwritten) receives the
  * gradient of sum_{q,m,v,j} R[m][v][j] dws[m][v][j] with respect to the
  * parameters.  dws: float32, the workspace layout (workspace_bytes / element
- * size elements).  The BF16 roundings of the forward pass are held fixed. */
+ * size elements).  The BF16 roundings of the forward pass are held fixed.
+ * Workgroup partial sums are added in a fixed order: the same inputs give the
+ * same bits on every call.  Calls that overlap on one plan (two streams)
+ * race on the plan's partial-sum buffer. */
 fdkod_status fdkod_learned_backward(fdkod_plan_t plan, const void* filt, const float* dws,
                                     const uint16_t* weights, float* grad, fdkod_stream_t stream);
 
 /* Transpose of fdkod_reconstruct for s > 0: dws (float32, workspace layout,
  * overwritten) receives, for every voxel with value resid and every decimated
  * angle, resid * (pi / P') U^-2 spread over the four samples of its bilinear
- * interpolation.  resid: float32 [N_z][N][N].  Uses float atomics, so the
- * summation order (and the last bits) vary from run to run.  Plans with
- * cone-corrected rows (FDKOD_ROWS_CONE) return FDKOD_E_UNSUPPORTED. */
+ * interpolation.  resid: float32 [N_z][N][N].  Deterministic: each FP32
+ * contribution is rounded to a multiple of 2^-e and the multiples are summed
+ * exactly in int64 (e chosen per call from max |resid| so that no sum can
+ * overflow; the step 2^-e is below 2^-60 of the largest possible sum), then
+ * every entry is rounded once to FP32; a resid that holds a value that is
+ * not finite gives NaN.  The plan holds the int64 sums: the first call
+ * allocates them (8 bytes per workspace element), a later call that needs
+ * more grows them (hipFree waits for the device), and calls that overlap on
+ * one plan race on them.  Plans with cone-corrected rows (FDKOD_ROWS_CONE)
+ * return FDKOD_E_UNSUPPORTED. */
 fdkod_status fdkod_reconstruct_adjoint(fdkod_plan_t plan, const float* resid, float* dws,
                                        fdkod_stream_t stream);
 

@@ -144,6 +144,7 @@ void release(fdkod_plan_t pl) {
     if (hipGetDevice(&prev) == hipSuccess) {
         (void)hipSetDevice(pl->device);
         for (void* p : pl->allocs) (void)hipFree(p);
+        if (pl->d_adj) (void)hipFree(pl->d_adj);
         (void)hipSetDevice(prev);
     }
     delete pl;

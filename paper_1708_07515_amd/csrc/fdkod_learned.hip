@@ -65,7 +65,38 @@ AdjArgs adjoint_args(const fdkod_plan_s* pl, const float* resid, float* dws, int
     a.cz = (float)((pl->nz - 1) / 2.0);
     a.scale = (float)(M_PI / pl->pd);
     a.ws_elems = pl->ws_row_elems * nv;
+    a.nvox = (int64_t)nzs * pl->n * pl->n;
+    // a voxel's weight (pi / P') U^-2 is largest at the least source
+    // distance along the central ray, R - (N - 1) / sqrt(2); its four
+    // bilinear shares sum to it.  Twice the product bounds every partial sum
+    // of |contributions| per unit of max |resid|.
+    const double umax = pl->r / (pl->r - (pl->n - 1) / std::sqrt(2.0));
+    a.bound = 2.0 * (M_PI / pl->pd) * umax * umax * (double)a.nvox;
+    a.qs = (AdjScale*)pl->d_adj;
+    a.dq = (unsigned long long*)((char*)pl->d_adj + 256);
     return a;
+}
+
+// the adjoint's scale block and int64 sums for elems workspace elements
+fdkod_status adjoint_buffer(fdkod_plan_s* pl, int64_t elems) {
+    if (pl->d_adj && pl->adj_cap >= elems) return FDKOD_OK;
+    int prev = 0;
+    HIP_TRY(hipGetDevice(&prev), "hipGetDevice");
+    HIP_TRY(hipSetDevice(pl->device), "hipSetDevice");
+    if (pl->d_adj) {
+        (void)hipFree(pl->d_adj);          // waits for the work that used it
+        pl->d_adj = nullptr;
+        pl->adj_cap = 0;
+    }
+    std::vector<void*> tmp;
+    const fdkod_status st = dev_alloc(tmp, &pl->d_adj, 256 + sizeof(int64_t) * (size_t)elems);
+    (void)hipSetDevice(prev);
+    if (st != FDKOD_OK) {
+        pl->d_adj = nullptr;
+        return st;
+    }
+    pl->adj_cap = elems;
+    return FDKOD_OK;
 }
 
 fdkod_status adjoint_check(const fdkod_plan_s* pl) {
@@ -131,6 +162,7 @@ fdkod_status fdkod_reconstruct_adjoint(fdkod_plan_t pl, const float* resid, floa
     if (!pl || !resid || !dws) return fail(FDKOD_E_ARG, "NULL argument");
     fdkod_status st = adjoint_check(pl);
     if (st != FDKOD_OK) return st;
+    if ((st = adjoint_buffer(pl, pl->ws_row_elems * pl->n)) != FDKOD_OK) return st;
     const AdjArgs a = adjoint_args(pl, resid, dws, 0, pl->n, 0, pl->nz);
     HIP_TRY(launch_bp_adjoint(a, (hipStream_t)stream), "adjoint kernel launch");
     return FDKOD_OK;
@@ -143,6 +175,7 @@ fdkod_status fdkod_reconstruct_adjoint_slab(fdkod_plan_t pl, const float* resid_
     if (st != FDKOD_OK) return st;
     if ((st = check_band(pl, v0, nrows)) != FDKOD_OK) return st;
     if ((st = check_slab(pl, v0, nrows, z0, nzs)) != FDKOD_OK) return st;
+    if ((st = adjoint_buffer(pl, pl->ws_row_elems * nrows)) != FDKOD_OK) return st;
     const AdjArgs a = adjoint_args(pl, resid_slab, dws_band, v0, nrows, z0, nzs);
     HIP_TRY(launch_bp_adjoint(a, (hipStream_t)stream), "adjoint kernel launch");
     return FDKOD_OK;

@@ -190,6 +190,14 @@ struct LearnedArgs {
 };
 
 // Transpose of the per-square backprojection (training).
+// the adjoint's fixed-point scale: qscale = 2^e with bound * max |resid| *
+// qscale < 2^61 (qscale = 0 when resid holds a value that is not finite)
+struct AdjScale {
+    double qscale;
+    unsigned rmax;           // bits of max |resid| (non-negative floats order as integers)
+    unsigned pad;
+};
+
 struct AdjArgs {
     const float* resid;      // [nz][n][n]
     float* dws;              // FP32, workspace layout, overwritten
@@ -204,6 +212,13 @@ struct AdjArgs {
     float r, cu, cv, cz;
     float scale;             // pi / P'
     int64_t ws_elems;
+    // fixed-point accumulation: every contribution is rounded to an integer
+    // multiple of 1 / qscale and summed in int64 (exact, so the result does
+    // not depend on the order of the atomics)
+    unsigned long long* dq;  // [ws_elems] int64 sums, two's complement
+    AdjScale* qs;            // the call's scale (device)
+    double bound;            // an upper bound of sum |weight| over the voxels, per unit of max |resid|
+    int64_t nvox;            // voxels of resid
 };
 
 struct AdamArgs {

@@ -43,14 +43,18 @@ typedef float f2v __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) const char* lds_cptr;
 typedef __attribute__((address_space(3))) const f2v* lds_f2ptr;
 
-// LDS of one workgroup: G staged footprints and, in a ring of three angle
-// batches, their per-angle constants.
+// Per-angle footprints and constants are computed for kFpChunk angles at a
+// time (one lane per angle) and kept for two such chunks.
+constexpr int kFpChunk = 64;
+
+// LDS of one workgroup: G staged footprints and, for two chunks of angles,
+// the per-angle constants.
 template <int TW, int TH, int G>
 struct BpSmem {
     float2 tile[G][TH * (TW + 1)];
-    int4 meta[3][G];      // c0, r0 (first column / row of the footprint), rows, -
-    float4 mgeo[3][G];    // cos, sin, Dc, Lc
-    float2 mgeo2[3][G];   // R / Dc, c_u - u0 - c0
+    int4 meta[2][kFpChunk];      // c0, r0 (first column / row of the footprint), rows, -
+    float4 mgeo[2][kFpChunk];    // cos, sin, Dc, Lc
+    float2 mgeo2[2][kFpChunk];   // R / Dc, c_u - u0 - c0
 };
 
 // Lane l receives lane l + 1's value (a DPP wave shift; lane 63 receives 0).
@@ -109,12 +113,15 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
     const int scol = threadIdx.x % TW;
     const int srow = threadIdx.x / TW;
 
-    // footprint of the block at angles [m0, m0 + G) into ring slot `slot`:
-    // eq. (1) at the block's corners bounds the columns, eq. (9) at its corner
-    // depths and end slices the rows; one sample of margin on every side
-    // covers the rounding of the reciprocals
-    auto footprint = [&](int slot, int m0) {
-        if (threadIdx.x < G && m0 + (int)threadIdx.x < v.pd) {
+    // footprints of the block at the kFpChunk angles from m0 (a multiple of
+    // kFpChunk), one lane of the first wave per angle: eq. (1) at the block's
+    // corners bounds the columns, eq. (9) at its corner depths and end slices
+    // the rows; one sample of margin on every side covers the rounding of the
+    // reciprocals.  Angle m's constants sit at [(m / kFpChunk) % 2][m % kFpChunk].
+    static_assert(kFpChunk % G == 0, "a batch of angles lies within one chunk");
+    auto footprint = [&](int m0) {
+        const int slot = (m0 / kFpChunk) & 1;
+        if (threadIdx.x < kFpChunk && m0 + (int)threadIdx.x < v.pd) {
             const int m = m0 + threadIdx.x;
             const float2 t = v.trig[m];
             const float dc = v.r + sq.xc * t.x + sq.yc * t.y;
@@ -158,10 +165,10 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
     const uint32_t plane_bytes = (uint32_t)(plane * ES);
     const int rstep_bytes = RSTEP * row_stride * ES;
     uint32_t pre[G][NR];
-    auto fetch_one = [&](int slot, int m0, int g) {
+    auto fetch_one = [&](int m0, int g) {
         {
             const bool gok = m0 + g < v.pd;
-            const int4 mt = gok ? sm.meta[slot][g] : make_int4(0, 0, 0, 0);
+            const int4 mt = gok ? sm.meta[((m0 + g) / kFpChunk) & 1][(m0 + g) % kFpChunk] : make_int4(0, 0, 0, 0);
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                 uniform_ptr(data + (size_t)(gok ? m0 + g : 0) * plane), (short)0, (int)plane_bytes, 0x00020000);
             const int col = mt.x + scol;
@@ -172,8 +179,13 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
             // whole offset of every sample)
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
-                int off = off0 + r * rstep_bytes;
-                asm volatile("" : "+v"(off));
+                int off;
+                if (r == 0) {
+                    off = off0;
+                    asm volatile("" : "+v"(off));
+                } else {
+                    asm volatile("v_add_u32 %0, %1, %2" : "=v"(off) : "s"(r * rstep_bytes), "v"(off0));
+                }
                 pre[g][r] = S::raw_bits(rs, off);
             }
         }
@@ -183,9 +195,7 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
     // the next footprint row's first sample writes an unused pair.  Rows
     // below the footprint's last are written too: they lie inside the tile
     // and are never read.
-    auto stage_one = [&](int slot, int m0, int g) {
-        (void)slot;
-        (void)m0;
+    auto stage_one = [&](int g) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const int rr = srow + r * RSTEP;
@@ -199,36 +209,36 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
 #pragma unroll
     for (int k = 0; k < ZR; ++k) acc[k] = 0.0f;
 
-    auto fetch_stage = [&](int slot, int m0) {
+    auto fetch_stage = [&](int m0) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            fetch_one(slot, m0, g);
-            stage_one(slot, m0, g);
+            fetch_one(m0, g);
+            stage_one(g);
         }
     };
 
-    footprint(0, 0);
-    footprint(1, G);
+    // the first chunk's footprints; the next chunk's are computed while the
+    // first batch of a chunk is accumulated (two barriers before their first
+    // use, and after the last use of the chunk two before them)
+    if (threadIdx.x < 64) footprint(0);
     __syncthreads();
-    fetch_stage(0, 0);
+    fetch_stage(0);
     __syncthreads();
-    int cur = 0;
 #pragma unroll 1
     for (int m0 = 0; m0 < v.pd; m0 += G) {
-        const int nxt = cur == 2 ? 0 : cur + 1;
-        const int nn = nxt == 2 ? 0 : nxt + 1;
+        const int cs = (m0 / kFpChunk) & 1, ci0 = m0 % kFpChunk;
         const int gcount = min(G, v.pd - m0);
         const bool more = m0 + G < v.pd;
         if (kPrefetch && more) {             // in flight during the arithmetic below
 #pragma unroll
-            for (int g = 0; g < G; ++g) fetch_one(nxt, m0 + G, g);
+            for (int g = 0; g < G; ++g) fetch_one(m0 + G, g);
         }
-        footprint(nn, m0 + 2 * G);
+        if (ci0 == 0 && m0 + kFpChunk < v.pd && threadIdx.x < 64) footprint(m0 + kFpChunk);
 #pragma unroll 1
         for (int g = 0; g < gcount; ++g) {
-            const float4 mg = sm.mgeo[cur][g];
-            const float2 mg2 = sm.mgeo2[cur][g];
-            const int4 mt = sm.meta[cur][g];
+            const float4 mg = sm.mgeo[cs][ci0 + g];
+            const float2 mg2 = sm.mgeo2[cs][ci0 + g];
+            const int4 mt = sm.meta[cs][ci0 + g];
             const float dl = dy * mg.x - dx * mg.y;
             const float dd = dx * mg.x + dy * mg.y;
             const float d = mg.z + dd;
@@ -278,13 +288,12 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
         if (more) {
             if (kPrefetch) {
 #pragma unroll
-                for (int g = 0; g < G; ++g) stage_one(nxt, m0 + G, g);
+                for (int g = 0; g < G; ++g) stage_one(g);
             } else {
-                fetch_stage(nxt, m0 + G);
+                fetch_stage(m0 + G);
             }
         }
         __syncthreads();
-        cur = nxt;
     }
     if (own) {
         const size_t slice = (size_t)n * n;

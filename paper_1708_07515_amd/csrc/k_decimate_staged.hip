@@ -29,6 +29,7 @@
 namespace fdkod {
 
 typedef __attribute__((address_space(4))) const int* cword_ptr;
+typedef __attribute__((address_space(3))) const float* lds_fptr;
 
 constexpr int kStagedSteps = 8;                 // schedule steps per stage (two per wave)
 
@@ -95,13 +96,16 @@ __global__ __launch_bounds__(256) void k_decimate_staged(DecimVol a) {
     // constant offset, a lane whose first offset lies left of the row
     // (negative) would read zero for all its chunks.
     float reg[kDirect ? 1 : 2][kDirect ? 1 : SEGC];
-    auto load_stage = [&](int t0, int buf) {
+    // (the step tables are read through pointers to the stage's first step,
+    // so each word's address is a constant offset from one scalar base: the
+    // per-word 64-bit address arithmetic otherwise costs more scalar
+    // instructions than the stage has vector ones)
+    auto load_stage = [&](cword_ptr s_st, cword_ptr l_st, int buf) {
         int p[2], lo[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int e = t0 + 2 * wave + h;
-            p[h] = sched[4 * e];
-            lo[h] = blo[e];
+            p[h] = s_st[4 * (2 * wave + h)];
+            lo[h] = l_st[2 * wave + h];
         }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -134,35 +138,35 @@ __global__ __launch_bounds__(256) void k_decimate_staged(DecimVol a) {
         }
     };
 
-    T* ws = (T*)a.ws;
-    const int64_t yoff = a.squares[q].y_off_row * a.nv;
+    // the next output window's row: row v of decimated angle m of the square
     const size_t plane = (size_t)a.nv * width;
-    const size_t vrow = (size_t)yoff + (size_t)v * width;
+    T* outp = (T*)a.ws + (size_t)(a.squares[q].y_off_row * a.nv) + (size_t)v * width;
     float acc0[CPT], acc1[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) acc0[c] = acc1[c] = 0.0f;
-    int m = 0;
 
-    load_stage(0, 0);
+    cword_ptr s_st = sched, q_st = sqo, l_st = blo;      // the current stage's first step
+    load_stage(s_st, l_st, 0);
     store_stage(0);
     __syncthreads();
     const int nstage = a.nsched / kStagedSteps;
     for (int st = 0; st < nstage; ++st) {
-        const int t0 = st * kStagedSteps;
         const bool more = st + 1 < nstage;
-        if (more) load_stage(t0 + kStagedSteps, (st + 1) & 1);
+        if (more) load_stage(s_st + 4 * kStagedSteps, l_st + kStagedSteps, (st + 1) & 1);
         // the stage's step tables, requested together
         int emit[kStagedSteps], off[kStagedSteps];
         float w0[kStagedSteps], w1[kStagedSteps], ph[kStagedSteps];
 #pragma unroll
         for (int k = 0; k < kStagedSteps; ++k) {
-            const int e = t0 + k;
-            emit[k] = sched[4 * e + 1];
-            w0[k] = __int_as_float(sched[4 * e + 2]);
-            w1[k] = __int_as_float(sched[4 * e + 3]);
-            off[k] = sqo[2 * e];
-            ph[k] = __int_as_float(sqo[2 * e + 1]);
+            emit[k] = s_st[4 * k + 1];
+            w0[k] = __int_as_float(s_st[4 * k + 2]);
+            w1[k] = __int_as_float(s_st[4 * k + 3]);
+            off[k] = q_st[2 * k];
+            ph[k] = __int_as_float(q_st[2 * k + 1]);
         }
+        s_st += 4 * kStagedSteps;
+        q_st += 2 * kStagedSteps;
+        l_st += kStagedSteps;
         const float(*buf)[SEG] = stage[st & 1];
 #pragma unroll
         for (int k = 0; k < kStagedSteps; ++k) {
@@ -171,7 +175,11 @@ __global__ __launch_bounds__(256) void k_decimate_staged(DecimVol a) {
             // read from LDS (a closed window is written at once: holding it
             // to the next stage, or taking x[j + 1] from the next lane by a
             // DPP shift, measured slower)
-            const float* row = buf[k] + off[k] + lane;
+            // one address register per step; the chunks' constant offsets
+            // (at most 64 (CPT - 1) + 1 words) fold into the LDS reads
+            uint32_t ad = (uint32_t)(uintptr_t)(lds_fptr)(buf[k] + off[k]) + 4u * (uint32_t)lane;
+            asm volatile("" : "+v"(ad));
+            const lds_fptr row = (lds_fptr)(uintptr_t)ad;
 #pragma unroll
             for (int c = 0; c < CPT; ++c) {
                 const float xa = row[64 * c], xb = row[64 * c + 1];
@@ -180,15 +188,14 @@ __global__ __launch_bounds__(256) void k_decimate_staged(DecimVol a) {
                 acc1[c] = fmaf(w1[k], sv, acc1[c]);
             }
             if (emit[k]) {
-                const size_t base = vrow + (size_t)m * plane;
 #pragma unroll
                 for (int c = 0; c < CPT; ++c) {
                     const int j = lane + 64 * c;
-                    if (j < width) S::put(ws, base + j, acc0[c]);
+                    if (j < width) S::put(outp, j, acc0[c]);
                     acc0[c] = acc1[c];
                     acc1[c] = 0.0f;
                 }
-                ++m;
+                outp += plane;
             }
         }
         if (more) store_stage((st + 1) & 1);

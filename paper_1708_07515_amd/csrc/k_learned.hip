@@ -681,12 +681,16 @@ __global__ __launch_bounds__(256) void k_grad_sum(const float* partials, int nbl
 
 // Transpose of the backprojection of decimated data (training): for every
 // voxel and decimated angle, the residual is scattered with the bilinear
-// weights and (pi / P') U^-2 into dY (FP32, workspace layout).  One workgroup
+// weights and (pi / P') U^-2 into dY (workspace layout).  The sums are exact
+// integer sums of the FP32 contributions rounded to multiples of 2^-e
+// (fixed point in int64; e from a bound of the largest possible sum, so
+// that no partial sum overflows), converted to FP32 at the end: the result
+// does not depend on the order in which the atomics land.  One workgroup
 // per 16 x 16 (x, y) tile of a square and slab of 32 slices (the
 // backprojection's blocks).  Per angle, the block's contributions are summed
 // in an LDS tile over its detector footprint, whose origin the block's
 // corners bound (the column is linear-fractional in x and y, the row linear
-// in z), and the tile is then added to dY with one FP32 global atomic per
+// in z), and the tile is then added to dY with one int64 global atomic per
 // non-zero entry.  A sample outside the tile (not expected) goes to dY
 // directly, so the result does not depend on the bound.  The block's
 // residuals sit in LDS, and in step k lane l takes slice (k + l) mod 32, so
@@ -697,8 +701,50 @@ __global__ __launch_bounds__(256) void k_grad_sum(const float* partials, int nbl
 // slice instead of two.
 constexpr int kAdjZR = 32, kAdjTW = 40, kAdjTH = 48;
 
+// max |resid| over the voxels, as the bits of a non-negative float
+__global__ __launch_bounds__(256) void k_adj_absmax(const float* resid, int64_t count, AdjScale* qs) {
+    unsigned m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, __float_as_uint(resid[i]) & 0x7FFFFFFFu);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) m = max(m, (unsigned)__shfl_xor((int)m, off, 64));
+    if ((threadIdx.x & 63) == 0 && m) atomicMax(&qs->rmax, m);
+}
+
+// clears the maximum and the sums' buffer (a fill kernel, no memset node)
+__global__ void k_adj_clear(AdjScale* qs, unsigned long long* dq, int64_t count) {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i0 == 0) qs->rmax = 0u;
+    for (int64_t i = i0; i < count; i += (int64_t)gridDim.x * blockDim.x) dq[i] = 0ull;
+}
+
+// qscale = 2^e, the largest power of two with bound * max |resid| * qscale < 2^61
+__global__ void k_adj_scale(AdjScale* qs, double bound) {
+    const unsigned bits = qs->rmax;
+    double q;
+    if (bits >= 0x7F800000u) {
+        q = 0.0;                                  // not finite: the result is NaN
+    } else if (bits == 0u) {
+        q = 1.0;                                  // all zero
+    } else {
+        int x;
+        (void)frexp(bound * (double)__uint_as_float(bits), &x);   // the product < 2^x
+        q = ldexp(1.0, 61 - x);
+    }
+    qs->qscale = q;
+}
+
+// dY = the int64 sums / qscale, rounded once to FP32
+__global__ void k_adj_convert(const unsigned long long* dq, const AdjScale* qs, float* dws, int64_t count) {
+    const double q = qs->qscale;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dws[i] = q > 0.0 ? (float)((double)(long long)dq[i] / q) : __builtin_nanf("");
+}
+
 __global__ __launch_bounds__(256) void k_bp_adjoint(AdjArgs a) {
-    __shared__ float acc[kAdjTH * kAdjTW];
+    __shared__ unsigned long long acc[kAdjTH * kAdjTW];
     __shared__ float rs[kAdjZR][256];          // residual of slice l0 + k, voxel threadIdx.x
     const int tile = (int)(blockIdx.x % (unsigned)a.ntiles), zt = (int)(blockIdx.x / (unsigned)a.ntiles);
     const BpTile tl = a.tiles[tile];
@@ -721,6 +767,10 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(AdjArgs a) {
         rs[k][threadIdx.x] = own && l <= l1 ? a.resid[((size_t)l * a.n + j) * a.n + i] : 0.0f;
     }
     const int skew = threadIdx.x & 63;
+    const double qscale = a.qs->qscale;
+    // a contribution as an integer multiple of 1 / qscale (qscale is a power
+    // of two: the product is exact, the conversion rounds to nearest)
+    auto fixed = [&](float v) { return (unsigned long long)__double2ll_rn((double)v * qscale); };
     for (int m = 0; m < a.pd; ++m) {
         const float2 t = a.trig[m];
         const float dc = a.r + sq.xc * t.x + sq.yc * t.y;
@@ -737,7 +787,7 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(AdjArgs a) {
         }
         const int c0 = (int)floorf(tlo) - 1, r0 = (int)floorf(vlo) - 1;
         const size_t plane = (size_t)sq.y_off_row * a.nv + (size_t)m * a.nv * width;
-        for (int e = threadIdx.x; e < kAdjTH * kAdjTW; e += 256) acc[e] = 0.0f;
+        for (int e = threadIdx.x; e < kAdjTH * kAdjTW; e += 256) acc[e] = 0ull;
         __syncthreads();
         if (own) {
             const float tau = rel_column(dx, dy, t.x, t.y, a.r, dc, lc, rdc) + a.cu - (float)u0;
@@ -754,13 +804,14 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(AdjArgs a) {
             auto flush_row = [&](int row, float val) {
                 if (val == 0.0f || (unsigned)(row - a.v0) >= (unsigned)a.nv) return;
                 const int rl = row - r0;
+                const unsigned long long q0 = fixed(val * (1.0f - fu)), q1 = fixed(val * fu);
                 if (cin && rl >= 0 && rl < kAdjTH) {
-                    atomicAdd(&acc[rl * kAdjTW + cl], val * (1.0f - fu));
-                    atomicAdd(&acc[rl * kAdjTW + cl + 1], val * fu);
+                    atomicAdd(&acc[rl * kAdjTW + cl], q0);
+                    atomicAdd(&acc[rl * kAdjTW + cl + 1], q1);
                 } else {
-                    float* p = a.dws + plane + (size_t)(row - a.v0) * width + iu;
-                    atomicAdd(p, val * (1.0f - fu));
-                    atomicAdd(p + 1, val * fu);
+                    unsigned long long* p = a.dq + plane + (size_t)(row - a.v0) * width + iu;
+                    atomicAdd(p, q0);
+                    atomicAdd(p + 1, q1);
                 }
             };
             // the slices in order (from the lane's skew, wrapping once) move
@@ -803,9 +854,9 @@ __global__ __launch_bounds__(256) void k_bp_adjoint(AdjArgs a) {
         // non-zero entries lie at rows in [v0, v0 + nv) and columns in
         // [0, W): only such samples were added
         for (int e = threadIdx.x; e < kAdjTH * kAdjTW; e += 256) {
-            const float val = acc[e];
-            if (val != 0.0f)
-                atomicAdd(&a.dws[plane + (size_t)(r0 - a.v0 + e / kAdjTW) * width + (c0 + e % kAdjTW)], val);
+            const unsigned long long val = acc[e];
+            if (val != 0ull)
+                atomicAdd(&a.dq[plane + (size_t)(r0 - a.v0 + e / kAdjTW) * width + (c0 + e % kAdjTW)], val);
         }
         __syncthreads();
     }
@@ -826,12 +877,6 @@ __global__ __launch_bounds__(256) void k_residual(const float* f, const float* r
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) atomicAdd(loss, (double)weight * (part[0] + part[1] + part[2] + part[3]));
-}
-
-__global__ void k_fill(float* p, int64_t count, float v) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
 }
 
 __global__ void k_fill_d(double* p, int64_t count) {
@@ -903,10 +948,14 @@ hipError_t launch_learned_bwd(const LearnedArgs& a, int store, hipStream_t st) {
 }
 
 hipError_t launch_bp_adjoint(const AdjArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, st, a.dws, a.ws_elems, 0.0f);
     const int64_t nblk = (int64_t)a.ntiles * ((a.nz + kAdjZR - 1) / kAdjZR);
     if (nblk <= 0 || nblk > (int64_t)1 << 31) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_adj_clear, dim3(1024), dim3(256), 0, st, a.qs, a.dq, a.ws_elems);
+    hipLaunchKernelGGL(k_adj_absmax, dim3(1024), dim3(256), 0, st, a.resid, a.nvox, a.qs);
+    hipLaunchKernelGGL(k_adj_scale, dim3(1), dim3(1), 0, st, a.qs, a.bound);
     hipLaunchKernelGGL(k_bp_adjoint, dim3((unsigned)nblk), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_adj_convert, dim3(1024), dim3(256), 0, st, (const unsigned long long*)a.dq,
+                       (const AdjScale*)a.qs, a.dws, a.ws_elems);
     return hipGetLastError();
 }
 

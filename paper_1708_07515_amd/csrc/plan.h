@@ -41,6 +41,10 @@ struct fdkod_plan_s {
     int* d_blo = nullptr;       // row-staged decimation: [blocks][nsched] least crop offset of a 2 x 2 block
     int2* d_sqoff = nullptr;    // row-staged decimation: [nsq][nsched] offset from it, fraction bits
     float* d_lpartials = nullptr;  // learned backward: per-workgroup partial gradients (learned plans only)
+    // the adjoint's scale and int64 sums (allocated by the first adjoint call,
+    // grown when a later call needs more; freed with the plan)
+    void* d_adj = nullptr;
+    int64_t adj_cap = 0;        // int64 elements after the 256-byte scale block
     float* d_rscale = nullptr;  // [nsq][nsched] R / D_c (cone-corrected rows only)
     float* d_wext = nullptr;    // [nsched][nw - 2] weights of windows 2.. (nw > 2 only)
     float4* d_geo_m = nullptr;
