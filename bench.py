@@ -222,12 +222,48 @@ def run_learned(torch, pkg, wl, res, steps):
                  "step": "learned decomposition, backprojection, squared residual against the "
                          "triangle step's volume, transpose of the backprojection, weight gradient, AdamW"}
         del resid, dws, train_target
-    return {"ms_per_step": round(step_ms, 4),
-            "gvups": round(updates_eq / (step_ms * 1e-3) / 1e9, 3),
-            "stage_ms": {a: round(b, 4) for a, b in per.items()},
-            "decompose_triangle_ms": round(res["per"]["decompose"], 4),
-            "weights": "817 BF16 parameters, seeded random",
-            "training_step": train}
+    out = {"ms_per_step": round(step_ms, 4),
+           "gvups": round(updates_eq / (step_ms * 1e-3) / 1e9, 3),
+           "stage_ms": {a: round(b, 4) for a, b in per.items()},
+           "decompose_triangle_ms": round(res["per"]["decompose"], 4),
+           "weights": "817 BF16 parameters, seeded random",
+           "training_step": train}
+    if wl.name == "cone2000_p720" and plan.s == 4:
+        out["trained"] = run_learned_slabs(torch, pkg, wl)
+    return out
+
+
+def run_learned_slabs(torch, pkg, wl, nzs=32):
+    """The filter trained at this geometry (weights written by the quality
+    study's --learned-c5 run) on held-out slabs: rel-RMSE against direct FDK
+    of the triangle, the learned filter and the windowed sinc + cubic shift;
+    and the time of one AdamW step on a slab (learned decomposition of the
+    slab's band, slab reconstruction, residual, slab transpose, weight
+    gradient, update)."""
+    import study
+    net = study.load_learned_c5(pkg)
+    if net is None:
+        return None
+    scans = study.SlabScans(torch, pkg, wl, 4, nzs, wl.ellipsoids)
+    seeds, positions = [9200, 9201, 9202, 9203], [384, 768, 1152, 1536]
+    held = study.held_out_slabs(torch, pkg, scans, net, seeds, positions)
+    log("[bench] trained learned filter, held-out slabs, rel-RMSE vs direct FDK: "
+        + ", ".join(f"{a} {b:.4f}" for a, b in held["mean"].items()))
+    # one training step on the last held-out slab (a copy of the net: the
+    # trained weights stay as they are)
+    trainer = study.load_learned_c5(pkg)
+    z0 = positions[-1]
+    v0, nr, fb = scans.slab(seeds[-1], z0)
+    w = 1.0 / scans.energy(scans.tgt)
+    tstages = [("train_step_slab", lambda: trainer.train_step_slab(
+        scans.plan, fb, v0, scans.ws(nr), z0, scans.vol, scans.tgt, scans.resid, scans.dws(nr), weight=w))]
+    _, train_ms, _ = timed_steps(torch, tstages, 3, 1)
+    scans.close()
+    return {"held_out": {k: [round(x, 5) for x in v] if k != "slabs" else v for k, v in held.items() if k != "mean"},
+            "held_out_mean": {k: round(v, 5) for k, v in held["mean"].items()},
+            "reference": "direct FDK (s = 0) of the same slab from the same filtered band",
+            "slab_slices": nzs, "weights": "paper_1708_07515_amd/learned_c5_weights.txt",
+            "train_step_slab_ms": round(train_ms, 3), "train_step_slab_rows": nr}
 
 
 def _rel_rmse_regions(torch, vol, ref, regions, chunk=32):

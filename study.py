@@ -399,17 +399,19 @@ class SlabScans:
         self.direct.close()
 
 
-def train_learned_slabs(torch, pkg, scans, steps, lr, seed0, rng_seed=7, log_every=64):
+def train_learned_slabs(torch, pkg, scans, steps, lr, seed0, rng_seed=7, log_every=64, positions=None):
     """AdamW on one slab per step (phantom seed0 + step, slab position drawn
-    with rng_seed), each slab's squared error weighted by the inverse of its
-    target's energy; returns the trained LearnedDecimation and the training
-    time split (ms of library kernels per step, seconds of data generation)."""
+    with rng_seed from ``positions``, default every position), each slab's
+    squared error weighted by the inverse of its target's energy; returns the
+    trained LearnedDecimation and the training time split (ms of library
+    kernels per step, seconds of data generation)."""
     net = pkg.LearnedDecimation("cuda:0", seed=0, lr=lr)
     rng = np.random.default_rng(rng_seed)
     t_gen = t_train = 0.0
     skipped = 0
+    positions = scans.zs if positions is None else positions
     for it in range(steps):
-        z0 = int(rng.choice(scans.zs))
+        z0 = int(rng.choice(positions))
         t0 = time.time()
         v0, nr, fb = scans.slab(seed0 + it, z0)
         e = scans.energy(scans.tgt)
@@ -462,7 +464,18 @@ def held_out_slabs(torch, pkg, scans, net, seeds, positions):
     return out
 
 
-def learned_c5(torch, pkg, steps=512, lr=5e-4, nzs=32, held=16):
+def load_learned_c5(pkg, path=LEARNED_C5_WEIGHTS, device="cuda:0"):
+    """A LearnedDecimation holding the weights learned_c5 wrote (None when the
+    file is absent)."""
+    if not os.path.exists(path):
+        return None
+    vals = [float(x) for x in open(path).read().split("\n") if x.strip() and not x.startswith("#")]
+    net = pkg.LearnedDecimation(device, seed=0)
+    net.load(np.asarray(vals, dtype=np.float32))
+    return net
+
+
+def learned_c5(torch, pkg, steps=512, lr=1e-3, nzs=32, held=16, out_path=LEARNED_C5_WEIGHTS):
     """The learned decimation at the N = 2000, P = 720, s = 4 workload (D = 16,
     dilation 4): trained on ``steps`` seeded 30-ellipsoid phantoms (seeds
     5000 + i), one slab of nzs slices each, and compared on ``held`` other
@@ -472,7 +485,13 @@ def learned_c5(torch, pkg, steps=512, lr=5e-4, nzs=32, held=16):
     from synth import configs
     wl = configs.C5
     scans = SlabScans(torch, pkg, wl, 4, nzs, wl.ellipsoids)
-    net, timing = train_learned_slabs(torch, pkg, scans, steps, lr, 5000)
+    # training slabs from the central half of the volume: towards its ends a
+    # slab can hold little of the phantom, and its inverse-energy weight then
+    # lets a few nearly empty slabs drive the updates (training on every
+    # position diverged at lr 2e-3)
+    nzv = wl.nz or wl.n
+    central = [z for z in scans.zs if abs(z + nzs / 2 - nzv / 2) < nzv / 4]
+    net, timing = train_learned_slabs(torch, pkg, scans, steps, lr, 5000, positions=central, log_every=32)
     # held-out slabs spread over the central three quarters of the volume
     lo, hi = (wl.nz or wl.n) // 8, (wl.nz or wl.n) - (wl.nz or wl.n) // 8 - nzs
     positions = [z for z in (int(x) // 32 * 32 for x in np.linspace(lo, hi, held))]
@@ -480,7 +499,7 @@ def learned_c5(torch, pkg, steps=512, lr=5e-4, nzs=32, held=16):
     log("[study] learned c5 held-out mean rel-RMSE vs direct FDK: "
         + ", ".join(f"{a} {b:.4f}" for a, b in res["mean"].items()))
     w = net.master.detach().cpu().double().numpy()
-    with open(LEARNED_C5_WEIGHTS, "w") as f:
+    with open(out_path, "w") as f:
         f.write("# learned decimation filter for N = 2000, P = 720, R = 8000, s = 4 (D = 16): 817 FP32 master\n"
                 f"# weights (W1 [16][5][5], b1 [16], W2 [16][5][5], b2), AdamW lr {lr}, {steps} slabs of "
                 f"{nzs} slices; written by study.py --learned-c5\n")
@@ -488,8 +507,9 @@ def learned_c5(torch, pkg, steps=512, lr=5e-4, nzs=32, held=16):
             f.write(f"{x:.9e}\n")
     scans.close()
     return {"n": wl.n, "p": wl.p, "r": wl.r, "s": 4, "d": 16, "slab_slices": nzs, "train_phantoms": steps,
-            "held_out_phantoms": held, "lr": lr, "timing": timing, "held_out": res,
-            "weights_file": os.path.relpath(LEARNED_C5_WEIGHTS, ROOT)}
+            "held_out_phantoms": held, "lr": lr, "train_slices": [central[0], central[-1] + nzs],
+            "timing": timing, "held_out": res,
+            "weights_file": os.path.relpath(os.path.abspath(out_path), ROOT)}
 
 
 def main():
@@ -499,7 +519,8 @@ def main():
     ap.add_argument("--learned-c5", action="store_true",
                     help="only train and evaluate the learned filter at N = 2000, P = 720, s = 4")
     ap.add_argument("--c5-steps", type=int, default=512)
-    ap.add_argument("--c5-lr", type=float, default=5e-4)
+    ap.add_argument("--c5-lr", type=float, default=1e-3)
+    ap.add_argument("--c5-out", default=LEARNED_C5_WEIGHTS, help="where the trained weights are written")
     args = ap.parse_args()
     import torch
 
@@ -507,7 +528,7 @@ def main():
 
     t0 = time.time()
     if args.learned_c5:
-        res = learned_c5(torch, pkg, steps=args.c5_steps, lr=args.c5_lr)
+        res = learned_c5(torch, pkg, steps=args.c5_steps, lr=args.c5_lr, out_path=args.c5_out)
         print(json.dumps({"study": "learned decimation at N = 2000, P = 720, s = 4 on one MI355X",
                           "data": "synthetic", "learned_c5": res, "seconds": round(time.time() - t0, 1)}),
               flush=True)

@@ -59,10 +59,55 @@ def oracle_reconstruct(proj, r, s, skip=0, slices=None, nz=None, store=None):
     return ofdkod.fdkod(arr, r, s, skip, slices=slices, nz=nz, store=rounder)
 
 
-def report(tag, got, ref):
+# what the oracle's worker processes read: set before the pool forks, so the
+# projections are shared with the children (copy on write), never pickled
+_POOL = {}
+
+
+def _oracle_job(task):
+    from threadpoolctl import threadpool_limits
+    vi, l = task
+    c = _POOL["scans"][vi]
+    with threadpool_limits(limits=1):
+        if c["s"] == 0:
+            return ofdk.fdk(c["proj"], c["r"], slices=[l], nz=c["nz"])[0]
+        return ofdkod.fdkod(c["proj"], c["r"], c["s"], c["k"], slices=[l], nz=c["nz"])[0]
+
+
+def oracle_slices_many(scans, tasks, workers=16):
+    """FP64 oracle slices of several scans, one slice per task on forked
+    worker processes (numpy pools limited to one thread each).  scans: list
+    of dict(proj, r, s, k, nz), proj a CPU tensor or array [P][N][N]; tasks:
+    list of (scan index, slice).  Returns the slices in task order."""
+    import multiprocessing as mp
+    import os
+    _POOL["scans"] = [dict(c, proj=c["proj"].numpy() if isinstance(c["proj"], torch.Tensor)
+                           else np.asarray(c["proj"])) for c in scans]
+    nw = max(1, min(len(tasks), workers, len(os.sched_getaffinity(0))))
+    try:
+        with mp.get_context("fork").Pool(processes=nw) as pool:
+            return pool.map(_oracle_job, [(int(a), int(b)) for a, b in tasks], chunksize=1)
+    finally:
+        _POOL.clear()
+
+
+def oracle_slices_parallel(proj, r, s, k, slices, nz, workers=16):
+    """The FP64 oracle's slices (a list of indices) of one scan, one slice per
+    worker process: [len(slices)][N][N]."""
+    scans = [dict(proj=proj, r=r, s=s, k=k, nz=nz)]
+    return np.stack(oracle_slices_many(scans, [(0, l) for l in slices], workers))
+
+
+def report(tag, got, ref, bar=None, factor=20.0):
+    """rel-RMSE and max-abs of got against ref, logged; with a rel-RMSE bar,
+    also asserts that the largest single error is at most factor x bar of
+    max |ref| (a bad square edge or tail column that the RMSE over a whole
+    volume would average away fails this)."""
     err = metrics.rel_rmse(got, ref)
     mx, mxr = metrics.max_abs(got, ref)
     log(f"{tag}: rel-RMSE {err:.3e}  max-abs {mx:.3e} ({mxr:.3e} of max|ref|)")
+    if bar is not None:
+        assert mxr <= factor * bar, f"{tag}: max-abs {mxr:.3e} of max|ref| above {factor:g} x {bar:g}"
     return err, mxr
 
 

@@ -103,7 +103,7 @@ def test_learned_forward_matches_oracle(case):
     tri = ofdkod.triangle_weights(p, len(betas_dec))
     got_y = square_views(plan, _as(plan, ws_l))
     got_t = square_views(plan, _as(plan, ws_plain))
-    errs_r, errs_y = [], []
+    errs_r, errs_y, maxs_y = [], [], []
     for q, sub in enumerate(subs):
         r_or, _ = learned.forward(sub, net, d_factor, len(betas_dec), bf16=True)   # [v, P', W]
         t_or = np.moveaxis(np.tensordot(sub, tri.T, axes=(1, 0)), -1, 1)
@@ -111,6 +111,7 @@ def test_learned_forward_matches_oracle(case):
         gt = got_t[q].numpy().transpose(1, 0, 2)
         errs_r.append(metrics.rel_rmse(gy - gt, r_or))
         errs_y.append(metrics.rel_rmse(gy, t_or + r_or))
+        maxs_y.append(metrics.max_abs(gy, t_or + r_or)[1])
     log(f"learned forward {case}: R rel-RMSE max {max(errs_r):.2e}, Y rel-RMSE max {max(errs_y):.2e}")
     # Both sides round S and the activations to BF16.  The GPU's S carries the
     # FP32 filter's ~1e-6 relative error, which moves a few values across a
@@ -118,6 +119,8 @@ def test_learned_forward_matches_oracle(case):
     # changes R by about 3e-4 rel-RMSE.  Hence 1e-3.
     assert max(errs_r) <= 1e-3
     assert max(errs_y) <= 1e-3
+    # the largest single error of Y, of its square's max |Y|: at most 20 x the bar
+    assert max(maxs_y) <= 2e-2, max(maxs_y)
     plan.close()
 
 
@@ -430,10 +433,64 @@ def test_adjoint_identity_and_oracle(case):
     torch.cuda.synchronize()
     got = square_views(plan, dws.cpu().double())
     err = metrics.rel_rmse(got[q].numpy().transpose(1, 0, 2), ref)
+    mxr = metrics.max_abs(got[q].numpy().transpose(1, 0, 2), ref)[1]
     others = max(float(got[o].abs().max()) for o in range(len(sqs)) if o != q)
-    log(f"adjoint square {q} vs oracle: rel-RMSE {err:.2e}, other squares max {others:.1e}")
-    assert err <= 1e-5 and others == 0.0
+    log(f"adjoint square {q} vs oracle: rel-RMSE {err:.2e}, max-abs {mxr:.2e} of max|ref|, "
+        f"other squares max {others:.1e}")
+    assert err <= 1e-5 and mxr <= 2e-4 and others == 0.0
     plan.close()
+
+
+def test_adjoint_is_deterministic_and_flags_non_finite():
+    """The transpose sums in fixed point: calls on different streams give the
+    same bits; a non-finite residual makes every entry NaN."""
+    n, p, r, s = 64, 96, 256.0, 3
+    plan = pkg.Plan(n, p, r, s=s)
+    gen = torch.Generator().manual_seed(8)
+    res = torch.randn((plan.nz, n, n), generator=gen).to(DEV)
+    a = torch.empty(plan.workspace_elems, dtype=torch.float32, device=DEV)
+    b = torch.empty_like(a)
+    plan.reconstruct_adjoint(res, a)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.reconstruct_adjoint(res, b, side)
+    side.synchronize()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and bool(torch.isfinite(a).all()) and float(a.abs().max()) > 0
+    res[3, 20, 30] = float("inf")
+    plan.reconstruct_adjoint(res, b)
+    torch.cuda.synchronize()
+    assert bool(torch.isnan(b).all())
+    res.zero_()
+    plan.reconstruct_adjoint(res, b)
+    torch.cuda.synchronize()
+    assert int(torch.count_nonzero(b)) == 0
+    plan.close()
+
+
+def test_training_is_repeatable():
+    """Two trainings from the same seed take the same steps bit for bit (the
+    transpose sums in fixed point, the weight gradient in a fixed order)."""
+    n, nz, p, r, s = 64, 32, 96, 256.0, 3
+    direct = pkg.Plan(n, p, r, s=0, nz=nz)
+    data = _scans(direct, n, p, r, range(300, 302))
+    plan = pkg.Plan(n, p, r, s=s, nz=nz)
+    ws, vol = plan.empty_workspace(), plan.empty_volume()
+    resid = torch.empty_like(vol)
+    dws = torch.empty(plan.workspace_elems, dtype=torch.float32, device=DEV)
+    finals = []
+    for _ in range(2):
+        net = pkg.LearnedDecimation(DEV, seed=0, lr=3e-3)
+        for it in range(6):
+            filt, tgt = data[it % len(data)]
+            net.train_step(plan, filt, ws, vol, tgt, resid, dws)
+        torch.cuda.synchronize()
+        finals.append((net.master.cpu().clone(), net.m2.cpu().clone()))
+    assert torch.equal(finals[0][0], finals[1][0]) and torch.equal(finals[0][1], finals[1][1])
+    assert not torch.equal(finals[0][0], pkg.LearnedDecimation("cpu", seed=0).master)
+    for pl in (plan, direct):
+        pl.close()
 
 
 def test_residual_and_adamw_match_torch():
@@ -558,10 +615,10 @@ def test_training_beats_plain_decimation_on_held_out_phantoms():
     trained = held_out_error(True)
     log(f"held-out rel-RMSE vs direct FDK: triangle {plain:.4f}, learned {trained:.4f} "
         f"({plain / trained:.3f}x lower)")
-    # training is not bitwise repeatable (the weight gradients are summed with
-    # atomics, so AdamW's path varies from run to run): held-out errors of
-    # 0.101-0.115 against 0.120 have been seen, so the bar is 2 % below plain
-    assert np.isfinite(trained) and trained <= 0.98 * plain
+    # training is bitwise repeatable (fixed-point transpose, fixed-order
+    # gradient sums), so the result is one number for this code: the bar is
+    # 5 % below plain
+    assert np.isfinite(trained) and trained <= 0.95 * plain
     for pl in (plan, direct):
         pl.close()
 
@@ -637,3 +694,30 @@ def test_learned_band_calls_match_whole_volume_rows():
         ea = (num / den) ** 0.5
         log(f"band gradient rel-RMSE {eg:.2e}, slab adjoint rel-RMSE {ea:.2e}")
         assert eg <= 1e-5 and ea <= 1e-6
+
+
+# The committed weights (AdamW at lr 1e-3 on one 32-slice slab from the central
+# half of each of 512 phantoms) lower the error to 0.962..0.992 of the
+# triangle's on the quality study's 16 held-out slabs (mean 0.967); the
+# forward pass is deterministic, so the bar holds one fixed number per slab.
+C5_GAIN_BAR = 0.98
+
+
+def test_trained_filter_at_n2000_beats_the_triangle_on_held_out_slabs():
+    """The filter trained at N = 2000, P = 720, s = 4 (D = 16; 512 seeded
+    phantoms, one 32-slice slab each, written by the quality study) lowers
+    the FDK-OD error against direct FDK on slabs of phantoms it was not
+    trained on, slab by slab and on average."""
+    import study
+    from synth import configs
+    net = study.load_learned_c5(pkg)
+    assert net is not None, "paper_1708_07515_amd/learned_c5_weights.txt is missing"
+    wl = configs.C5
+    scans = study.SlabScans(torch, pkg, wl, 4, 32, wl.ellipsoids)
+    res = study.held_out_slabs(torch, pkg, scans, net, [9100, 9101, 9102], [640, 992, 1312])
+    scans.close()
+    tri, lrn = np.array(res["triangle"]), np.array(res["learned"])
+    log(f"N = 2000 held-out slabs: triangle {np.round(tri, 4)}, learned {np.round(lrn, 4)}, "
+        f"sinc6 + cubic {np.round(res['sinc6_cubic'], 4)}")
+    assert len(tri) == 3 and np.all(lrn < tri)
+    assert lrn.mean() <= C5_GAIN_BAR * tri.mean()
