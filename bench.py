@@ -434,11 +434,10 @@ def run_batch(torch, pkg, bw, steps):
     }
 
 
-def measured_traffic(kernel, wl, s, k, store):
-    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration),
-    or None when the kernel's source or the workload differs from the one that
-    was profiled."""
+def profiled(kernel, wl, s, k, store):
+    """The committed rocprofv3 summary record of ``kernel``
+    (profiles/hbm_traffic.json), or None when the kernel's source or the
+    workload differs from the one that was profiled."""
     import hashlib
     try:
         with open(os.path.join(ROOT, "profiles", "hbm_traffic.json")) as f:
@@ -449,7 +448,21 @@ def measured_traffic(kernel, wl, s, k, store):
         return None
     if sha != rec["source_sha256"] or (rec["workload"], rec["s"], rec["k"], rec["store"]) != (wl.name, s, k, store):
         return None
-    return rec["read_bytes"] + rec["write_bytes"]
+    return rec
+
+
+def measured_traffic(kernel, wl, s, k, store):
+    """HBM bytes per launch of ``kernel`` (FETCH_SIZE + WRITE_SIZE, scaled by
+    the copy-kernel calibration) from the committed counter summary."""
+    rec = profiled(kernel, wl, s, k, store)
+    return None if rec is None else rec["read_bytes"] + rec["write_bytes"]
+
+
+def measured_counter(kernel, wl, s, k, store, key):
+    """A derived counter figure (e.g. VALU instructions per work unit) from
+    the committed counter summary."""
+    rec = profiled(kernel, wl, s, k, store)
+    return None if rec is None else rec.get(key)
 
 
 def kernel_rooflines(wl, s, k, store, res):
@@ -475,7 +488,8 @@ def kernel_rooflines(wl, s, k, store, res):
     out = {
         "filter": hbm("k_filter", "filter", n * n * p * (4 + bs),
                       "projections read once (FP32) + filtered rows written once (store type)"),
-        "decompose": hbm("k_decimate", "decompose", n * n * p * bs + ws_bytes,
+        "decompose": hbm("k_decimate_staged" if plan.get_tuning()["decim_chunks"] == 0 else "k_decimate",
+                         "decompose", n * n * p * bs + ws_bytes,
                          "filtered rows read once + decimated sub-sinograms written once"),
     }
     ms = per["reconstruct"]
@@ -495,6 +509,11 @@ def kernel_rooflines(wl, s, k, store, res):
                 "unit": "GB/s", "bytes": "decimated sub-sinograms read once + volume written once"},
         "traffic": measured_traffic("k_backproject", wl, s, k, store),
     }
+    # the backprojection's VALU instructions per update (all of them: the
+    # inner loop, the per-angle set-up and the staging) from the committed
+    # counter summary, when it was taken on this kernel and workload
+    out["reconstruct"]["valu_instr_per_update"] = measured_counter("k_backproject", wl, s, k, store,
+                                                                   "valu_instr_per_update")
     return out
 
 

@@ -13,11 +13,12 @@
 // with eq. (1) at the block's corners (columns) and eq. (9) at its corner
 // depths and end slices (rows) -- the paper's vertex bound applied to the
 // block -- and that footprint (at most TH x TW samples, padded by one sample
-// on every side) is staged in LDS as pairs (Y[c], Y[c+1] - Y[c]), so one
-// 64-bit LDS read pair fetches the two rows of a bilinear sample and each
-// horizontal interpolation is one FMA.  Per (x, y, angle) a thread computes
-// tau, U and the weight once; along z only the row coordinate moves, linearly
-// (b = z / U), so an update costs a row index, one LDS read and five FMAs.
+// on every side) is staged in LDS as quads (Y, dU, dV, dUV) of forward
+// differences, so one 128-bit LDS read fetches all four samples of a
+// bilinear interpolation, which is then three FMAs.  Per (x, y, angle) a
+// thread computes tau, U and the weight once; along z only the row
+// coordinate moves, linearly (b = z / U), so an update costs a row index,
+// one LDS read and four FMAs.
 #include "internal.h"
 #include "dtype.h"
 
@@ -38,10 +39,10 @@ hipError_t checks_read_backproject(unsigned long long* out, bool reset) {
     return e;
 }
 
-typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 
 typedef __attribute__((address_space(3))) const char* lds_cptr;
-typedef __attribute__((address_space(3))) const f2v* lds_f2ptr;
+typedef __attribute__((address_space(3))) const f4v* lds_f4ptr;
 
 // Per-angle footprints and constants are computed for kFpChunk angles at a
 // time (one lane per angle) and kept for two such chunks.
@@ -51,7 +52,7 @@ constexpr int kFpChunk = 64;
 // the per-angle constants.
 template <int TW, int TH, int G>
 struct BpSmem {
-    float2 tile[G][TH * (TW + 1)];
+    float4 tile[G][TH * (TW + 1)];
     int4 meta[2][kFpChunk];      // c0, r0 (first column / row of the footprint), rows, -
     float4 mgeo[2][kFpChunk];    // cos, sin, Dc, Lc
     float2 mgeo2[2][kFpChunk];   // R / Dc, c_u - u0 - c0
@@ -74,8 +75,7 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
                                          BpSmem<TW, TH, G>& sm) {
     using S = Store<STORE>;
     using T = typename S::T;
-    constexpr int TWP = TW + 1;   // LDS row pitch in pairs (odd: spreads banks)
-    static_assert(TWP <= 255, "ds_read2_b64 offset range");
+    constexpr int TWP = TW + 1;   // LDS row pitch in quads (odd: spreads banks)
     auto& tile = sm.tile;
     const SquareDesc sq = v.squares[tl.sq];
     const int2 gd = v.grid[tl.sq];
@@ -106,12 +106,14 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
     const T* data = (const T*)v.data + (direct ? 0 : sq.y_off_row * v.nv);
     const float kq = v.cu - (float)u0;            // tau = rel + kq
 
-    // staging map: a lane keeps one footprint column, rows strided by 256 / TW
-    constexpr int RSTEP = 256 / TW;
-    static_assert(TH % RSTEP == 0, "uniform staging trip count");
-    constexpr int NR = TH / RSTEP;
+    // staging map: a lane keeps one footprint column and NQ consecutive rows
+    // (their quads), for which it loads NQ + 1 rows
+    constexpr int NGRP = 256 / TW;
+    static_assert(TH % NGRP == 0, "uniform staging trip count");
+    constexpr int NQ = TH / NGRP;
+    constexpr int NR = NQ + 1;
     const int scol = threadIdx.x % TW;
-    const int srow = threadIdx.x / TW;
+    const int srow = (threadIdx.x / TW) * NQ;
 
     // footprints of the block at the kFpChunk angles from m0 (a multiple of
     // kFpChunk), one lane of the first wave per angle: eq. (1) at the block's
@@ -157,13 +159,13 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
     // data: rows outside the buffer fall outside it and read zero (a row above
     // the first wraps to a huge unsigned offset), and a column outside
     // [0, width) gets an offset beyond every plane, so its samples read zero
-    // too.  A lane's samples are RSTEP rows apart, so each costs one add.
+    // too.  A lane's samples are consecutive rows, so each costs one add.
     // Footprints of more than 16 samples per thread are loaded after the
     // arithmetic instead (their registers would cost occupancy).
     constexpr bool kPrefetch = G * NR <= 16;
     constexpr int ES = (int)sizeof(T);
     const uint32_t plane_bytes = (uint32_t)(plane * ES);
-    const int rstep_bytes = RSTEP * row_stride * ES;
+    const int rstep_bytes = row_stride * ES;
     uint32_t pre[G][NR];
     auto fetch_one = [&](int m0, int g) {
         {
@@ -190,19 +192,25 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
             }
         }
     };
-    // pairs (Y[c], Y[c+1] - Y[c]) into LDS; the last column's pair is never
-    // read (the column index is at most TW - 2), so the lane that receives
-    // the next footprint row's first sample writes an unused pair.  Rows
-    // below the footprint's last are written too: they lie inside the tile
-    // and are never read.
+    // quads (Y, dU, dV, dUV) into LDS: at (r, c), Y = Y[r][c], dU = Y[r][c+1]
+    // - Y[r][c], dV = Y[r+1][c] - Y[r][c], dUV = dU[r+1] - dU[r], so that the
+    // bilinear sample at (r + fv, c + fu) is Y + fu dU + fv (dV + fu dUV).
+    // The last column's quad is never read (the column index is at most
+    // TW - 2), so the lane that receives the next group's first sample
+    // writes an unused quad; nor is the last row's (the row index is at most
+    // TH - 2), whose extra row lies past the tile.  Rows below the
+    // footprint's last are written too: they lie inside the tile and are
+    // never read.
     auto stage_one = [&](int g) {
+        float y[NR], du[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int rr = srow + r * RSTEP;
-            const float y0 = S::from_bits(pre[g][r]);
-            const float y1 = from_next_lane(y0);
-            tile[g][rr * TWP + scol] = make_float2(y0, y1 - y0);
+            y[r] = S::from_bits(pre[g][r]);
+            du[r] = from_next_lane(y[r]) - y[r];
         }
+#pragma unroll
+        for (int r = 0; r < NQ; ++r)
+            tile[g][(srow + r) * TWP + scol] = make_float4(y[r], du[r], y[r + 1] - y[r], du[r + 1] - du[r]);
     };
 
     float acc[ZR];
@@ -270,11 +278,11 @@ __device__ __forceinline__ void bp_block(const BpVol& v, int zt, const BpTile& t
                 const float vv = fmaf((float)k, vstep, v0);
                 const float fv = __builtin_amdgcn_fractf(vv);
                 const uint32_t ri = (uint32_t)(int)vv;
-                const lds_f2ptr p = (lds_f2ptr)(uintptr_t)(tga + __umul24(ri, (uint32_t)(TWP * sizeof(float2))));
-                const f2v A = p[0], B = p[TWP];
-                const float top = fmaf(fu, A.y, A.x);
-                const float bot = fmaf(fu, B.y, B.x);
-                acc[k] = fmaf(w, fmaf(fv, bot - top, top), acc[k]);
+                const lds_f4ptr p = (lds_f4ptr)(uintptr_t)(tga + __umul24(ri, (uint32_t)(TWP * sizeof(float4))));
+                const f4v Q = p[0];
+                const float top = fmaf(fu, Q.y, Q.x);          // row ri at tau
+                const float dv = fmaf(fu, Q.w, Q.z);           // row ri + 1 minus row ri at tau
+                acc[k] = fmaf(w, fmaf(fv, dv, top), acc[k]);
                 // four slices per group: their accumulators are complete before
                 // the next group's reads are issued (without this fence the
                 // compiler may issue all ZR reads first and trade occupancy

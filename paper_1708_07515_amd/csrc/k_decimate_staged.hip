@@ -8,13 +8,15 @@
 // squares (one wavefront per square).  Their crops of row v overlap: at every
 // projection they lie within one segment [lo, lo + seg) of the row, lo the
 // least crop offset of the four squares.  The workgroup walks the decimation
-// schedule eight steps (projections) at a time: each wave loads two steps'
+// schedule a stage of eight (or, for long segments, four) steps
+// (projections) at a time: each wave loads a quarter of the next stage's
 // segments (zero outside the detector, by the buffer range check) while the
-// previous eight steps are being computed -- FP32 rows straight into LDS,
-// 16-bit rows into registers that are widened and written to LDS after the
-// computation; one barrier per eight steps orders the double buffer.  The
-// step tables (schedule, the block's least crop offset, each square's offset
-// from it) are built once per plan and read a stage at a time.  A lane owns local columns lane + 64 c of its wave's square, reads
+// current stage is computed -- FP32 rows straight into LDS, 16-bit rows into
+// registers that are widened and written to LDS after the computation; one
+// barrier per stage orders the double buffer.  The step tables (schedule,
+// the block's least crop offset, each square's offset from it) are built
+// once per plan and read a stage at a time.  A lane owns local columns
+// lane + 64 c of its wave's square, reads
 // the two samples of each column's linear interpolation from LDS (adjacent
 // lanes read adjacent words: no bank conflicts), and adds the interpolated
 // value to the two open triangle windows; a window is written when its last
@@ -31,7 +33,12 @@ namespace fdkod {
 typedef __attribute__((address_space(4))) const int* cword_ptr;
 typedef __attribute__((address_space(3))) const float* lds_fptr;
 
-constexpr int kStagedSteps = 8;                 // schedule steps per stage (two per wave)
+// schedule steps per stage: eight (two per wave), or four for long segments,
+// whose double buffer of eight would hold the LDS to five workgroups per CU
+// (four steps: 16.7 ms against 19.3 ms at N = 2000, s = 4, 512-sample
+// segments; eight where the buffer allows eight workgroups anyway)
+template <int SEGC>
+constexpr int staged_steps() { return SEGC >= 6 ? 4 : 8; }
 
 // event counters of a checked build (see CheckKind)
 static __device__ unsigned g_checks_dec[kCheckKinds];
@@ -47,7 +54,7 @@ hipError_t checks_read_decimate(unsigned long long* out, bool reset) {
     }
     return e;
 }
-static_assert(kDecimUnroll % kStagedSteps == 0, "the schedule is padded to whole stages");
+static_assert(kDecimUnroll % 8 == 0 && kDecimUnroll % 4 == 0, "the schedule is padded to whole stages");
 
 // CPT: column chunks of 64 per lane; SEGC: 64-sample chunks of a staged
 // segment (seg = 64 SEGC >= the spread of the four crop offsets + 64 CPT + 1).
@@ -57,6 +64,8 @@ __global__ __launch_bounds__(256) void k_decimate_staged(DecimVol a) {
     using T = typename S::T;
     constexpr int ES = (int)sizeof(T);
     constexpr int SEG = 64 * SEGC;
+    constexpr int kStagedSteps = staged_steps<SEGC>();
+    constexpr int kSpw = kStagedSteps / 4;             // steps each wave stages
     // FP32 rows go from memory straight into LDS (no registers); 16-bit rows
     // pass through registers, where they are widened to FP32
     constexpr bool kDirect = STORE == 0;
@@ -91,24 +100,24 @@ __global__ __launch_bounds__(256) void k_decimate_staged(DecimVol a) {
     const size_t pstride = (size_t)a.nv * a.n;
     const int nbytes = a.n * ES;
 
-    // staging of a stage's segments: wave w takes steps 2w and 2w + 1.  Every
+    // staging of a stage's segments: wave w takes steps kSpw w .. kSpw w + kSpw - 1.  Every
     // chunk's offset is its own register: folded into the instruction's
     // constant offset, a lane whose first offset lies left of the row
     // (negative) would read zero for all its chunks.
-    float reg[kDirect ? 1 : 2][kDirect ? 1 : SEGC];
+    float reg[kDirect ? 1 : kSpw][kDirect ? 1 : SEGC];
     // (the step tables are read through pointers to the stage's first step,
     // so each word's address is a constant offset from one scalar base: the
     // per-word 64-bit address arithmetic otherwise costs more scalar
     // instructions than the stage has vector ones)
     auto load_stage = [&](cword_ptr s_st, cword_ptr l_st, int buf) {
-        int p[2], lo[2];
+        int p[kSpw], lo[kSpw];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            p[h] = s_st[4 * (2 * wave + h)];
-            lo[h] = l_st[2 * wave + h];
+        for (int h = 0; h < kSpw; ++h) {
+            p[h] = s_st[4 * (kSpw * wave + h)];
+            lo[h] = l_st[kSpw * wave + h];
         }
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < kSpw; ++h) {
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                 uniform_ptr(frow + (size_t)p[h] * pstride), (short)0, nbytes, 0x00020000);
 #pragma unroll
@@ -118,7 +127,7 @@ __global__ __launch_bounds__(256) void k_decimate_staged(DecimVol a) {
                 if constexpr (kDirect) {
                     // lane l's word lands at stage[buf][k][64 c + l]
                     __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                        rs, (__attribute__((address_space(3))) void*)&stage[buf][2 * wave + h][64 * c], 4, off,
+                        rs, (__attribute__((address_space(3))) void*)&stage[buf][kSpw * wave + h][64 * c], 4, off,
                         0, 0, 0);
                 } else {
                     reg[h][c] = S::raw(rs, off);
@@ -129,9 +138,9 @@ __global__ __launch_bounds__(256) void k_decimate_staged(DecimVol a) {
     auto store_stage = [&](int buf) {
         if constexpr (!kDirect) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+            for (int h = 0; h < kSpw; ++h)
 #pragma unroll
-                for (int c = 0; c < SEGC; ++c) stage[buf][2 * wave + h][lane + 64 * c] = reg[h][c];
+                for (int c = 0; c < SEGC; ++c) stage[buf][kSpw * wave + h][lane + 64 * c] = reg[h][c];
         } else {
             (void)buf;
             vmem_drain();            // the direct loads have written the LDS
