@@ -643,6 +643,9 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
     pl->nw = window_taps(*prm);
     pl->cubic = prm->interp == FDKOD_INTERP_CUBIC;
     {
+        // the FFT length: the least power of two (at least 8) holding the
+        // linear convolution, so N <= M / 2, which the filter kernel's pruned
+        // first and last stages rely on
         int m = 8;
         while (m < 2 * pl->n - 1) m <<= 1;
         pl->logm = 0;

@@ -95,9 +95,14 @@ __device__ __forceinline__ void transform_sync() {
 }
 
 // One Stockham stage of radix R (16, 4 or 2) at stride NS, TP threads.  The
-// first stage (NS = 1) needs no twiddles.
-template <int R, int M, int TP, int NS>
-__device__ __forceinline__ void fft_stage(float2* z, int t, const float2* __restrict__ tw) {
+// first stage (NS = 1) needs no twiddles.  DIFF (first stage): the input is
+// the first difference x[u] - x[u-1] of the values in LDS (x[-1] = 0) for
+// u < n and zero from n on; as n <= M / 2, the upper half of every
+// butterfly's inputs is zero and not read.  HALF (last stage, NS R = M):
+// only outputs below M / 2 are wanted, the upper half of every butterfly's
+// outputs is neither computed nor written.
+template <int R, int M, int TP, int NS, bool DIFF, bool HALF>
+__device__ __forceinline__ void fft_stage(float2* z, int t, const float2* __restrict__ tw, int n) {
     constexpr int NB = M / R;                       // butterflies of this stage
     constexpr int BPT = (NB + TP - 1) / TP;
     constexpr int ns = NS;
@@ -118,8 +123,22 @@ __device__ __forceinline__ void fft_stage(float2* z, int t, const float2* __rest
     for (int b = 0; b < BPT; ++b) {
         const int j = t + b * TP;
         if (j < NB) {
+            if constexpr (DIFF && NS == 1) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[b][r] = z[pidx(j + r * NB)];
+                for (int r = 0; r < R; ++r) {
+                    const int u = j + r * NB;
+                    if (r < R / 2) {
+                        const float2 x1 = z[pidx(u)];
+                        const float2 x0 = u > 0 ? z[pidx(u - 1)] : make_float2(0.0f, 0.0f);
+                        v[b][r] = u < n ? csub(x1, x0) : make_float2(0.0f, 0.0f);
+                    } else {
+                        v[b][r] = make_float2(0.0f, 0.0f);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[b][r] = z[pidx(j + r * NB)];
+            }
             if constexpr (NS > 1) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], w[b][r]);
@@ -143,7 +162,7 @@ __device__ __forceinline__ void fft_stage(float2* z, int t, const float2* __rest
             const int k = j & (ns - 1);
             const int dst = (j / ns) * ns * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) z[pidx(dst + r * ns)] = v[b][r];
+            for (int r = 0; r < (HALF && NS * R == M ? R / 2 : R); ++r) z[pidx(dst + r * ns)] = v[b][r];
         }
     }
     transform_sync<TP>();
@@ -151,26 +170,28 @@ __device__ __forceinline__ void fft_stage(float2* z, int t, const float2* __rest
 
 // The stages from stride NS on: radix 16 while at least four bits remain,
 // then 4, then 2.
-template <int M, int TP, int NS>
-__device__ __forceinline__ void fft_stages(float2* z, int t, const float2* __restrict__ tw) {
+template <int M, int TP, int NS, bool DIFF, bool HALF>
+__device__ __forceinline__ void fft_stages(float2* z, int t, const float2* __restrict__ tw, int n) {
     if constexpr (NS * 16 <= M) {
-        fft_stage<16, M, TP, NS>(z, t, tw);
-        fft_stages<M, TP, NS * 16>(z, t, tw);
+        fft_stage<16, M, TP, NS, DIFF, HALF>(z, t, tw, n);
+        fft_stages<M, TP, NS * 16, false, HALF>(z, t, tw, n);
     } else if constexpr (NS * 4 <= M) {
-        fft_stage<4, M, TP, NS>(z, t, tw);
-        fft_stages<M, TP, NS * 4>(z, t, tw);
+        fft_stage<4, M, TP, NS, DIFF, HALF>(z, t, tw, n);
+        fft_stages<M, TP, NS * 4, false, HALF>(z, t, tw, n);
     } else if constexpr (NS * 2 <= M) {
-        fft_stage<2, M, TP, NS>(z, t, tw);
+        fft_stage<2, M, TP, NS, DIFF, HALF>(z, t, tw, n);
     }
 }
 
 // In-place forward DFT of length M = 2^LOGM (natural order in and out, LDS
 // positions through pidx) by Stockham stages.  TP threads cooperate on one
 // transform; every thread of the workgroup calls this the same number of
-// times because it contains barriers.
-template <int LOGM, int TP>
-__device__ __forceinline__ void fft_lds(float2* z, int t, const float2* __restrict__ tw) {
-    fft_stages<1 << LOGM, TP, 1>(z, t, tw);
+// times because it contains barriers.  DIFF: the transform of the first
+// difference of the first n <= M / 2 values; HALF: only the lower half of
+// the result is wanted (see fft_stage).
+template <int LOGM, int TP, bool DIFF, bool HALF>
+__device__ __forceinline__ void fft_lds(float2* z, int t, const float2* __restrict__ tw, int n) {
+    fft_stages<1 << LOGM, TP, 1, DIFF, HALF>(z, t, tw, n);
 }
 
 // Threads per transform: one radix-16 butterfly per thread and stage (at
@@ -208,8 +229,8 @@ void k_filter(FilterArgs a) {
     const int n = a.n;
     const float rr = a.r * a.r;
 
-    // pre-weighted first difference d[u] = p~[u] - p~[u-1] (zero-padded);
-    // p~[u-1] is recomputed from the row rather than read back from LDS
+    // the pre-weighted rows p~ go to LDS; the first stage of the forward
+    // transform reads their first difference d[u] = p~[u] - p~[u-1]
     const float b0 = has0 ? (float)(a.v0 + r0 % a.nv) - a.c : 0.0f;
     const float b1 = has1 ? (float)(a.v0 + r1 % a.nv) - a.c : 0.0f;
     const float rb0 = rr + b0 * b0, rb1 = rr + b1 * b1;
@@ -221,11 +242,10 @@ void k_filter(FilterArgs a) {
         const float au = (float)u - a.c;
         return a.r * __builtin_amdgcn_rsqf(rb + au * au);
     };
-    // every sample of the thread is requested before any is used: samples
-    // u - 1 and u in one 8-byte load (u >= 1; u = 0 reads samples 0 and 1 and
-    // uses the first), both rows, all positions
+    // every sample of the thread is requested before any is used: both
+    // rows, all positions
     constexpr int IT = (M + TP - 1) / TP;
-    float2 q0[IT], q1[IT];
+    float q0[IT], q1[IT];
     if constexpr (TP >= 64) {
         // one row pair per wave or more waves per pair: the rows are wave-
         // uniform, so they are read through buffer resources (32-bit offsets,
@@ -241,34 +261,29 @@ void k_filter(FilterArgs a) {
             0x00020000);
 #pragma unroll
         for (int i = 0; i < IT; ++i) {
-            const int u = t + i * TP;
-            const int off = (u > 0 ? u - 1 : 0) * 4;
-            q0[i] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs0, off, 0, 0));
-            q1[i] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs1, off, 0, 0));
+            const int off = (t + i * TP) * 4;
+            q0[i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs0, off, 0, 0));
+            q1[i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs1, off, 0, 0));
         }
     } else {
 #pragma unroll
         for (int i = 0; i < IT; ++i) {
             const int u = t + i * TP;
-            const int u1 = u > 0 ? u - 1 : 0;
             const bool in = u < n;
-            q0[i] = (in && has0) ? *(const float2*)(p0 + u1) : make_float2(0.0f, 0.0f);
-            q1[i] = (in && has1) ? *(const float2*)(p1 + u1) : make_float2(0.0f, 0.0f);
+            q0[i] = (in && has0) ? p0[u] : 0.0f;
+            q1[i] = (in && has1) ? p1[u] : 0.0f;
         }
     }
-    // pre-weighted first difference d[u] = p~[u] - p~[u-1] (zero-padded); the
-    // difference at u = N is applied after the FFT
+    // pre-weighted rows p~[u] (zero from N on); the difference at u = N is
+    // applied after the FFT
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
         const int u = t + i * TP;
         if (u < M) {
             float d0 = 0.0f, d1 = 0.0f;
-            if (u == 0) {
-                d0 = q0[i].x * weight(0, rb0);
-                d1 = q1[i].x * weight(0, rb1);
-            } else if (u < n) {
-                d0 = q0[i].y * weight(u, rb0) - q0[i].x * weight(u - 1, rb0);
-                d1 = q1[i].y * weight(u, rb1) - q1[i].x * weight(u - 1, rb1);
+            if (u < n) {
+                d0 = q0[i] * weight(u, rb0);
+                d1 = q1[i] * weight(u, rb1);
             }
             z[pidx(u)] = make_float2(d0, d1);
         }
@@ -276,7 +291,7 @@ void k_filter(FilterArgs a) {
     const float last0 = has0 ? p0[n - 1] * weight(n - 1, rb0) : 0.0f;
     const float last1 = has1 ? p1[n - 1] * weight(n - 1, rb1) : 0.0f;
     transform_sync<TP>();
-    fft_lds<LOGM, TP>(z, t, a.twiddle);
+    fft_lds<LOGM, TP, true, false>(z, t, a.twiddle, n);
     // tables (L2-resident) are requested in one batch before their first use
     float2 gr[IT];
 #pragma unroll
@@ -293,7 +308,7 @@ void k_filter(FilterArgs a) {
         }
     }
     transform_sync<TP>();
-    fft_lds<LOGM, TP>(z, t, a.twiddle);
+    fft_lds<LOGM, TP, false, true>(z, t, a.twiddle, n);
     float gtl[IT];
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
