@@ -18,6 +18,8 @@
 // 4096-point transform takes three passes through LDS).  Two real rows travel in one complex transform (row0 + i row1); g is
 // real, so its transform G is Hermitian and multiplying by it keeps the rows
 // apart.  The inverse transform is conj(FFT(conj(.))); 1/M is folded into G.
+// For M = 4096 (N = 1025..2048) a four-step form with one row pair per
+// wavefront replaces the Stockham stages (k_filter4096 below).
 #include "internal.h"
 #include "dtype.h"
 
@@ -350,6 +352,189 @@ void k_filter(FilterArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// M = 4096 (N = 1025..2048): four-step transform, one row pair per wavefront.
+// Index u = a + 64 b (a: the lane, b: a register); the length-4096 DFT is a
+// 64-point DFT over b in every lane, a twiddle w^(a c), a transpose through
+// LDS, and a 64-point DFT over a in every lane: X[c + 64 d] lands in lane c,
+// register d -- the same layout (lane = low six bits of the index), so the
+// second transform of the filter (the forward DFT of conj(X G), section above)
+// runs the same steps on it.  The 64-point DFTs are in registers (4 x 16:
+// four 16-point DFTs, constant twiddles, sixteen 4-point DFTs); two passes
+// through LDS per transform and no workgroup barrier (the wavefront is the
+// whole workgroup).  N <= M / 2: the upper half of the first DFT's inputs
+// (b >= 32) is zero and the upper half of the last DFT's outputs is unused,
+// both left out.
+
+// w64^j = exp(-2 pi i j / 64)
+__device__ constexpr float kW64[64][2] = {
+    {1.0f, 0.0f}, {0.9951847195625305f, -0.0980171412229538f}, {0.9807852506637573f, -0.19509032368659973f}, {0.9569403529167175f, -0.290284663438797f},
+    {0.9238795042037964f, -0.3826834261417389f}, {0.8819212913513184f, -0.4713967442512512f}, {0.8314695954322815f, -0.5555702447891235f}, {0.7730104327201843f, -0.6343932747840881f},
+    {0.7071067690849304f, -0.7071067690849304f}, {0.6343932747840881f, -0.7730104327201843f}, {0.5555702447891235f, -0.8314695954322815f}, {0.4713967442512512f, -0.8819212913513184f},
+    {0.3826834261417389f, -0.9238795042037964f}, {0.290284663438797f, -0.9569403529167175f}, {0.19509032368659973f, -0.9807852506637573f}, {0.0980171412229538f, -0.9951847195625305f},
+    {0.0f, -1.0f}, {-0.0980171412229538f, -0.9951847195625305f}, {-0.19509032368659973f, -0.9807852506637573f}, {-0.290284663438797f, -0.9569403529167175f},
+    {-0.3826834261417389f, -0.9238795042037964f}, {-0.4713967442512512f, -0.8819212913513184f}, {-0.5555702447891235f, -0.8314695954322815f}, {-0.6343932747840881f, -0.7730104327201843f},
+    {-0.7071067690849304f, -0.7071067690849304f}, {-0.7730104327201843f, -0.6343932747840881f}, {-0.8314695954322815f, -0.5555702447891235f}, {-0.8819212913513184f, -0.4713967442512512f},
+    {-0.9238795042037964f, -0.3826834261417389f}, {-0.9569403529167175f, -0.290284663438797f}, {-0.9807852506637573f, -0.19509032368659973f}, {-0.9951847195625305f, -0.0980171412229538f},
+    {-1.0f, 0.0f}, {-0.9951847195625305f, 0.0980171412229538f}, {-0.9807852506637573f, 0.19509032368659973f}, {-0.9569403529167175f, 0.290284663438797f},
+    {-0.9238795042037964f, 0.3826834261417389f}, {-0.8819212913513184f, 0.4713967442512512f}, {-0.8314695954322815f, 0.5555702447891235f}, {-0.7730104327201843f, 0.6343932747840881f},
+    {-0.7071067690849304f, 0.7071067690849304f}, {-0.6343932747840881f, 0.7730104327201843f}, {-0.5555702447891235f, 0.8314695954322815f}, {-0.4713967442512512f, 0.8819212913513184f},
+    {-0.3826834261417389f, 0.9238795042037964f}, {-0.290284663438797f, 0.9569403529167175f}, {-0.19509032368659973f, 0.9807852506637573f}, {-0.0980171412229538f, 0.9951847195625305f},
+    {0.0f, 1.0f}, {0.0980171412229538f, 0.9951847195625305f}, {0.19509032368659973f, 0.9807852506637573f}, {0.290284663438797f, 0.9569403529167175f},
+    {0.3826834261417389f, 0.9238795042037964f}, {0.4713967442512512f, 0.8819212913513184f}, {0.5555702447891235f, 0.8314695954322815f}, {0.6343932747840881f, 0.7730104327201843f},
+    {0.7071067690849304f, 0.7071067690849304f}, {0.7730104327201843f, 0.6343932747840881f}, {0.8314695954322815f, 0.5555702447891235f}, {0.8819212913513184f, 0.4713967442512512f},
+    {0.9238795042037964f, 0.3826834261417389f}, {0.9569403529167175f, 0.290284663438797f}, {0.9807852506637573f, 0.19509032368659973f}, {0.9951847195625305f, 0.0980171412229538f}};
+
+// 64-point forward DFT in registers, natural order in and out; HALF_IN: the
+// inputs from 32 on are zero; HALF_OUT: only the outputs below 32 are used.
+template <bool HALF_IN, bool HALF_OUT>
+__device__ __forceinline__ void dft64(float2 (&v)[64]) {
+    float2 A[4][16];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2)
+#pragma unroll
+        for (int n1 = 0; n1 < 16; ++n1)
+            A[n2][n1] = (HALF_IN && 4 * n1 + n2 >= 32) ? make_float2(0.0f, 0.0f) : v[4 * n1 + n2];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft16(A[n2]);
+#pragma unroll
+    for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+        for (int k1 = 1; k1 < 16; ++k1) {
+            const int j = n2 * k1;
+            A[n2][k1] = cmul(A[n2][k1], make_float2(kW64[j][0], kW64[j][1]));
+        }
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) {
+        float2 a = A[0][k1], b = A[1][k1], c = A[2][k1], d = A[3][k1];
+        dft4(a, b, c, d);
+        v[k1] = a;
+        v[k1 + 16] = b;
+        if (!HALF_OUT) {
+            v[k1 + 32] = c;
+            v[k1 + 48] = d;
+        }
+    }
+}
+
+// One length-4096 forward DFT of the wavefront's data in four steps (see
+// above): v[b] of lane a holds x[a + 64 b] on entry and X[a + 64 b] on exit.
+template <bool HALF_IN, bool HALF_OUT>
+__device__ __forceinline__ void dft4096_wave(float2 (&v)[64], float2* T, const float2* __restrict__ tw,
+                                             int lane) {
+    constexpr int TP = 65;                         // LDS row pitch (float2): rows spread over the banks
+    dft64<HALF_IN, false>(v);
+    // twiddles w^(a c), a = lane (requested together, then applied)
+#pragma unroll
+    for (int c0 = 0; c0 < 64; c0 += 16) {
+        float2 w[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) w[c] = tw[(lane * (c0 + c)) & 4095];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) v[c0 + c] = cmul(v[c0 + c], w[c]);
+    }
+    // transpose: lane a writes row a, then lane c reads column c
+#pragma unroll
+    for (int c = 0; c < 64; ++c) T[lane * TP + c] = v[c];
+    transform_sync<64>();
+#pragma unroll
+    for (int a = 0; a < 64; ++a) v[a] = T[a * TP + lane];
+    transform_sync<64>();
+    dft64<false, HALF_OUT>(v);
+}
+
+template <int STORE>
+__global__ __launch_bounds__(64) void k_filter4096(FilterArgs a) {
+    using S = Store<STORE>;
+    constexpr int ES = (int)sizeof(typename S::T);
+    __shared__ float2 T[64 * 65];
+    const int lane = threadIdx.x;
+    const int hp = (a.nv + 1) >> 1;
+    const int pair = blockIdx.x;
+    const int pp = pair / hp, kk = pair - pp * hp;
+    const int r0 = pp * a.nv + 2 * kk, r1 = r0 + 1;
+    const bool has0 = r0 < a.rows, has1 = has0 && 2 * kk + 1 < a.nv;
+    const int n = a.n;
+    const float rr = a.r * a.r;
+    const float b0 = has0 ? (float)(a.v0 + r0 % a.nv) - a.c : 0.0f;
+    const float b1 = has1 ? (float)(a.v0 + r1 % a.nv) - a.c : 0.0f;
+    const float rb0 = rr + b0 * b0, rb1 = rr + b1 * b1;
+    auto weight = [&](int u, float rb) {
+        const float au = (float)u - a.c;
+        return a.r * __builtin_amdgcn_rsqf(rb + au * au);
+    };
+    const int u0r = __builtin_amdgcn_readfirstlane(has0 ? r0 : 0);
+    const int u1r = __builtin_amdgcn_readfirstlane(has1 ? r1 : 0);
+    const __amdgpu_buffer_rsrc_t rs0 = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(a.proj + (size_t)u0r * n), (short)0, __builtin_amdgcn_readfirstlane(has0 ? n * 4 : 0), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rs1 = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(a.proj + (size_t)u1r * n), (short)0, __builtin_amdgcn_readfirstlane(has1 ? n * 4 : 0), 0x00020000);
+    // pre-weighted rows p~[u], u = lane + 64 b < 2048 (zero from n on: past
+    // the row the buffer reads zero), then their first difference: p~[u-1]
+    // is the previous lane's (a DPP shift), for lane 0 lane 63's of b - 1
+    float2 v[64];
+    float q0[32], q1[32];
+#pragma unroll
+    for (int b = 0; b < 32; ++b) {
+        q0[b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs0, (lane + 64 * b) * 4, 0, 0));
+        q1[b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs1, (lane + 64 * b) * 4, 0, 0));
+    }
+    float prev0 = 0.0f, prev1 = 0.0f;              // p~ of lane 63 at b - 1
+#pragma unroll
+    for (int b = 0; b < 32; ++b) {
+        const int u = lane + 64 * b;
+        const float t0 = u < n ? q0[b] * weight(u, rb0) : 0.0f;
+        const float t1 = u < n ? q1[b] * weight(u, rb1) : 0.0f;
+        float s0 = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t0), 0x138 /* wave_shr:1 */, 0xf, 0xf, false));
+        float s1 = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t1), 0x138 /* wave_shr:1 */, 0xf, 0xf, false));
+        if (lane == 0) {
+            s0 = prev0;
+            s1 = prev1;
+        }
+        prev0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t0), 63));
+        prev1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t1), 63));
+        v[b] = u < n ? make_float2(t0 - s0, t1 - s1) : make_float2(0.0f, 0.0f);
+    }
+#pragma unroll
+    for (int b = 32; b < 64; ++b) v[b] = make_float2(0.0f, 0.0f);
+    const float last0 = has0 ? a.proj[(size_t)u0r * n + n - 1] * weight(n - 1, rb0) : 0.0f;
+    const float last1 = has1 ? a.proj[(size_t)u1r * n + n - 1] * weight(n - 1, rb1) : 0.0f;
+    dft4096_wave<true, false>(v, T, a.twiddle, lane);
+    // conj(X G): X[lane + 64 d] in v[d]
+#pragma unroll
+    for (int d0 = 0; d0 < 64; d0 += 16) {
+        float2 g[16];
+#pragma unroll
+        for (int d = 0; d < 16; ++d) g[d] = a.resp[lane + 64 * (d0 + d)];
+#pragma unroll
+        for (int d = 0; d < 16; ++d) {
+            const float2 x = cmul(v[d0 + d], g[d]);
+            v[d0 + d] = make_float2(x.x, -x.y);
+        }
+    }
+    dft4096_wave<false, true>(v, T, a.twiddle, lane);
+    // the result is conj(v): row 0 its real part, row 1 its imaginary part
+    float gt[32];
+#pragma unroll
+    for (int f = 0; f < 32; ++f) {
+        const int u = lane + 64 * f;
+        gt[f] = u < n ? a.gtail[u] : 0.0f;
+    }
+    typename S::T* out = (typename S::T*)a.out;
+    const __amdgpu_buffer_rsrc_t ro0 = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(out + (size_t)u0r * n), (short)0, __builtin_amdgcn_readfirstlane(has0 ? n * ES : 0), 0x00020000);
+    const __amdgpu_buffer_rsrc_t ro1 = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(out + (size_t)u1r * n), (short)0, __builtin_amdgcn_readfirstlane(has1 ? n * ES : 0), 0x00020000);
+#pragma unroll
+    for (int f = 0; f < 32; ++f) {
+        const int u = lane + 64 * f;
+        if (u < n) {
+            S::put_raw(ro0, u * ES, v[f].x - last0 * gt[f]);
+            S::put_raw(ro1, u * ES, -v[f].y - last1 * gt[f]);
+        }
+    }
+}
+
 template <int LOGM>
 static hipError_t launch_filter_m(const FilterArgs& a, int store, hipStream_t st) {
     constexpr int TP = FilterShape<LOGM>::TP;
@@ -375,7 +560,16 @@ hipError_t launch_filter(const FilterArgs& a, int logm, int store, hipStream_t s
         case 9: return launch_filter_m<9>(a, store, st);
         case 10: return launch_filter_m<10>(a, store, st);
         case 11: return launch_filter_m<11>(a, store, st);
-        case 12: return launch_filter_m<12>(a, store, st);
+        case 12: {
+            // the four-step form: one row pair per 64-thread workgroup
+            const dim3 grid((a.rows / a.nv) * ((a.nv + 1) / 2));
+            switch (store) {
+                case 0: hipLaunchKernelGGL((k_filter4096<0>), grid, dim3(64), 0, st, a); break;
+                case 1: hipLaunchKernelGGL((k_filter4096<1>), grid, dim3(64), 0, st, a); break;
+                default: hipLaunchKernelGGL((k_filter4096<2>), grid, dim3(64), 0, st, a); break;
+            }
+            return hipGetLastError();
+        }
         case 13: return launch_filter_m<13>(a, store, st);
         default: return hipErrorInvalidValue;
     }
