@@ -486,7 +486,7 @@ def kernel_rooflines(wl, s, k, store, res):
                 "traffic": measured_traffic(kernel, wl, s, k, store)}
 
     out = {
-        "filter": hbm("k_filter", "filter", n * n * p * (4 + bs),
+        "filter": hbm("k_filter4096" if plan.info.fft_len == 4096 else "k_filter", "filter", n * n * p * (4 + bs),
                       "projections read once (FP32) + filtered rows written once (store type)"),
         "decompose": hbm("k_decimate_staged" if plan.get_tuning()["decim_chunks"] == 0 else "k_decimate",
                          "decompose", n * n * p * bs + ws_bytes,
