@@ -63,8 +63,10 @@ def test_bounds_match_oracle_and_cover(n, p, r, s, k):
 
 # --------------------------------------------------------------------- filter
 
+# N = 1025..2048 takes the four-step 4096-point form (1025: the fewest
+# samples per lane; 1100: a ragged last register of samples)
 @pytest.mark.parametrize("n,p,r", [(64, 90, 512.0), (50, 7, 80.0), (33, 5, 40.0), (512, 4, 2048.0),
-                                   (2000, 2, 8000.0)])
+                                   (2000, 2, 8000.0), (1025, 2, 4100.0), (1100, 3, 4400.0)])
 def test_filter_matches_oracle(n, p, r):
     log(f"filter n={n} p={p}")
     proj = scan(n, p, r, 8, 21)
