@@ -137,6 +137,33 @@ def interior_mask(ell, n, margin=3.0, min_density=0.2, step=2):
     return sl, same
 
 
+def ratio_map(v, ref, n, grid=16, band=8):
+    """The E4 picture in numbers: FDK-OD / direct FDK on the central slice,
+    averaged over grid x grid blocks of voxels where direct FDK is at least a
+    fifth of its largest magnitude (None elsewhere), and the two
+    reconstructions along the central row, every n // 64 voxels, averaged
+    over `band` rows."""
+    mid = n // 2
+    a, b = v[mid], ref[mid]
+    keep = np.abs(b) >= 0.2 * np.abs(b).max()
+    bs = n // grid
+    out = []
+    for i in range(grid):
+        row = []
+        for j in range(grid):
+            blk = (slice(i * bs, (i + 1) * bs), slice(j * bs, (j + 1) * bs))
+            kk = keep[blk]
+            row.append(round(float((a[blk][kk] / b[blk][kk]).mean()), 4) if kk.sum() >= bs else None)
+        out.append(row)
+    step = max(n // 64, 1)
+    rows = slice(mid - band // 2, mid + band // 2)
+    prof_od = a[rows].mean(axis=0)[::step]
+    prof_fdk = b[rows].mean(axis=0)[::step]
+    return {"ratio_blocks": out, "block_voxels": bs,
+            "profile_step": step, "profile_fdkod": [round(float(x), 5) for x in prof_od],
+            "profile_fdk": [round(float(x), 5) for x in prof_fdk]}
+
+
 def rel_rmse(a, b):
     return float(np.sqrt(np.mean((a - b) ** 2) / np.mean(b ** 2)))
 
@@ -220,7 +247,8 @@ def quality_sweep(torch, pkg, n, p, r, smax):
                "rel_rmse_vs_fdk": rel_rmse(v, ref_np),
                "interior_ratio_mean": float(ratio.mean()), "interior_ratio_std": float(ratio.std()),
                "interior_ratio_p01": float(np.percentile(ratio, 1)),
-               "interior_ratio_p99": float(np.percentile(ratio, 99)), **edge}
+               "interior_ratio_p99": float(np.percentile(ratio, 99)), **edge,
+               "e4_central_slice": ratio_map(v, ref_np, n)}
         log(f"[study] s={s} k={k} {rw} rows: rel-RMSE {row['rel_rmse_vs_fdk']:.4f}, interior ratio "
             f"{row['interior_ratio_mean']:.4f} +- {row['interior_ratio_std']:.4f}, MTF50 {edge['mtf50']:.3f} "
             f"MTF10 {edge['mtf10']:.3f}, 10-90 {edge['width_10_90']:.2f}")
@@ -399,12 +427,14 @@ class SlabScans:
         self.direct.close()
 
 
-def train_learned_slabs(torch, pkg, scans, steps, lr, seed0, rng_seed=7, log_every=64, positions=None):
+def train_learned_slabs(torch, pkg, scans, steps, lr, seed0, rng_seed=7, log_every=64, positions=None,
+                        lr_end=None):
     """AdamW on one slab per step (phantom seed0 + step, slab position drawn
     with rng_seed from ``positions``, default every position), each slab's
-    squared error weighted by the inverse of its target's energy; returns the
-    trained LearnedDecimation and the training time split (ms of library
-    kernels per step, seconds of data generation)."""
+    squared error weighted by the inverse of its target's energy; with
+    lr_end, the step size falls from lr to lr_end along a half cosine.
+    Returns the trained LearnedDecimation and the training time split (ms of
+    library kernels per step, seconds of data generation)."""
     net = pkg.LearnedDecimation("cuda:0", seed=0, lr=lr)
     rng = np.random.default_rng(rng_seed)
     t_gen = t_train = 0.0
@@ -421,6 +451,8 @@ def train_learned_slabs(torch, pkg, scans, steps, lr, seed0, rng_seed=7, log_eve
         w = 1.0 / e
         torch.cuda.synchronize()
         t1 = time.time()
+        if lr_end is not None:
+            net.lr = lr_end + 0.5 * (lr - lr_end) * (1.0 + math.cos(math.pi * it / max(steps - 1, 1)))
         net.train_step_slab(scans.plan, fb, v0, scans.ws(nr), z0, scans.vol, scans.tgt, scans.resid,
                             scans.dws(nr), weight=w)
         torch.cuda.synchronize()
@@ -475,7 +507,7 @@ def load_learned_c5(pkg, path=LEARNED_C5_WEIGHTS, device="cuda:0"):
     return net
 
 
-def learned_c5(torch, pkg, steps=512, lr=1e-3, nzs=32, held=16, out_path=LEARNED_C5_WEIGHTS):
+def learned_c5(torch, pkg, steps=512, lr=1e-3, nzs=32, held=16, out_path=LEARNED_C5_WEIGHTS, lr_end=None):
     """The learned decimation at the N = 2000, P = 720, s = 4 workload (D = 16,
     dilation 4): trained on ``steps`` seeded 30-ellipsoid phantoms (seeds
     5000 + i), one slab of nzs slices each, and compared on ``held`` other
@@ -491,7 +523,8 @@ def learned_c5(torch, pkg, steps=512, lr=1e-3, nzs=32, held=16, out_path=LEARNED
     # position diverged at lr 2e-3)
     nzv = wl.nz or wl.n
     central = [z for z in scans.zs if abs(z + nzs / 2 - nzv / 2) < nzv / 4]
-    net, timing = train_learned_slabs(torch, pkg, scans, steps, lr, 5000, positions=central, log_every=32)
+    net, timing = train_learned_slabs(torch, pkg, scans, steps, lr, 5000, positions=central, log_every=32,
+                                      lr_end=lr_end)
     # held-out slabs spread over the central three quarters of the volume
     lo, hi = (wl.nz or wl.n) // 8, (wl.nz or wl.n) - (wl.nz or wl.n) // 8 - nzs
     positions = [z for z in (int(x) // 32 * 32 for x in np.linspace(lo, hi, held))]
@@ -501,13 +534,14 @@ def learned_c5(torch, pkg, steps=512, lr=1e-3, nzs=32, held=16, out_path=LEARNED
     w = net.master.detach().cpu().double().numpy()
     with open(out_path, "w") as f:
         f.write("# learned decimation filter for N = 2000, P = 720, R = 8000, s = 4 (D = 16): 817 FP32 master\n"
-                f"# weights (W1 [16][5][5], b1 [16], W2 [16][5][5], b2), AdamW lr {lr}, {steps} slabs of "
+                f"# weights (W1 [16][5][5], b1 [16], W2 [16][5][5], b2), AdamW lr {lr}"
+                + (f" falling to {lr_end} (half cosine)" if lr_end is not None else "") + f", {steps} slabs of "
                 f"{nzs} slices; written by study.py --learned-c5\n")
         for x in w:
             f.write(f"{x:.9e}\n")
     scans.close()
     return {"n": wl.n, "p": wl.p, "r": wl.r, "s": 4, "d": 16, "slab_slices": nzs, "train_phantoms": steps,
-            "held_out_phantoms": held, "lr": lr, "train_slices": [central[0], central[-1] + nzs],
+            "held_out_phantoms": held, "lr": lr, "lr_end": lr_end, "train_slices": [central[0], central[-1] + nzs],
             "timing": timing, "held_out": res,
             "weights_file": os.path.relpath(os.path.abspath(out_path), ROOT)}
 
@@ -521,6 +555,7 @@ def main():
     ap.add_argument("--c5-steps", type=int, default=512)
     ap.add_argument("--c5-lr", type=float, default=1e-3)
     ap.add_argument("--c5-out", default=LEARNED_C5_WEIGHTS, help="where the trained weights are written")
+    ap.add_argument("--c5-lr-end", type=float, default=None, help="final step size (half-cosine decay)")
     args = ap.parse_args()
     import torch
 
@@ -528,7 +563,8 @@ def main():
 
     t0 = time.time()
     if args.learned_c5:
-        res = learned_c5(torch, pkg, steps=args.c5_steps, lr=args.c5_lr, out_path=args.c5_out)
+        res = learned_c5(torch, pkg, steps=args.c5_steps, lr=args.c5_lr, out_path=args.c5_out,
+                         lr_end=args.c5_lr_end)
         print(json.dumps({"study": "learned decimation at N = 2000, P = 720, s = 4 on one MI355X",
                           "data": "synthetic", "learned_c5": res, "seconds": round(time.time() - t0, 1)}),
               flush=True)

@@ -66,3 +66,18 @@ def test_interior_mask_of_a_sphere():
     # the axis-aligned +-3 probes stay inside for every point within 8 - 3 of the centre
     assert np.all(mask[rad <= 5.0])
     assert not np.any(mask[rad > 8.0])
+
+
+def test_ratio_map_blocks_and_profiles():
+    """E4 ratio map: a volume that is 1.02 times the reference reads 1.02 in
+    every block where the reference is large, None where it is small; the
+    profiles are the band-averaged central rows, subsampled."""
+    n = 64
+    ref = np.zeros((n, n, n))
+    ref[:, 16:48, 16:48] = 2.0
+    v = 1.02 * ref
+    m = study.ratio_map(v, ref, n, grid=8, band=4)
+    blocks = np.array([[np.nan if x is None else x for x in row] for row in m["ratio_blocks"]])
+    assert np.allclose(blocks[2:6, 2:6], 1.02) and np.isnan(blocks[0, 0]) and np.isnan(blocks[7, 7])
+    assert m["profile_step"] == 1 and len(m["profile_fdk"]) == n
+    assert m["profile_fdk"][32] == 2.0 and m["profile_fdkod"][32] == 2.04 and m["profile_fdk"][0] == 0.0
