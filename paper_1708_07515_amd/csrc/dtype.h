@@ -56,12 +56,14 @@ template <> struct Store<2> {
     static __device__ __forceinline__ float load(const T* p, size_t i) {
         return __uint_as_float(((uint32_t)p[i]) << 16);
     }
+    // round to nearest even; a NaN stays a (quiet) NaN.  Written as a select,
+    // not a branch: a branch here splits the caller's arithmetic into blocks
+    // and changes which of its multiplies and adds are fused
     static __device__ __forceinline__ uint16_t enc(float v) {
-        uint32_t b = __float_as_uint(v);
-        if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu))
-            return (uint16_t)((b >> 16) | 0x40u);     // quiet NaN
-        b += 0x7FFFu + ((b >> 16) & 1u);              // round to nearest even
-        return (uint16_t)(b >> 16);
+        const uint32_t b = __float_as_uint(v);
+        const uint32_t rne = (b + 0x7FFFu + ((b >> 16) & 1u)) >> 16;
+        const uint32_t qnan = (b >> 16) | 0x40u;
+        return (uint16_t)(v != v ? qnan : rne);
     }
     static __device__ __forceinline__ void put(T* p, size_t i, float v) { p[i] = enc(v); }
     static __device__ __forceinline__ float raw(__amdgpu_buffer_rsrc_t r, int off) {

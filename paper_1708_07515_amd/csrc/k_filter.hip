@@ -470,8 +470,10 @@ __global__ __launch_bounds__(64) void k_filter4096(FilterArgs a) {
     const __amdgpu_buffer_rsrc_t rs1 = __builtin_amdgcn_make_buffer_rsrc(
         (void*)(a.proj + (size_t)u1r * n), (short)0, __builtin_amdgcn_readfirstlane(has1 ? n * 4 : 0), 0x00020000);
     // pre-weighted rows p~[u], u = lane + 64 b < 2048 (zero from n on: past
-    // the row the buffer reads zero), then their first difference: p~[u-1]
-    // is the previous lane's (a DPP shift), for lane 0 lane 63's of b - 1
+    // the row the buffer reads zero, and the weight is finite, so no lane is
+    // masked off), then their first difference: p~[u-1] is the previous
+    // lane's (a DPP rotation of the wave by one lane), for lane 0 lane 63's of
+    // b - 1 (the previous register's rotation, held in lane 0)
     float2 v[64];
     float q0[32], q1[32];
 #pragma unroll
@@ -479,21 +481,22 @@ __global__ __launch_bounds__(64) void k_filter4096(FilterArgs a) {
         q0[b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs0, (lane + 64 * b) * 4, 0, 0));
         q1[b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs1, (lane + 64 * b) * 4, 0, 0));
     }
-    float prev0 = 0.0f, prev1 = 0.0f;              // p~ of lane 63 at b - 1
+    const bool lane0 = lane == 0;
+    float rot0 = 0.0f, rot1 = 0.0f;                // rotation of b - 1 (p~[-1] = 0 for b = 0)
 #pragma unroll
     for (int b = 0; b < 32; ++b) {
         const int u = lane + 64 * b;
-        const float t0 = u < n ? q0[b] * weight(u, rb0) : 0.0f;
-        const float t1 = u < n ? q1[b] * weight(u, rb1) : 0.0f;
-        float s0 = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t0), 0x138 /* wave_shr:1 */, 0xf, 0xf, false));
-        float s1 = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t1), 0x138 /* wave_shr:1 */, 0xf, 0xf, false));
-        if (lane == 0) {
-            s0 = prev0;
-            s1 = prev1;
-        }
-        prev0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t0), 63));
-        prev1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t1), 63));
-        v[b] = u < n ? make_float2(t0 - s0, t1 - s1) : make_float2(0.0f, 0.0f);
+        const float t0 = q0[b] * weight(u, rb0);
+        const float t1 = q1[b] * weight(u, rb1);
+        const float r0 = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t0), 0x13C /* wave_ror:1 */, 0xf, 0xf, false));
+        const float r1 = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t1), 0x13C /* wave_ror:1 */, 0xf, 0xf, false));
+        const float s0 = lane0 ? rot0 : r0;
+        const float s1 = lane0 ? rot1 : r1;
+        rot0 = r0;
+        rot1 = r1;
+        const bool in = u < n;
+        v[b].x = in ? t0 - s0 : 0.0f;
+        v[b].y = in ? t1 - s1 : 0.0f;
     }
 #pragma unroll
     for (int b = 32; b < 64; ++b) v[b] = make_float2(0.0f, 0.0f);
@@ -513,13 +516,16 @@ __global__ __launch_bounds__(64) void k_filter4096(FilterArgs a) {
         }
     }
     dft4096_wave<false, true>(v, T, a.twiddle, lane);
-    // the result is conj(v): row 0 its real part, row 1 its imaginary part
+    // the result is conj(v): row 0 its real part, row 1 its imaginary part.
+    // The tail table and the rows go through buffer resources of n samples:
+    // from n on the table reads zero and the stores are dropped, so no lane
+    // is masked off.
+    const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)a.gtail, (short)0, n * 4, 0x00020000);
     float gt[32];
 #pragma unroll
-    for (int f = 0; f < 32; ++f) {
-        const int u = lane + 64 * f;
-        gt[f] = u < n ? a.gtail[u] : 0.0f;
-    }
+    for (int f = 0; f < 32; ++f)
+        gt[f] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rg, (lane + 64 * f) * 4, 0, 0));
     typename S::T* out = (typename S::T*)a.out;
     const __amdgpu_buffer_rsrc_t ro0 = __builtin_amdgcn_make_buffer_rsrc(
         (void*)(out + (size_t)u0r * n), (short)0, __builtin_amdgcn_readfirstlane(has0 ? n * ES : 0), 0x00020000);
@@ -528,10 +534,8 @@ __global__ __launch_bounds__(64) void k_filter4096(FilterArgs a) {
 #pragma unroll
     for (int f = 0; f < 32; ++f) {
         const int u = lane + 64 * f;
-        if (u < n) {
-            S::put_raw(ro0, u * ES, v[f].x - last0 * gt[f]);
-            S::put_raw(ro1, u * ES, -v[f].y - last1 * gt[f]);
-        }
+        S::put_raw(ro0, u * ES, v[f].x - last0 * gt[f]);
+        S::put_raw(ro1, u * ES, -v[f].y - last1 * gt[f]);
     }
 }
 

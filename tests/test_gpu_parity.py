@@ -89,6 +89,27 @@ def test_filter_matches_oracle(n, p, r):
     assert err <= bound and mxr <= 4 * bound
 
 
+@pytest.mark.parametrize("n,p,r", [(64, 3, 512.0), (512, 4, 2048.0), (1100, 3, 4400.0), (2000, 2, 8000.0)])
+def test_half_storage_filter_is_the_rounded_fp32_filter(n, p, r):
+    """The storage type changes only the filter's final store: the FP16 and
+    BF16 rows are the FP32 rows rounded to nearest even, bit for bit (both
+    the radix-16 and the four-step 4096-point forms)."""
+    proj = scan(n, p, r, 8, 21).to(DEV)
+    out = {}
+    for store in ("f32", "f16", "bf16"):
+        with pkg.Plan(n, p, r, s=0, store=store) as plan:
+            f = plan.empty_filtered()
+            plan.filter(proj, f)
+            torch.cuda.synchronize()
+            out[store] = f
+    for store, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
+        want = out["f32"].to(dt).view(torch.int16)
+        got = out[store].view(torch.int16)
+        bad = int((got != want).sum())
+        log(f"filter n={n} {store}: {bad} of {got.numel()} samples differ from the rounded FP32 rows")
+        assert bad == 0
+
+
 # ------------------------------------------------------------ reconstruction
 
 def test_direct_fdk_c1_full_volume():
