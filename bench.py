@@ -727,11 +727,15 @@ def main():
         del sres
         torch.cuda.empty_cache()
 
-    batch = None
+    batch = batch_small = None
     if not args.no_batch:
         batch = run_batch(torch, pkg, configs.C4, 3)
         log(f"[bench] batch: {batch['ms_per_run_graph']} ms per graph replay, "
             f"{batch['ms_one_plan_at_a_time']} ms one plan at a time")
+        torch.cuda.empty_cache()
+        batch_small = run_batch(torch, pkg, configs.C4S, 10)
+        log(f"[bench] small batch: {batch_small['ms_per_run_graph']} ms per graph replay, "
+            f"{batch_small['ms_one_plan_at_a_time']} ms one plan at a time")
         torch.cuda.empty_cache()
 
     out = {
@@ -766,6 +770,7 @@ def main():
         "streamed": streamed,
         "small_workload": small,
         "batch_workload": batch,
+        "batch_small_workload": batch_small,
         "copy_peak": copy_peak,
     }
     print(json.dumps(out), flush=True)

@@ -233,10 +233,13 @@ fdkod_status fdkod_choose_s(const fdkod_params* prm, int32_t s_max, double c1_ms
 
 /* ------------------------------------------------------------------ batches
  * Many volumes of different sizes reconstructed together (the decomposition of
- * Sec. 2.1 applied to every volume): one grouped decimation launch over all
- * volumes' (square, row) tasks and one persistent backprojection launch whose
- * workgroups take (volume, square, 16 x 16 tile, slab) items from a ticket
- * queue, largest first.  The launch sequence can be captured in a hipGraph. */
+ * Sec. 2.1 applied to every volume): one bounds launch over all volumes'
+ * squares, one filter launch per FFT length over the volumes too small to fill
+ * the GPU alone (larger ones keep a launch each), one grouped decimation launch
+ * over all volumes' (square, row) tasks and one persistent backprojection
+ * launch whose workgroups take (volume, square, 16 x 16 tile, slab) items from
+ * a ticket queue, largest first.  The launch sequence can be captured in a
+ * hipGraph. */
 typedef struct fdkod_batch_s* fdkod_batch_t;
 
 /* Create a batch of `count` plans (1..4096) on `device`; every plan is
@@ -256,7 +259,7 @@ fdkod_status fdkod_batch_plan(fdkod_batch_t batch, int32_t index, fdkod_plan_t* 
 fdkod_status fdkod_batch_bind(fdkod_batch_t batch, const float* const* proj, void* const* filt,
                               void* const* ws, float* const* vol);
 
-/* Enqueue bounds and filtering of every volume, the grouped decimation and the
+/* Enqueue the grouped bounds and filters, the grouped decimation and the
  * persistent backprojection on `stream`.  Asynchronous, allocates nothing;
  * capture-safe (the ticket counter is cleared by a kernel, not a memset). */
 fdkod_status fdkod_batch_run(fdkod_batch_t batch, fdkod_stream_t stream);

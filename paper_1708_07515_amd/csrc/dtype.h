@@ -103,6 +103,34 @@ __device__ __forceinline__ T uniform_load(const T* p) {
     return out;
 }
 
+// A table that no kernel writes while it runs, read at a lane-uniform
+// address through the constant address space: scalar loads into scalar
+// registers (through the generic address space the compiler cannot rule out
+// a write, and issues vector loads that each wait on memory).
+template <class T>
+__device__ __forceinline__ T const_load(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "whole 32-bit words");
+    typedef const __attribute__((address_space(4))) int* cword;
+    const cword src = (cword)(p);
+    T out;
+    int* dst = (int*)&out;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = src[i];
+    return out;
+}
+
+// The volume v with start[v] <= b < start[v + 1] (start ascending, nvol >= 1,
+// a read-only table; b lane-uniform): a binary search in scalar registers.
+__device__ __forceinline__ int batch_volume(const int* start, int nvol, int b) {
+    int lo = 0, hi = nvol - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (const_load(start + mid) <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Wait for every outstanding vector memory access of the wave (s_waitcnt
 // vmcnt(0) on gfx9 encodings; expcnt and lgkmcnt left at their maxima).  A
 // kernel places it where every load it issued has been consumed, on every

@@ -1,11 +1,14 @@
 // Batches of uneven volumes (C ABI in include/fdkod.h): every volume keeps its
-// own plan (squares, bounds, schedule); the decimation of all volumes runs as
-// one grouped launch and the backprojection as one persistent launch that
-// takes (volume, square, tile, slab) items from a ticket queue, largest first.
+// own plan (squares, bounds, schedule); the bounds of all volumes run as one
+// launch, the filters as one launch per FFT length (volumes that fill the GPU
+// alone keep their own), the decimation as one grouped launch and the
+// backprojection as one persistent launch that takes (volume, square, tile,
+// slab) items from a ticket queue, largest first.
 // The launch sequence is capture-safe and can be replayed as a hipGraph.
 #include <algorithm>
 #include <cstring>
 #include <numeric>
+#include <utility>
 #include <vector>
 
 #include "fdkod.h"
@@ -31,6 +34,21 @@ struct fdkod_batch_s {
     int2* d_block_vol = nullptr;
     int block_vol_cap = 0;
     unsigned* d_counter = nullptr;
+    // bounds of every volume in one launch, filters in one launch per FFT
+    // length (volumes grouped by length; per-volume arguments and workgroup
+    // ranges, written when the buffers are bound)
+    struct FilterGroup {
+        int logm, nvol, workgroups;
+        const FilterArgs* args;
+        const int* start;
+    };
+    std::vector<FilterGroup> fgroups;
+    std::vector<std::pair<FilterArgs, int>> fown;   // (arguments, log2 M) of volumes with a launch of their own
+    FilterArgs* d_fargs = nullptr;
+    int* d_fstart = nullptr;
+    BoundsArgs* d_bargs = nullptr;
+    int* d_bstart = nullptr;
+    int bounds_wg = 0;
     std::vector<void*> allocs;
     // bound buffers
     bool bound = false;
@@ -163,6 +181,86 @@ fdkod_status upload_tables(fdkod_batch_t b) {
         HIP_TRY(hipMemcpy(b->d_block_vol, block_vol.data(), sizeof(int2) * block_vol.size(), hipMemcpyHostToDevice),
                 "hipMemcpy workgroup table");
     }
+    return FDKOD_OK;
+}
+
+// A volume whose filter alone has this many workgroups fills the GPU and
+// keeps a launch of its own (the grouped kernels of the larger lengths spill
+// registers to scratch; the single-volume ones do not).
+constexpr int kFilterOwnLaunch = 8192;
+
+// The bounds and filter tables of the bound buffers (sizes depend only on
+// the volumes: allocated at the first binding).
+fdkod_status upload_front_tables(fdkod_batch_t b) {
+    const int n = b->count;
+    fdkod_status st;
+    if (!b->d_fargs) {
+        if ((st = dev_alloc(b->allocs, (void**)&b->d_fargs, sizeof(FilterArgs) * n)) != FDKOD_OK) return st;
+        if ((st = dev_alloc(b->allocs, (void**)&b->d_fstart, sizeof(int) * 2 * n)) != FDKOD_OK) return st;
+        if ((st = dev_alloc(b->allocs, (void**)&b->d_bargs, sizeof(BoundsArgs) * n)) != FDKOD_OK) return st;
+        if ((st = dev_alloc(b->allocs, (void**)&b->d_bstart, sizeof(int) * (n + 1))) != FDKOD_OK) return st;
+    }
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return b->plans[x]->logm < b->plans[y]->logm; });
+    std::vector<FilterArgs> fargs;
+    std::vector<int> fstart;
+    b->fgroups.clear();
+    b->fown.clear();
+    for (int i = 0; i < n;) {
+        const int logm = b->plans[order[i]]->logm;
+        fdkod_batch_s::FilterGroup g{logm, 0, 0, b->d_fargs + fargs.size(), b->d_fstart + fstart.size()};
+        int wg = 0;
+        for (; i < n && b->plans[order[i]]->logm == logm; ++i) {
+            const int v = order[i];
+            const FilterArgs fa = filter_args(b->plans[v], b->proj[v], b->filt[v], 0, b->plans[v]->n);
+            if (filter_workgroups(fa, logm) >= kFilterOwnLaunch) {
+                b->fown.emplace_back(fa, logm);
+                continue;
+            }
+            fargs.push_back(fa);
+            fstart.push_back(wg);
+            wg += filter_workgroups(fa, logm);
+            ++g.nvol;
+        }
+        if (g.nvol == 0) continue;
+        fstart.push_back(wg);
+        g.workgroups = wg;
+        b->fgroups.push_back(g);
+    }
+    std::vector<BoundsArgs> bargs(n);
+    std::vector<int> bstart(n + 1, 0);
+    for (int v = 0; v < n; ++v) {
+        bargs[v] = bounds_args(b->plans[v]);
+        bstart[v + 1] = bstart[v] + b->plans[v]->nsq;
+    }
+    b->bounds_wg = bstart[n];
+    if (!fargs.empty()) {
+        HIP_TRY(hipMemcpy(b->d_fargs, fargs.data(), sizeof(FilterArgs) * fargs.size(), hipMemcpyHostToDevice),
+                "hipMemcpy filter arguments");
+        HIP_TRY(hipMemcpy(b->d_fstart, fstart.data(), sizeof(int) * fstart.size(), hipMemcpyHostToDevice),
+                "hipMemcpy filter ranges");
+    }
+    HIP_TRY(hipMemcpy(b->d_bargs, bargs.data(), sizeof(BoundsArgs) * n, hipMemcpyHostToDevice),
+            "hipMemcpy bounds arguments");
+    HIP_TRY(hipMemcpy(b->d_bstart, bstart.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice),
+            "hipMemcpy bounds ranges");
+    return FDKOD_OK;
+}
+
+fdkod_status run_filters(fdkod_batch_t b, hipStream_t st) {
+    for (const auto& g : b->fgroups)
+        HIP_TRY(launch_filter_batch(FilterBatchArgs{g.args, g.start, g.nvol}, g.logm, b->store, g.workgroups, st),
+                "batched filter launch");
+    for (const auto& f : b->fown)
+        HIP_TRY(launch_filter(f.first, f.second, b->store, st), "filter kernel launch");
+    return FDKOD_OK;
+}
+
+fdkod_status run_bounds(fdkod_batch_t b, hipStream_t st) {
+    HIP_TRY(launch_bounds_batch(BoundsBatchArgs{b->d_bargs, b->d_bstart, b->count}, b->bounds_wg, st),
+            "batched bounds launch");
     return FDKOD_OK;
 }
 
@@ -304,6 +402,7 @@ fdkod_status fdkod_batch_bind(fdkod_batch_t b, const float* const* proj, void* c
     b->vol.assign(vol, vol + b->count);
     drop_graph(b);
     fdkod_status st = upload_tables(b);
+    if (st == FDKOD_OK) st = upload_front_tables(b);
     b->bound = st == FDKOD_OK;
     return st;
 }
@@ -313,10 +412,8 @@ fdkod_status fdkod_batch_run(fdkod_batch_t b, fdkod_stream_t stream) {
     if (!b->bound) return fail(FDKOD_E_STATE, "batch buffers are not bound");
     hipStream_t st = (hipStream_t)stream;
     fdkod_status r;
-    for (int i = 0; i < b->count; ++i) {
-        if ((r = fdkod_bounds(b->plans[i], stream)) != FDKOD_OK) return r;
-        if ((r = fdkod_filter(b->plans[i], b->proj[i], b->filt[i], stream)) != FDKOD_OK) return r;
-    }
+    if ((r = run_bounds(b, st)) != FDKOD_OK) return r;
+    if ((r = run_filters(b, st)) != FDKOD_OK) return r;
     if ((r = run_decimate(b, st)) != FDKOD_OK) return r;
     return run_backproject(b, st);
 }
@@ -354,8 +451,7 @@ fdkod_status fdkod_batch_tune(fdkod_batch_t b, fdkod_stream_t stream, fdkod_tuni
     hipStream_t st = (hipStream_t)stream;
     drop_graph(b);
     fdkod_status r;
-    for (int i = 0; i < b->count; ++i)
-        if ((r = fdkod_filter(b->plans[i], b->proj[i], b->filt[i], stream)) != FDKOD_OK) return r;
+    if ((r = run_filters(b, st)) != FDKOD_OK) return r;
     float dec_best = 0.0f;
     if (b->ndec > 0) {
         float best = 1e30f;

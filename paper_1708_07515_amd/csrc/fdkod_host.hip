@@ -306,6 +306,27 @@ fdkod_status enqueue_decimate(const fdkod_plan_s* pl, const void* filt, void* ws
     return FDKOD_OK;
 }
 
+BoundsArgs bounds_args(const fdkod_plan_s* pl) {
+    BoundsArgs a;
+    a.squares = pl->d_sq;
+    a.trig_p = pl->d_trig_p;
+    a.trig_m = pl->d_trig_m;
+    a.ac_p = pl->d_ac_p;
+    a.geo_m = pl->d_geo_m;
+    a.grid = pl->d_grid;
+    a.sched = pl->d_sched;
+    a.crop = pl->d_crop;
+    a.rscale = pl->d_rscale;
+    a.n = pl->n;
+    a.p = pl->p;
+    a.pd = pl->pd;
+    a.nsq = pl->nsq;
+    a.nsched = pl->nsched;
+    a.r = (float)pl->r;
+    a.cu = (float)((pl->n - 1) / 2.0);
+    return a;
+}
+
 FilterArgs filter_args(const fdkod_plan_s* pl, const float* proj, void* filt, int v0, int nv) {
     FilterArgs a;
     a.proj = proj;
@@ -812,24 +833,7 @@ fdkod_status fdkod_plan_info(fdkod_plan_t pl, fdkod_info* info) {
 
 fdkod_status fdkod_bounds(fdkod_plan_t pl, fdkod_stream_t stream) {
     if (!pl) return fail(FDKOD_E_ARG, "plan is NULL");
-    BoundsArgs a;
-    a.squares = pl->d_sq;
-    a.trig_p = pl->d_trig_p;
-    a.trig_m = pl->d_trig_m;
-    a.ac_p = pl->d_ac_p;
-    a.geo_m = pl->d_geo_m;
-    a.grid = pl->d_grid;
-    a.sched = pl->d_sched;
-    a.crop = pl->d_crop;
-    a.rscale = pl->d_rscale;
-    a.n = pl->n;
-    a.p = pl->p;
-    a.pd = pl->pd;
-    a.nsq = pl->nsq;
-    a.nsched = pl->nsched;
-    a.r = (float)pl->r;
-    a.cu = (float)((pl->n - 1) / 2.0);
-    HIP_TRY(launch_bounds(a, (hipStream_t)stream), "bounds kernel launch");
+    HIP_TRY(launch_bounds(bounds_args(pl), (hipStream_t)stream), "bounds kernel launch");
     return FDKOD_OK;
 }
 

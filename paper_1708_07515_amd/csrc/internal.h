@@ -89,6 +89,26 @@ struct DecimVol {
     const int2* sqoff;      // [nsq][nsched] crop offset - block's least, bits of the fraction (row-staged)
 };
 
+// Many volumes' filters or bounds in one launch: volume v owns the
+// workgroups [start[v], start[v + 1]) and runs them as its own launch would
+// (workgroup b - start[v]); all volumes of a filter launch share the FFT
+// length.
+struct FilterBatchArgs {
+    const FilterArgs* vols;     // [nvol]
+    const int* start;           // [nvol + 1]
+    int nvol;
+};
+struct BoundsBatchArgs {
+    const BoundsArgs* vols;     // [nvol]
+    const int* start;           // [nvol + 1]: the first square of each volume
+    int nvol;
+};
+
+// Threads per row pair of the radix-16 filter of length 2^logm.
+constexpr int filter_threads_per_pair(int logm) {
+    return (1 << logm) / 16 < 1 ? 1 : ((1 << logm) / 16 > 256 ? 256 : (1 << logm) / 16);
+}
+
 // Many volumes in one launch: volume b owns tasks [start_b, start_b + ntasks_b)
 // with start_b a multiple of 4, so a workgroup (4 waves) never spans two
 // volumes; block_vol[g] = (volume, start) of workgroup g's volume.
@@ -151,7 +171,11 @@ struct BpVariant {
 };
 
 hipError_t launch_bounds(const BoundsArgs& a, hipStream_t st);
+hipError_t launch_bounds_batch(const BoundsBatchArgs& a, int workgroups, hipStream_t st);
 hipError_t launch_filter(const FilterArgs& a, int logm, int store, hipStream_t st);
+// workgroups of one volume's filter launch
+int filter_workgroups(const FilterArgs& a, int logm);
+hipError_t launch_filter_batch(const FilterBatchArgs& a, int logm, int store, int workgroups, hipStream_t st);
 hipError_t launch_decimate(const DecimVol& a, int chunks, int store, hipStream_t st);
 // row-staged decimation (plain rows, triangle, linear shift): cpt 64-column
 // chunks per lane, segc 64-sample chunks per staged row segment

@@ -7,6 +7,7 @@
 // (origin u0 and width W) follows.  Per original angle p it writes a_c(beta_p),
 // the centre trajectory that the crop follows.
 #include "internal.h"
+#include "dtype.h"
 #include "geom.h"
 
 namespace fdkod {
@@ -25,9 +26,9 @@ __device__ __forceinline__ float wave_max(float v) {
     return v;
 }
 
-__global__ __launch_bounds__(256) void k_bounds(BoundsArgs a) {
+// Bounds, grid and crop table of square q (one 256-thread workgroup).
+__device__ __forceinline__ void bounds_square(const BoundsArgs& a, int q) {
     __shared__ float red[2][4];
-    const int q = blockIdx.x;
     const SquareDesc sq = a.squares[q];
     const float c = a.cu;
     // vertex offsets from the centre: corner voxel centres of the square
@@ -90,8 +91,23 @@ __global__ __launch_bounds__(256) void k_bounds(BoundsArgs a) {
     }
 }
 
+__global__ __launch_bounds__(256) void k_bounds(BoundsArgs a) { bounds_square(a, blockIdx.x); }
+
+// Many volumes: workgroup b is square b - start[v] of volume v.
+__global__ __launch_bounds__(256) void k_bounds_batch(BoundsBatchArgs ba) {
+    const int b = blockIdx.x;
+    const int v = batch_volume(ba.start, ba.nvol, b);
+    const BoundsArgs a = const_load(ba.vols + v);
+    bounds_square(a, b - const_load(ba.start + v));
+}
+
 hipError_t launch_bounds(const BoundsArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_bounds, dim3(a.nsq), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_bounds_batch(const BoundsBatchArgs& a, int workgroups, hipStream_t st) {
+    hipLaunchKernelGGL(k_bounds_batch, dim3(workgroups), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -203,13 +203,13 @@ __device__ __forceinline__ void fft_lds(float2* z, int t, const float2* __restri
 template <int LOGM>
 struct FilterShape {
     static constexpr int M = 1 << LOGM;
-    static constexpr int TP = M / 16 < 1 ? 1 : (M / 16 > 256 ? 256 : M / 16);
+    static constexpr int TP = filter_threads_per_pair(LOGM);
     static constexpr int WAVES = LOGM >= 13 ? 2 : (LOGM == 11 ? 3 : 4);
 };
 
+// Workgroup `block` of one volume's filter (row pairs block * PAIRS ...).
 template <int LOGM, int STORE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FilterShape<LOGM>::WAVES)))
-void k_filter(FilterArgs a) {
+__device__ __forceinline__ void filter_block(const FilterArgs& a, int block) {
     using S = Store<STORE>;
     constexpr int M = 1 << LOGM;
     constexpr int TP = FilterShape<LOGM>::TP;          // threads per row pair
@@ -223,7 +223,7 @@ void k_filter(FilterArgs a) {
     // with an odd number of rows leaves its last row alone), so a band that
     // starts at an even row pairs its rows as the whole detector does
     const int hp = (a.nv + 1) >> 1;                   // row pairs per projection
-    const int pair = blockIdx.x * PAIRS + grp;
+    const int pair = block * PAIRS + grp;
     const int pp = pair / hp, kk = pair - pp * hp;
     const int r0 = pp * a.nv + 2 * kk, r1 = r0 + 1;
     const bool has0 = r0 < a.rows, has1 = has0 && 2 * kk + 1 < a.nv;
@@ -352,6 +352,23 @@ void k_filter(FilterArgs a) {
     }
 }
 
+template <int LOGM, int STORE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FilterShape<LOGM>::WAVES)))
+void k_filter(FilterArgs a) {
+    filter_block<LOGM, STORE>(a, blockIdx.x);
+}
+
+// Many volumes of one FFT length: workgroup b is workgroup b - start[v] of
+// volume v.
+template <int LOGM, int STORE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FilterShape<LOGM>::WAVES)))
+void k_filter_batch(FilterBatchArgs ba) {
+    const int b = blockIdx.x;
+    const int v = batch_volume(ba.start, ba.nvol, b);
+    const FilterArgs a = const_load(ba.vols + v);
+    filter_block<LOGM, STORE>(a, b - const_load(ba.start + v));
+}
+
 // ---------------------------------------------------------------------------
 // M = 4096 (N = 1025..2048): four-step transform, one row pair per wavefront.
 // Index u = a + 64 b (a: the lane, b: a register); the length-4096 DFT is a
@@ -443,14 +460,14 @@ __device__ __forceinline__ void dft4096_wave(float2 (&v)[64], float2* T, const f
     dft64<false, HALF_OUT>(v);
 }
 
+// Row pair `pair` of one volume (a 64-thread workgroup).
 template <int STORE>
-__global__ __launch_bounds__(64) void k_filter4096(FilterArgs a) {
+__device__ __forceinline__ void filter4096_pair(const FilterArgs& a, int pair) {
     using S = Store<STORE>;
     constexpr int ES = (int)sizeof(typename S::T);
     __shared__ float2 T[64 * 65];
     const int lane = threadIdx.x;
     const int hp = (a.nv + 1) >> 1;
-    const int pair = blockIdx.x;
     const int pp = pair / hp, kk = pair - pp * hp;
     const int r0 = pp * a.nv + 2 * kk, r1 = r0 + 1;
     const bool has0 = r0 < a.rows, has1 = has0 && 2 * kk + 1 < a.nv;
@@ -539,6 +556,19 @@ __global__ __launch_bounds__(64) void k_filter4096(FilterArgs a) {
     }
 }
 
+template <int STORE>
+__global__ __launch_bounds__(64) void k_filter4096(FilterArgs a) {
+    filter4096_pair<STORE>(a, blockIdx.x);
+}
+
+template <int STORE>
+__global__ __launch_bounds__(64) void k_filter4096_batch(FilterBatchArgs ba) {
+    const int b = blockIdx.x;
+    const int v = batch_volume(ba.start, ba.nvol, b);
+    const FilterArgs a = const_load(ba.vols + v);
+    filter4096_pair<STORE>(a, b - const_load(ba.start + v));
+}
+
 template <int LOGM>
 static hipError_t launch_filter_m(const FilterArgs& a, int store, hipStream_t st) {
     constexpr int TP = FilterShape<LOGM>::TP;
@@ -575,6 +605,48 @@ hipError_t launch_filter(const FilterArgs& a, int logm, int store, hipStream_t s
             return hipGetLastError();
         }
         case 13: return launch_filter_m<13>(a, store, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int filter_workgroups(const FilterArgs& a, int logm) {
+    const int pairs = (a.rows / a.nv) * ((a.nv + 1) / 2);
+    if (logm == 12) return pairs;
+    const int per = 256 / filter_threads_per_pair(logm);
+    return (pairs + per - 1) / per;
+}
+
+template <int LOGM>
+static hipError_t launch_filter_batch_m(const FilterBatchArgs& a, int store, int workgroups, hipStream_t st) {
+    const dim3 grid(workgroups);
+    switch (store) {
+        case 0: hipLaunchKernelGGL((k_filter_batch<LOGM, 0>), grid, dim3(256), 0, st, a); break;
+        case 1: hipLaunchKernelGGL((k_filter_batch<LOGM, 1>), grid, dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_filter_batch<LOGM, 2>), grid, dim3(256), 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_filter_batch(const FilterBatchArgs& a, int logm, int store, int workgroups, hipStream_t st) {
+    if (workgroups <= 0) return hipSuccess;
+    switch (logm) {
+        case 3: return launch_filter_batch_m<3>(a, store, workgroups, st);
+        case 4: return launch_filter_batch_m<4>(a, store, workgroups, st);
+        case 5: return launch_filter_batch_m<5>(a, store, workgroups, st);
+        case 6: return launch_filter_batch_m<6>(a, store, workgroups, st);
+        case 7: return launch_filter_batch_m<7>(a, store, workgroups, st);
+        case 8: return launch_filter_batch_m<8>(a, store, workgroups, st);
+        case 9: return launch_filter_batch_m<9>(a, store, workgroups, st);
+        case 10: return launch_filter_batch_m<10>(a, store, workgroups, st);
+        case 11: return launch_filter_batch_m<11>(a, store, workgroups, st);
+        case 12:
+            switch (store) {
+                case 0: hipLaunchKernelGGL((k_filter4096_batch<0>), dim3(workgroups), dim3(64), 0, st, a); break;
+                case 1: hipLaunchKernelGGL((k_filter4096_batch<1>), dim3(workgroups), dim3(64), 0, st, a); break;
+                default: hipLaunchKernelGGL((k_filter4096_batch<2>), dim3(workgroups), dim3(64), 0, st, a); break;
+            }
+            return hipGetLastError();
+        case 13: return launch_filter_batch_m<13>(a, store, workgroups, st);
         default: return hipErrorInvalidValue;
     }
 }

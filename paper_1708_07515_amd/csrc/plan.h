@@ -90,6 +90,8 @@ BpVol bp_vol(const fdkod_plan_s* pl, const void* filt, const void* ws, float* vo
 BpVol bp_vol_band(const fdkod_plan_s* pl, const void* filt, const void* ws, float* vol, int v0, int nv,
                   int zbase, int nzs);
 FilterArgs filter_args(const fdkod_plan_s* pl, const float* proj, void* filt, int v0, int nv);
+// arguments of the bounds kernel for a plan
+BoundsArgs bounds_args(const fdkod_plan_s* pl);
 // bands of detector rows and slabs of slices (eq. (9)): the rows a slab
 // samples, and argument checks of the band calls
 void band_for(const fdkod_plan_s* pl, int z0, int nzs, int* v0, int* nv);

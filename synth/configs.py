@@ -66,5 +66,7 @@ class BatchWorkload:
 
 
 C4 = BatchWorkload()
+# many small volumes, where one volume alone is far from filling the GPU
+C4S = BatchWorkload(name="batch256_small", count=256, sizes=(32, 48, 64), ellipsoids=6, seed=6)
 
 ALL = {w.name: w for w in (C1, C2, C3, C5)}
