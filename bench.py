@@ -31,12 +31,15 @@ VALU_PACKED_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 # LDS: 128 bytes per clock per compute unit, 256 CUs at 2.4 GHz
 LDS_PEAK_GBS = 128 * 256 * 2.4
+# VALU issue limit: one 64-lane instruction per compute unit per cycle (four
+# SIMDs, each taking four cycles for a wave's instruction), 256 CUs at 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 2.4e9
 # algorithmic FP32 work of one voxel-angle update of the backprojection: three
 # linear interpolations (a subtraction and an FMA each, counted as one flop
 # and two) and the weighted accumulation (one FMA): 3 x 2 + 2 = 8
 FLOPS_PER_UPDATE = 8
-# on-chip bytes of one update: the two detector rows' (value, difference)
-# pairs of the bilinear sample, FP32 (one 16-byte LDS read)
+# on-chip bytes of one update: the bilinear sample's quad (value, column,
+# row and mixed differences), FP32 (one 16-byte LDS read)
 LDS_BYTES_PER_UPDATE = 16
 # the workers of the CPU oracle baseline: the machine's CPU share for one GPU
 CPU_WORKERS_MAX = 16
@@ -512,8 +515,17 @@ def kernel_rooflines(wl, s, k, store, res):
     # the backprojection's VALU instructions per update (all of them: the
     # inner loop, the per-angle set-up and the staging) from the committed
     # counter summary, when it was taken on this kernel and workload
-    out["reconstruct"]["valu_instr_per_update"] = measured_counter("k_backproject", wl, s, k, store,
-                                                                   "valu_instr_per_update")
+    vipu = measured_counter("k_backproject", wl, s, k, store, "valu_instr_per_update")
+    out["reconstruct"]["valu_instr_per_update"] = vipu
+    # the rate at which those instructions issue (64-lane instructions per
+    # second) against the issue limit of one per compute unit per cycle:
+    # the kernel's bound once the instructions per update are fixed
+    if vipu is not None:
+        rate = vipu * ups / 64.0
+        out["reconstruct"]["valu_issue"] = {
+            "achieved": round(rate / 1e9, 1), "peak": round(VALU_ISSUE_PEAK / 1e9, 1),
+            "unit": "G wave-instructions/s", "frac": round(rate / VALU_ISSUE_PEAK, 4),
+            "instructions": "counter-measured VALU instructions per update (profiles/) x the live update rate"}
     return out
 
 
