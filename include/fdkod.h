@@ -308,8 +308,8 @@ fdkod_status fdkod_get_bounds(fdkod_plan_t plan, float* ac_p, float* ac_m, float
  * Parameters: FDKOD_LEARNED_PARAMS BF16 values on the device, in the order
  * W1 [16][5][5], b1 [16], W2 [16][5][5], b2.  Both convolutions multiply BF16
  * operands (S, the weights, the activations) with FP32 accumulation.  With
- * W2 = 0 and b2 = 0 the result is the triangle decimation.  Requires s > 0,
- * P <= 2048 and W_q <= 252 for every square (FDKOD_E_UNSUPPORTED otherwise).
+ * W2 = 0 and b2 = 0 the result is the triangle decimation.  Requires s > 0
+ * and W_q <= 252 for every square (FDKOD_E_UNSUPPORTED otherwise).
  * ------------------------------------------------------------------------- */
 #define FDKOD_LEARNED_PARAMS 817
 

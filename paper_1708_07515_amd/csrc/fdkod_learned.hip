@@ -17,7 +17,6 @@ fdkod_status learned_check(const fdkod_plan_s* pl) {
                     "the learned decimation corrects the triangle decimation of detector rows, linear shift");
     if (pl->wmax > kLearnedMaxWidth)
         return fail(FDKOD_E_UNSUPPORTED, "a square is wider than 252 local columns");
-    if (pl->p > kLearnedMaxP) return fail(FDKOD_E_UNSUPPORTED, "more than 2048 projections");
     return FDKOD_OK;
 }
 

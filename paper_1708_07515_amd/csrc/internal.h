@@ -194,7 +194,6 @@ hipError_t launch_reset_counter(unsigned* counter, hipStream_t st);
 // decimation): 817 BF16 parameters W1 [16][5][5], b1 [16], W2 [16][5][5], b2.
 constexpr int kLearnedParams = 817;
 constexpr int kLearnedMaxWidth = 252;   // widest square (local columns) it takes
-constexpr int kLearnedMaxP = 2048;      // most projections it takes
 constexpr int kLearnedBwdGrid = 1024;   // workgroups of the backward pass (most)
 
 struct LearnedArgs {

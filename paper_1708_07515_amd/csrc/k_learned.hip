@@ -79,8 +79,8 @@ struct CentreWalk {
 // span exactly one detector row, so samples outside the detector, and every
 // sample of a column outside [0, W) (given a negative offset), read zero.
 template <int STORE>
-__device__ __forceinline__ void s_fetch_rows(const LearnedArgs& a, const float* o_tab, int v, int c, int jj,
-                                             bool valid, const int offr[9], float x0[9], float x1[9],
+__device__ __forceinline__ void s_fetch_rows(const LearnedArgs& a, const float* acq, float u0f, int v, int c,
+                                             int jj, bool valid, const int offr[9], float x0[9], float x1[9],
                                              float ph[9]) {
     using S = Store<STORE>;
     using T = typename S::T;
@@ -89,7 +89,7 @@ __device__ __forceinline__ void s_fetch_rows(const LearnedArgs& a, const float* 
     for (int t = 0; t < 9; ++t) {
         int p = c + offr[t];
         if (p >= a.p) p -= a.p;
-        const float o = o_tab[p];
+        const float o = const_load(acq + p) + u0f;
         const float of = floorf(o);
         ph[t] = o - of;
         const __amdgpu_buffer_rsrc_t rs = row_rsrc((const T*)a.filt + ((size_t)p * a.nv + v) * a.n, a.n);
@@ -112,7 +112,6 @@ constexpr int kPP = 16 * ((kLearnedMaxWidth + 15) / 16) + 8;   // pitch in pairs
 static_assert(kPP >= kThreads + 1, "every staged column has a pair entry");
 
 struct FwdSmem {
-    float o_tab[kLearnedMaxP];
     int off_tab[9];
     uint32_t sp[9 * kPP];
 };
@@ -282,7 +281,10 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd(LearnedArgs a) {
     const FwdOperands op = load_fwd_operands<kPP>(a.w);
     const float b2 = bf2f(a.w[kOffB2]);
     const int ntile = (width + 15) >> 4;
-    for (int p = threadIdx.x; p < a.p; p += kThreads) sm.o_tab[p] = a.ac_p[(size_t)q * a.p + p] + (float)u0;
+    // the crop offset of projection p is a_c(beta_p) + u0 (a_c from the
+    // bounds, read through scalar loads where it is used)
+    const float* acq = a.ac_p + (size_t)q * a.p;
+    const float u0f = (float)u0;
     if (threadIdx.x < 9) {
         int off = ((int)threadIdx.x - 4) * a.d % a.p;
         sm.off_tab[threadIdx.x] = off < 0 ? off + a.p : off;
@@ -304,7 +306,7 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd(LearnedArgs a) {
     for (int t = 0; t < 9; ++t) offr[t] = __builtin_amdgcn_readfirstlane(sm.off_tab[t]);
 
     float x0[9], x1[9], ph[9];
-    s_fetch_rows<STORE>(a, sm.o_tab, v, cw.c, jj, valid, offr, x0, x1, ph);
+    s_fetch_rows<STORE>(a, acq, u0f, v, cw.c, jj, valid, offr, x0, x1, ph);
     float y_cur = j < width ? S::load(ws, yrow + j) : 0.0f;
     if (stager) s_stage_pairs(sm.sp, col, x0, x1, ph);
     vmem_drain();
@@ -314,7 +316,7 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd(LearnedArgs a) {
         float y_next = 0.0f;
         if (more) {
             cw.next();
-            s_fetch_rows<STORE>(a, sm.o_tab, v, cw.c, jj, valid, offr, x0, x1, ph);
+            s_fetch_rows<STORE>(a, acq, u0f, v, cw.c, jj, valid, offr, x0, x1, ph);
             if (j < width) y_next = S::load(ws, yrow + (size_t)(m + 1) * yplane + j);
         }
 #pragma unroll
@@ -358,7 +360,11 @@ struct RingSmem {
     uint32_t sp[kRingSlots * kPitch];
     float qb[2][5 * kQPitch];
 };
-static_assert(sizeof(RingSmem<256>) + 4 * kLearnedMaxP <= 65536, "ring tile fits the LDS of a workgroup");
+// The ring kernel stages the crop offsets of all P projections in LDS beside
+// its tile (64 KB per workgroup): up to this many projections; more take the
+// general kernel, which reads each offset where it is used.
+constexpr int kRingMaxP = (65536 - (int)sizeof(RingSmem<256>)) / 4;
+static_assert(kRingMaxP >= 2048, "ring tile and offset table fit the LDS of a workgroup");
 
 // Row p of S at the thread's staged column (local column jj): the two
 // detector samples and the interpolation fraction (zero outside the row and
@@ -500,7 +506,6 @@ constexpr int kDrPad = 16;                          // dR row: column c at index
 constexpr int kDrLen = kDrPad + 16 * ((kLearnedMaxWidth + 15) / 16) + 18;
 
 struct BwdSmem {
-    float o_tab[kLearnedMaxP];
     int off_tab[9];
     uint32_t sp[9 * kPP];
     float dr[kDrLen];
@@ -508,7 +513,12 @@ struct BwdSmem {
 
 template <int STORE>
 __global__ __launch_bounds__(kThreads) void k_learned_bwd(LearnedArgs a) {
-    __shared__ BwdSmem sm;
+    // the task state, and after the last task the waves' partial gradients
+    __shared__ union {
+        BwdSmem s;
+        float red[4 * kLearnedParams];
+    } smu;
+    BwdSmem& sm = smu.s;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lg = lane >> 4;
     const FwdOperands op = load_fwd_operands<kPP>(a.w);
@@ -545,7 +555,8 @@ __global__ __launch_bounds__(kThreads) void k_learned_bwd(LearnedArgs a) {
         const int u0 = gd.x, width = gd.y;
         const int ntile = (width + 15) >> 4;
         __syncthreads();                                   // the previous task's reads are done
-        for (int p = threadIdx.x; p < a.p; p += kThreads) sm.o_tab[p] = a.ac_p[(size_t)q * a.p + p] + (float)u0;
+        const float* acq = a.ac_p + (size_t)q * a.p;   // crop offsets a_c(beta_p) + u0
+        const float u0f = (float)u0;
         if (threadIdx.x < 9) {
             int off = ((int)threadIdx.x - 4) * a.d % a.p;
             sm.off_tab[threadIdx.x] = off < 0 ? off + a.p : off;
@@ -566,7 +577,7 @@ __global__ __launch_bounds__(kThreads) void k_learned_bwd(LearnedArgs a) {
         for (int m = 0; m < a.pd; ++m) {
             {
                 float x0[9], x1[9], ph[9];
-                s_fetch_rows<STORE>(a, sm.o_tab, v, cw.c, jj, valid, offr, x0, x1, ph);
+                s_fetch_rows<STORE>(a, acq, u0f, v, cw.c, jj, valid, offr, x0, x1, ph);
                 if (stager) s_stage_pairs(sm.sp, col, x0, x1, ph);
                 cw.next();
             }
@@ -640,8 +651,7 @@ __global__ __launch_bounds__(kThreads) void k_learned_bwd(LearnedArgs a) {
     // gradient; k_grad_sum adds the workgroups' partials in a fixed order, so
     // the gradient does not depend on scheduling.
     __syncthreads();                                       // the last task's reads of sm are done
-    float* red = reinterpret_cast<float*>(&sm);            // [4][kLearnedParams]
-    static_assert(sizeof(BwdSmem) >= 4 * kLearnedParams * sizeof(float), "wave partials fit");
+    float* red = smu.red;                                  // [4][kLearnedParams]
     float* mine = red + wave * kLearnedParams;
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
@@ -911,8 +921,8 @@ void launch_fwd_ring(const LearnedArgs& a, int max_width, hipStream_t st) {
 }
 
 hipError_t launch_learned_fwd(const LearnedArgs& a, int max_width, int dfac, int store, hipStream_t st) {
-    if (max_width > kLearnedMaxWidth || a.p > kLearnedMaxP) return hipErrorInvalidValue;
-    if (dfac >= 4 && a.p % dfac == 0 && a.pd * dfac == a.p && a.d * 4 == dfac) {
+    if (max_width > kLearnedMaxWidth) return hipErrorInvalidValue;
+    if (dfac >= 4 && a.p % dfac == 0 && a.pd * dfac == a.p && a.d * 4 == dfac && a.p <= kRingMaxP) {
         switch (store) {
             case 0: launch_fwd_ring<0>(a, max_width, st); break;
             case 1: launch_fwd_ring<1>(a, max_width, st); break;

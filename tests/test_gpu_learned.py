@@ -20,6 +20,10 @@ CASES = [(32, 48, 128.0, 2, 0), (40, 64, 160.0, 3, 0), (37, 50, 150.0, 3, 1), (3
          (128, 64, 512.0, 4, 0)]
 # The last has D = 16, so the angle dilation is d = 4 (the decimation of the
 # N = 2000, P = 720, s = 4 workload), again with D | P.
+# More than 2048 projections (each crop offset is read from the bounds table
+# where it is used, so P is not bounded by a staged table): one case with
+# D | P (the row-reusing kernel) and one without (the general kernel).
+LONG_P = [(16, 2304, 64.0, 2, 0), (16, 2102, 64.0, 2, 0)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -93,7 +97,7 @@ def _as(plan, ws):
     return ws.view(plan.store_torch_dtype())[:plan.workspace_elems].double().cpu()
 
 
-@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("case", CASES + LONG_P)
 def test_learned_forward_matches_oracle(case):
     n, p, r, s, k = case
     net = random_net(1)
@@ -353,7 +357,7 @@ def _perturbed_subsinograms(proj, n, p, r, s, k, seed=12):
     return [np.moveaxis(_crop_fp32_position(frows, sq, betas, r, n), 0, 1) for sq in sqs]
 
 
-@pytest.mark.parametrize("case", CASES[:2] + CASES[4:])
+@pytest.mark.parametrize("case", CASES[:2] + CASES[4:] + LONG_P[:1])
 def test_learned_gradient_matches_oracle(case):
     n, p, r, s, k = case
     net = random_net(4)
