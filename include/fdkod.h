@@ -76,8 +76,9 @@ typedef enum { FDKOD_F32 = 0, FDKOD_F16 = 1, FDKOD_BF16 = 2 } fdkod_dtype;
  *            Nyquist frequency, times a Hann window over `taps` decimated
  *            steps (even, 2..6; 0 selects 4), normalised per window; each
  *            projection feeds up to `taps` windows.  Needs P >= taps * D.
- *            Not available to the learned decimation and batches
- *            (FDKOD_E_UNSUPPORTED); the slab mode supports it. */
+ *            The learned decimation adds its correction to it as to the
+ *            triangle; not available to batches (FDKOD_E_UNSUPPORTED); the
+ *            slab mode supports it. */
 typedef enum { FDKOD_DECIM_TRIANGLE = 0, FDKOD_DECIM_SINC = 1 } fdkod_decim;
 
 /* Rows of the decomposed data:
@@ -294,8 +295,8 @@ fdkod_status fdkod_get_bounds(fdkod_plan_t plan, float* ac_p, float* ac_m, float
 /* ---------------------------------------------------------------------------
  * Learned decimation filter.  Sec. 2.1 leaves the low-pass filter of the
  * angular decimation open (the quality depends on its implementation).  This
- * filter adds a trained correction R to the triangle decimation T of every
- * square q and detector row v:
+ * filter adds a trained correction R to the plan's decimation T (the
+ * triangle, or the windowed sinc) of every square q and detector row v:
  *
  *   Y_q[m][v][j] = T[m][v][j] + R[m][v][j],   R = conv2(ReLU(conv1(S)))
  *   conv1: H_k(p, j) = b1_k + sum_{a,b<5} W1[k][a][b] S((p + (a-2) d) mod P, j + b - 2)
@@ -308,8 +309,9 @@ fdkod_status fdkod_get_bounds(fdkod_plan_t plan, float* ac_p, float* ac_m, float
  * Parameters: FDKOD_LEARNED_PARAMS BF16 values on the device, in the order
  * W1 [16][5][5], b1 [16], W2 [16][5][5], b2.  Both convolutions multiply BF16
  * operands (S, the weights, the activations) with FP32 accumulation.  With
- * W2 = 0 and b2 = 0 the result is the triangle decimation.  Requires s > 0
- * and W_q <= 252 for every square (FDKOD_E_UNSUPPORTED otherwise).
+ * W2 = 0 and b2 = 0 the result is the plan's decimation.  Requires s > 0,
+ * detector rows, the linear shift and W_q <= 252 for every square
+ * (FDKOD_E_UNSUPPORTED otherwise).
  * ------------------------------------------------------------------------- */
 #define FDKOD_LEARNED_PARAMS 817
 

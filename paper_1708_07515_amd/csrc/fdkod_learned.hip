@@ -12,9 +12,9 @@ namespace {
 
 fdkod_status learned_check(const fdkod_plan_s* pl) {
     if (pl->s == 0) return fail(FDKOD_E_UNSUPPORTED, "the learned decimation needs s > 0");
-    if (pl->cone || pl->sinc || pl->cubic)
+    if (pl->cone || pl->cubic)
         return fail(FDKOD_E_UNSUPPORTED,
-                    "the learned decimation corrects the triangle decimation of detector rows, linear shift");
+                    "the learned decimation corrects a decimation of detector rows with the linear shift");
     if (pl->wmax > kLearnedMaxWidth)
         return fail(FDKOD_E_UNSUPPORTED, "a square is wider than 252 local columns");
     return FDKOD_OK;

@@ -128,6 +128,39 @@ def test_learned_forward_matches_oracle(case):
     plan.close()
 
 
+@pytest.mark.parametrize("case", [(40, 64, 160.0, 3, 0), (37, 50, 150.0, 3, 1)])
+def test_learned_forward_on_the_windowed_sinc(case):
+    """With the windowed sinc (4 taps) as the plan's decimation the learned
+    filter adds the same correction R (it reads the linearly cropped S, not
+    the window): Y = Sinc + R against the oracle's sinc decimation and R."""
+    n, p, r, s, k = case
+    net = random_net(2)
+    proj = scan(n, p, r, 6, 11 + n)
+    plan = pkg.Plan(n, p, r, s=s, skip=k, decim="sinc", taps=4)
+    filt = plan.empty_filtered()
+    plan.filter(proj.to(DEV), filt)
+    ws_plain, ws_l = plan.empty_workspace(), plan.empty_workspace()
+    plan.decompose(filt, ws_plain)
+    plan.learned_decompose(filt, ws_l, device_weights(net))
+    torch.cuda.synchronize()
+    sqs, betas_dec, _, subs = oracle_subsinograms(proj, n, p, r, s, k)
+    d_factor = ofdkod.decimation_factor(s, k)
+    win = ofdkod.decimation_weights(p, len(betas_dec), "sinc", 4)
+    got_y = square_views(plan, _as(plan, ws_l))
+    got_t = square_views(plan, _as(plan, ws_plain))
+    errs_r, errs_y = [], []
+    for q, sub in enumerate(subs):
+        r_or, _ = learned.forward(sub, net, d_factor, len(betas_dec), bf16=True)
+        t_or = np.moveaxis(np.tensordot(sub, win.T, axes=(1, 0)), -1, 1)
+        gy = got_y[q].numpy().transpose(1, 0, 2)
+        gt = got_t[q].numpy().transpose(1, 0, 2)
+        errs_r.append(metrics.rel_rmse(gy - gt, r_or))
+        errs_y.append(metrics.rel_rmse(gy, t_or + r_or))
+    log(f"learned on sinc {case}: R rel-RMSE max {max(errs_r):.2e}, Y rel-RMSE max {max(errs_y):.2e}")
+    assert max(errs_r) <= 1e-3 and max(errs_y) <= 1e-3
+    plan.close()
+
+
 # Wide squares for the row-reusing kernel's tile pitches (128, 224 and 256
 # columns; the 224 form takes squares of 193..224 columns in 14 tiles, four
 # slots per wave): widths 122..148 (across 128), 194..212 (all inside the 224
@@ -560,6 +593,14 @@ def test_learned_rejects_unsupported_plans():
             plan.learned_decompose(filt, torch.empty(256, dtype=torch.uint8, device=DEV),
                                    device_weights(random_net(0)))
         assert ei.value.code == "E_UNSUPPORTED"
+    # the correction reads the linearly cropped rows of the detector: plans
+    # with the cubic shift or cone-corrected rows are refused
+    for knobs in (dict(interp="cubic"), dict(rows="cone")):
+        with pkg.Plan(32, 48, 128.0, s=2, **knobs) as plan:
+            filt, ws = plan.empty_filtered(), plan.empty_workspace()
+            with pytest.raises(pkg.FdkodError) as ei:
+                plan.learned_decompose(filt, ws, device_weights(random_net(0)))
+            assert ei.value.code == "E_UNSUPPORTED"
     # the transpose of the backprojection samples detector rows; a plan with
     # cone-corrected rows reads warped rows, so its transpose is refused
     with pkg.Plan(32, 48, 128.0, s=2, rows="cone") as plan:
