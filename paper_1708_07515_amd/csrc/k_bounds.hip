@@ -5,7 +5,8 @@
 // a_max; a wavefront + workgroup reduction gives the square's extremes of
 // a - a_c over the decimated angles, from which the local column grid
 // (origin u0 and width W) follows.  Per original angle p it writes a_c(beta_p),
-// the centre trajectory that the crop follows.
+// the centre trajectory that the crop follows.  Batches run the squares of
+// all their volumes in one launch (k_bounds_batch).
 #include "internal.h"
 #include "dtype.h"
 #include "geom.h"
