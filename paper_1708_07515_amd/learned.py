@@ -1,7 +1,8 @@
 """Learned decimation filter: parameters, AdamW state and one training step.
 
 The network (two 5 x 5 convolutions over angle x column, 16 channels, added to
-the triangle decimation of Sec. 2.1) and every step of its training run in the
+the plan's decimation of Sec. 2.1: the triangle, or the windowed sinc) and
+every step of its training run in the
 library's kernels; this module only owns the device buffers and sequences the
 calls:
 
@@ -28,7 +29,7 @@ class LearnedDecimation:
     """FP32 master weights on the device, their BF16 copy and AdamW moments.
 
     A new instance has W1 ~ N(0, (scale / 5)^2) (seeded), b1 = 0 and a zero
-    second layer, so it computes the plain triangle decimation until trained."""
+    second layer, so it computes the plan's plain decimation until trained."""
 
     def __init__(self, device="cuda:0", seed=0, scale=0.1, lr=2e-3, betas=(0.9, 0.999), eps=1e-8,
                  weight_decay=0.0):
