@@ -99,8 +99,9 @@ typedef enum { FDKOD_ROWS_DETECTOR = 0, FDKOD_ROWS_CONE = 1 } fdkod_rows;
  *  CUBIC   Keys' cubic convolution kernel with a = -1/2 (Catmull-Rom), four
  *          samples per cropped value, zero outside the detector (an
  *          extension: Sec. 2.2 notes that a more precise interpolation
- *          reduces smoothing).  Not available to the learned decimation and
- *          batches (FDKOD_E_UNSUPPORTED); the slab mode supports it. */
+ *          reduces smoothing).  The learned decimation reads its rows S
+ *          with the same interpolation; not available to batches
+ *          (FDKOD_E_UNSUPPORTED); the slab mode supports it. */
 typedef enum { FDKOD_INTERP_LINEAR = 0, FDKOD_INTERP_CUBIC = 1 } fdkod_interp;
 
 /* Problem statement, after Sec. 2.1: N, P, R, s, and the skipped
@@ -303,15 +304,16 @@ fdkod_status fdkod_get_bounds(fdkod_plan_t plan, float* ac_p, float* ac_m, float
  *   R(m, j) = b2 + sum_{k,a,b<5} W2[k][a][b] A_k((c(m) + (a-2) d) mod P, j + b - 2)
  *
  * S(p, j) = Lin(filt[p][v][.], a_c(beta_p) + u0_q + j) is the cropped and
- * shifted full-rate sub-sinogram (zero outside the columns [0, W_q)),
+ * shifted full-rate sub-sinogram (zero outside the columns [0, W_q)); with
+ * the cubic shift Lin is Keys' cubic convolution, as in the decimation;
  * A = ReLU(H) on [0, W_q) and zero outside, c(m) = floor(m P / P' + 1/2) mod P
  * the original angle nearest to beta'_m, d = max(1, D / 4), k < 16 channels.
  * Parameters: FDKOD_LEARNED_PARAMS BF16 values on the device, in the order
  * W1 [16][5][5], b1 [16], W2 [16][5][5], b2.  Both convolutions multiply BF16
  * operands (S, the weights, the activations) with FP32 accumulation.  With
  * W2 = 0 and b2 = 0 the result is the plan's decimation.  Requires s > 0,
- * detector rows, the linear shift and W_q <= 252 for every square
- * (FDKOD_E_UNSUPPORTED otherwise).
+ * detector rows and W_q <= 252 for every square (FDKOD_E_UNSUPPORTED
+ * otherwise).
  * ------------------------------------------------------------------------- */
 #define FDKOD_LEARNED_PARAMS 817
 

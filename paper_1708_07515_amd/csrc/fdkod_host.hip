@@ -801,7 +801,7 @@ fdkod_status fdkod_plan_create(const fdkod_params* prm, int device, fdkod_plan_t
     if ((st = upload(pl, &pl->d_tiles, tiles)) != FDKOD_OK) return bail(st);
     // the learned filter's backward pass sums its workgroups' partial
     // gradients in a fixed order (a plan the filter applies to only)
-    if (pl->s > 0 && !pl->cone && !pl->cubic && pl->wmax <= kLearnedMaxWidth &&
+    if (pl->s > 0 && !pl->cone && pl->wmax <= kLearnedMaxWidth &&
         (st = dev_alloc(pl->allocs, (void**)&pl->d_lpartials,
                         sizeof(float) * (size_t)kLearnedBwdGrid * kLearnedParams)) != FDKOD_OK)
         return bail(st);

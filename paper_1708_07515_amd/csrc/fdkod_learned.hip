@@ -12,9 +12,8 @@ namespace {
 
 fdkod_status learned_check(const fdkod_plan_s* pl) {
     if (pl->s == 0) return fail(FDKOD_E_UNSUPPORTED, "the learned decimation needs s > 0");
-    if (pl->cone || pl->cubic)
-        return fail(FDKOD_E_UNSUPPORTED,
-                    "the learned decimation corrects a decimation of detector rows with the linear shift");
+    if (pl->cone)
+        return fail(FDKOD_E_UNSUPPORTED, "the learned decimation corrects a decimation of detector rows");
     if (pl->wmax > kLearnedMaxWidth)
         return fail(FDKOD_E_UNSUPPORTED, "a square is wider than 252 local columns");
     return FDKOD_OK;
@@ -39,6 +38,7 @@ LearnedArgs learned_args(const fdkod_plan_s* pl, const void* filt, void* ws, con
     a.d = pl->d / 4 > 1 ? pl->d / 4 : 1;
     a.nv = nv;
     a.ntasks = pl->nsq * nv;
+    a.cubic = pl->cubic;
     return a;
 }
 

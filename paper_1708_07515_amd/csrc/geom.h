@@ -20,4 +20,13 @@ __device__ __forceinline__ float rel_column(float dx, float dy, float cs, float 
     return r * (dl * dc - lc * dd) * rdc / d;
 }
 
+// Keys' cubic convolution weights (a = -1/2) of the samples at offsets
+// -1, 0, 1, 2 from floor(u), for the fraction f of u (the crop's cubic shift).
+__device__ __forceinline__ void keys_weights(float f, float (&c)[4]) {
+    c[0] = ((-0.5f * f + 1.0f) * f - 0.5f) * f;
+    c[1] = (1.5f * f - 2.5f) * f * f + 1.0f;
+    c[2] = ((-1.5f * f + 2.0f) * f + 0.5f) * f;
+    c[3] = (0.5f * f - 0.5f) * f * f;
+}
+
 }  // namespace fdkod

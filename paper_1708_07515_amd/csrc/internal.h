@@ -210,6 +210,7 @@ struct LearnedArgs {
     int nv;                  // detector rows held by filt / ws / dws (a band of them: N in the whole-volume calls)
     int d;                   // angle dilation max(1, D / 4)
     int ntasks;              // nsq * nv
+    int cubic;               // S by Keys' cubic convolution (the plan's cubic shift), else linear
 };
 
 // Transpose of the per-square backprojection (training).

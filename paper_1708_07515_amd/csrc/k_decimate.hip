@@ -29,6 +29,7 @@
 // cropped value and weights them with Keys' kernel of the step's fraction.
 #include "internal.h"
 #include "dtype.h"
+#include "geom.h"
 
 namespace fdkod {
 
@@ -55,14 +56,6 @@ struct DecimShape {
     static constexpr int NX = NW > 2 ? NW - 2 : 1;     // extra weights per step (array size)
 };
 
-// Keys' cubic convolution weights (a = -1/2) of the samples at offsets
-// -1, 0, 1, 2 from floor(u), for the fraction f of u.
-__device__ __forceinline__ void keys_weights(float f, float (&c)[4]) {
-    c[0] = ((-0.5f * f + 1.0f) * f - 0.5f) * f;
-    c[1] = (1.5f * f - 2.5f) * f * f + 1.0f;
-    c[2] = ((-1.5f * f + 2.0f) * f + 0.5f) * f;
-    c[3] = (0.5f * f - 0.5f) * f * f;
-}
 
 // One task: square q, detector rows v .. v + RPT - 1 (warped row v' for
 // CONE), column group g of 64*CH columns, run by one wavefront (lane =

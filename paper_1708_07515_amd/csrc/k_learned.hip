@@ -73,31 +73,62 @@ struct CentreWalk {
     }
 };
 
+// One row of S at the thread's column: the detector samples of the crop's
+// interpolation -- two for the linear shift, four (offsets -1 .. 2) for Keys'
+// cubic convolution -- and the fraction; value() is S.
+template <bool CUBIC>
+struct SRow {
+    float x[CUBIC ? 4 : 2];
+    float ph;
+    __device__ __forceinline__ float value() const {
+        if constexpr (CUBIC) {
+            float c[4];
+            keys_weights(ph, c);
+            float s = c[0] * x[0];
+            s = fmaf(c[1], x[1], s);
+            s = fmaf(c[2], x[2], s);
+            return fmaf(c[3], x[3], s);
+        } else {
+            return fmaf(ph, x[1] - x[0], x[0]);
+        }
+    }
+};
+
+// The detector samples of row p at the crop offset o and local column jj,
+// each through its own range-checked load (zero outside the row; a column
+// outside [0, W) takes offsets left of the row and reads zero).
+template <int STORE, bool CUBIC>
+__device__ __forceinline__ void srow_load(const LearnedArgs& a, int v, int p, float o, int jj, bool valid,
+                                          SRow<CUBIC>& r) {
+    using S = Store<STORE>;
+    using T = typename S::T;
+    constexpr int ES = (int)sizeof(T);
+    const float of = floorf(o);
+    r.ph = o - of;
+    const __amdgpu_buffer_rsrc_t rs = row_rsrc((const T*)a.filt + ((size_t)p * a.nv + v) * a.n, a.n);
+    constexpr int K = CUBIC ? 4 : 2, LO = CUBIC ? -1 : 0;
+    const int off0 = valid ? ((int)of + jj + LO) * ES : -(K + 2) * ES;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        int off = off0 + i * ES;
+        if (i > 0) asm volatile("" : "+v"(off));   // separately range-checked loads, never one wider load
+        r.x[i] = S::raw(rs, off);
+    }
+}
+
 // The nine rows of S for centre angle c at the thread's column jj: detector
 // samples x0, x1 and the (row-uniform) interpolation fraction.  offr[t]: the
 // row offsets (t - 4) d mod P.  Rows are read through buffer resources that
 // span exactly one detector row, so samples outside the detector, and every
 // sample of a column outside [0, W) (given a negative offset), read zero.
-template <int STORE>
+template <int STORE, bool CUBIC>
 __device__ __forceinline__ void s_fetch_rows(const LearnedArgs& a, const float* acq, float u0f, int v, int c,
-                                             int jj, bool valid, const int offr[9], float x0[9], float x1[9],
-                                             float ph[9]) {
-    using S = Store<STORE>;
-    using T = typename S::T;
-    constexpr int ES = (int)sizeof(T);
+                                             int jj, bool valid, const int offr[9], SRow<CUBIC> (&rows)[9]) {
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
         int p = c + offr[t];
         if (p >= a.p) p -= a.p;
-        const float o = const_load(acq + p) + u0f;
-        const float of = floorf(o);
-        ph[t] = o - of;
-        const __amdgpu_buffer_rsrc_t rs = row_rsrc((const T*)a.filt + ((size_t)p * a.nv + v) * a.n, a.n);
-        const int off0 = valid ? ((int)of + jj) * ES : -4 * ES;
-        int off1 = off0 + ES;
-        asm volatile("" : "+v"(off1));   // two separately range-checked loads, never one wider load
-        x0[t] = S::raw(rs, off0);
-        x1[t] = S::raw(rs, off1);
+        srow_load<STORE, CUBIC>(a, v, p, const_load(acq + p) + u0f, jj, valid, rows[t]);
     }
 }
 
@@ -180,12 +211,12 @@ __device__ __forceinline__ FwdOperands load_fwd_operands(const uint16_t* w) {
 
 // Stage the thread's column x of the nine rows: the low half of pair x and
 // the high half of pair x - 1.
-__device__ __forceinline__ void s_stage_pairs(uint32_t* sp, int x, const float x0[9], const float x1[9],
-                                              const float ph[9]) {
+template <bool CUBIC>
+__device__ __forceinline__ void s_stage_pairs(uint32_t* sp, int x, const SRow<CUBIC> (&rows)[9]) {
     uint16_t* h = reinterpret_cast<uint16_t*>(sp);
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-        const uint16_t v = f2bf(fmaf(ph[t], x1[t] - x0[t], x0[t]));
+        const uint16_t v = f2bf(rows[t].value());
         h[2 * (t * kPP + x)] = v;
         if (x > 0) h[2 * (t * kPP + x - 1) + 1] = v;
     }
@@ -267,7 +298,7 @@ __host__ __device__ inline unsigned fwd_grid(const LearnedArgs& a) {
 // column t; the waves share the 16-column tiles.  This form fetches the nine
 // S rows of every angle; k_learned_fwd_ring below reuses them when the
 // decimated angles fall on original ones.
-template <int STORE>
+template <int STORE, bool CUBIC>
 __global__ __launch_bounds__(kThreads) void k_learned_fwd(LearnedArgs a) {
     using S = Store<STORE>;
     using T = typename S::T;
@@ -305,10 +336,10 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd(LearnedArgs a) {
 #pragma unroll
     for (int t = 0; t < 9; ++t) offr[t] = __builtin_amdgcn_readfirstlane(sm.off_tab[t]);
 
-    float x0[9], x1[9], ph[9];
-    s_fetch_rows<STORE>(a, acq, u0f, v, cw.c, jj, valid, offr, x0, x1, ph);
+    SRow<CUBIC> rows[9];
+    s_fetch_rows<STORE, CUBIC>(a, acq, u0f, v, cw.c, jj, valid, offr, rows);
     float y_cur = j < width ? S::load(ws, yrow + j) : 0.0f;
-    if (stager) s_stage_pairs(sm.sp, col, x0, x1, ph);
+    if (stager) s_stage_pairs(sm.sp, col, rows);
     vmem_drain();
     __syncthreads();
     for (int m = 0; m < a.pd; ++m) {
@@ -316,7 +347,7 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd(LearnedArgs a) {
         float y_next = 0.0f;
         if (more) {
             cw.next();
-            s_fetch_rows<STORE>(a, acq, u0f, v, cw.c, jj, valid, offr, x0, x1, ph);
+            s_fetch_rows<STORE, CUBIC>(a, acq, u0f, v, cw.c, jj, valid, offr, rows);
             if (j < width) y_next = S::load(ws, yrow + (size_t)(m + 1) * yplane + j);
         }
 #pragma unroll
@@ -331,7 +362,7 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd(LearnedArgs a) {
             for (int bb = 0; bb < 5; ++bb) r += q_tile[bb * kSP + j + bb];
             S::put(ws, yrow + (size_t)m * yplane + j, y_cur + r);
         }
-        if (more && stager) s_stage_pairs(sm.sp, col, x0, x1, ph);
+        if (more && stager) s_stage_pairs(sm.sp, col, rows);
         vmem_drain();
         y_cur = y_next;
         __syncthreads();
@@ -369,29 +400,18 @@ static_assert(kRingMaxP >= 2048, "ring tile and offset table fit the LDS of a wo
 // Row p of S at the thread's staged column (local column jj): the two
 // detector samples and the interpolation fraction (zero outside the row and
 // for columns outside [0, W), as s_fetch_rows).
-template <int STORE>
+template <int STORE, bool CUBIC>
 __device__ __forceinline__ void ring_fetch(const LearnedArgs& a, const float* o_tab, int v, int p, int jj,
-                                           bool valid, float& x0, float& x1, float& ph) {
-    using S = Store<STORE>;
-    using T = typename S::T;
-    constexpr int ES = (int)sizeof(T);
-    const float o = o_tab[p];
-    const float of = floorf(o);
-    ph = o - of;
-    const __amdgpu_buffer_rsrc_t rs = row_rsrc((const T*)a.filt + ((size_t)p * a.nv + v) * a.n, a.n);
-    const int off0 = valid ? ((int)of + jj) * ES : -4 * ES;
-    int off1 = off0 + ES;
-    asm volatile("" : "+v"(off1));   // two separately range-checked loads, never one wider load
-    x0 = S::raw(rs, off0);
-    x1 = S::raw(rs, off1);
+                                           bool valid, SRow<CUBIC>& r) {
+    srow_load<STORE, CUBIC>(a, v, p, o_tab[p], jj, valid, r);
 }
 
 // Stage the thread's column x of one row into ring slot `slot` (and its
 // mirror): the low half of pair x and the high half of pair x - 1.
-template <int PP>
-__device__ __forceinline__ void ring_stage(uint32_t* sp, int slot, int x, float x0, float x1, float ph) {
+template <int PP, bool CUBIC>
+__device__ __forceinline__ void ring_stage(uint32_t* sp, int slot, int x, const SRow<CUBIC>& r) {
     uint16_t* h = reinterpret_cast<uint16_t*>(sp);
-    const uint16_t val = f2bf(fmaf(ph, x1 - x0, x0));
+    const uint16_t val = f2bf(r.value());
     h[2 * (slot * PP + x)] = val;
     if (x > 0) h[2 * (slot * PP + x - 1) + 1] = val;
     if (slot < kRingMirror) {
@@ -400,7 +420,7 @@ __device__ __forceinline__ void ring_stage(uint32_t* sp, int slot, int x, float 
     }
 }
 
-template <int STORE, int PW>
+template <int STORE, int PW, bool CUBIC>
 __global__ __launch_bounds__(kThreads) void k_learned_fwd_ring(LearnedArgs a) {
     using S = Store<STORE>;
     using T = typename S::T;
@@ -431,16 +451,16 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd_ring(LearnedArgs a) {
     int pn = (a.p - (4 * d) % a.p) % a.p;      // p(0) = -4 d mod P
     __syncthreads();
     {
-        float x0[9], x1[9], ph[9];
+        SRow<CUBIC> rows[9];
 #pragma unroll
         for (int u = 0; u < 9; ++u) {
-            ring_fetch<STORE>(a, o_tab, v, pn, jj, valid, x0[u], x1[u], ph[u]);
+            ring_fetch<STORE, CUBIC>(a, o_tab, v, pn, jj, valid, rows[u]);
             pn += d;
             if (pn >= a.p) pn -= a.p;
         }
         if (stager) {
 #pragma unroll
-            for (int u = 0; u < 9; ++u) ring_stage<PP>(sm.sp, u, x, x0[u], x1[u], ph[u]);
+            for (int u = 0; u < 9; ++u) ring_stage<PP, CUBIC>(sm.sp, u, x, rows[u]);
         }
         vmem_drain();
     }
@@ -448,12 +468,12 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd_ring(LearnedArgs a) {
     __syncthreads();
     for (int m = 0; m < a.pd; ++m) {
         const bool more = m + 1 < a.pd;
-        float x0[4], x1[4], ph[4];
+        SRow<CUBIC> rows[4];
         float y_next = 0.0f;
         if (more) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                ring_fetch<STORE>(a, o_tab, v, pn, jj, valid, x0[k], x1[k], ph[k]);
+                ring_fetch<STORE, CUBIC>(a, o_tab, v, pn, jj, valid, rows[k]);
                 pn += d;
                 if (pn >= a.p) pn -= a.p;
             }
@@ -471,7 +491,7 @@ __global__ __launch_bounds__(kThreads) void k_learned_fwd_ring(LearnedArgs a) {
         }
         if (more && stager) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) ring_stage<PP>(sm.sp, (4 * m + 9 + k) & (kRing - 1), x, x0[k], x1[k], ph[k]);
+            for (int k = 0; k < 4; ++k) ring_stage<PP, CUBIC>(sm.sp, (4 * m + 9 + k) & (kRing - 1), x, rows[k]);
         }
         vmem_drain();
         __syncthreads();
@@ -511,7 +531,7 @@ struct BwdSmem {
     float dr[kDrLen];
 };
 
-template <int STORE>
+template <int STORE, bool CUBIC>
 __global__ __launch_bounds__(kThreads) void k_learned_bwd(LearnedArgs a) {
     // the task state, and after the last task the waves' partial gradients
     __shared__ union {
@@ -576,9 +596,9 @@ __global__ __launch_bounds__(kThreads) void k_learned_bwd(LearnedArgs a) {
         for (int t = 0; t < 9; ++t) offr[t] = __builtin_amdgcn_readfirstlane(sm.off_tab[t]);
         for (int m = 0; m < a.pd; ++m) {
             {
-                float x0[9], x1[9], ph[9];
-                s_fetch_rows<STORE>(a, acq, u0f, v, cw.c, jj, valid, offr, x0, x1, ph);
-                if (stager) s_stage_pairs(sm.sp, col, x0, x1, ph);
+                SRow<CUBIC> rows[9];
+                s_fetch_rows<STORE, CUBIC>(a, acq, u0f, v, cw.c, jj, valid, offr, rows);
+                if (stager) s_stage_pairs(sm.sp, col, rows);
                 cw.next();
             }
             if (col < width) {
@@ -909,32 +929,39 @@ __global__ void k_adamw(AdamArgs a) {
     a.w_bf16[i] = (uint16_t)f2bf(w);
 }
 
-template <int STORE>
+template <int STORE, bool CUBIC>
 void launch_fwd_ring(const LearnedArgs& a, int max_width, hipStream_t st) {
     const size_t dyn = sizeof(float) * (size_t)a.p;
     if (max_width <= 128)
-        hipLaunchKernelGGL((k_learned_fwd_ring<STORE, 128>), dim3(fwd_grid(a)), dim3(kThreads), dyn, st, a);
+        hipLaunchKernelGGL((k_learned_fwd_ring<STORE, 128, CUBIC>), dim3(fwd_grid(a)), dim3(kThreads), dyn, st, a);
     else if (max_width <= 224)
-        hipLaunchKernelGGL((k_learned_fwd_ring<STORE, 224>), dim3(fwd_grid(a)), dim3(kThreads), dyn, st, a);
+        hipLaunchKernelGGL((k_learned_fwd_ring<STORE, 224, CUBIC>), dim3(fwd_grid(a)), dim3(kThreads), dyn, st, a);
     else
-        hipLaunchKernelGGL((k_learned_fwd_ring<STORE, 256>), dim3(fwd_grid(a)), dim3(kThreads), dyn, st, a);
+        hipLaunchKernelGGL((k_learned_fwd_ring<STORE, 256, CUBIC>), dim3(fwd_grid(a)), dim3(kThreads), dyn, st, a);
+}
+
+template <bool CUBIC>
+void launch_fwd_store(const LearnedArgs& a, int max_width, bool ring, int store, hipStream_t st) {
+    if (ring) {
+        switch (store) {
+            case 0: launch_fwd_ring<0, CUBIC>(a, max_width, st); break;
+            case 1: launch_fwd_ring<1, CUBIC>(a, max_width, st); break;
+            default: launch_fwd_ring<2, CUBIC>(a, max_width, st); break;
+        }
+        return;
+    }
+    switch (store) {
+        case 0: hipLaunchKernelGGL((k_learned_fwd<0, CUBIC>), dim3(fwd_grid(a)), dim3(kThreads), 0, st, a); break;
+        case 1: hipLaunchKernelGGL((k_learned_fwd<1, CUBIC>), dim3(fwd_grid(a)), dim3(kThreads), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_learned_fwd<2, CUBIC>), dim3(fwd_grid(a)), dim3(kThreads), 0, st, a); break;
+    }
 }
 
 hipError_t launch_learned_fwd(const LearnedArgs& a, int max_width, int dfac, int store, hipStream_t st) {
     if (max_width > kLearnedMaxWidth) return hipErrorInvalidValue;
-    if (dfac >= 4 && a.p % dfac == 0 && a.pd * dfac == a.p && a.d * 4 == dfac && a.p <= kRingMaxP) {
-        switch (store) {
-            case 0: launch_fwd_ring<0>(a, max_width, st); break;
-            case 1: launch_fwd_ring<1>(a, max_width, st); break;
-            default: launch_fwd_ring<2>(a, max_width, st); break;
-        }
-        return hipGetLastError();
-    }
-    switch (store) {
-        case 0: hipLaunchKernelGGL(k_learned_fwd<0>, dim3(fwd_grid(a)), dim3(kThreads), 0, st, a); break;
-        case 1: hipLaunchKernelGGL(k_learned_fwd<1>, dim3(fwd_grid(a)), dim3(kThreads), 0, st, a); break;
-        default: hipLaunchKernelGGL(k_learned_fwd<2>, dim3(fwd_grid(a)), dim3(kThreads), 0, st, a); break;
-    }
+    const bool ring = dfac >= 4 && a.p % dfac == 0 && a.pd * dfac == a.p && a.d * 4 == dfac && a.p <= kRingMaxP;
+    if (a.cubic) launch_fwd_store<true>(a, max_width, ring, store, st);
+    else launch_fwd_store<false>(a, max_width, ring, store, st);
     return hipGetLastError();
 }
 
@@ -948,9 +975,18 @@ hipError_t launch_learned_bwd(const LearnedArgs& a, int store, hipStream_t st) {
     const unsigned ntot = fwd_grid(a);
     const dim3 grid(ntot < kBwdGrid ? ntot : kBwdGrid);
     switch (store) {
-        case 0: hipLaunchKernelGGL(k_learned_bwd<0>, grid, dim3(kThreads), 0, st, a); break;
-        case 1: hipLaunchKernelGGL(k_learned_bwd<1>, grid, dim3(kThreads), 0, st, a); break;
-        default: hipLaunchKernelGGL(k_learned_bwd<2>, grid, dim3(kThreads), 0, st, a); break;
+        case 0:
+            if (a.cubic) hipLaunchKernelGGL((k_learned_bwd<0, true>), grid, dim3(kThreads), 0, st, a);
+            else hipLaunchKernelGGL((k_learned_bwd<0, false>), grid, dim3(kThreads), 0, st, a);
+            break;
+        case 1:
+            if (a.cubic) hipLaunchKernelGGL((k_learned_bwd<1, true>), grid, dim3(kThreads), 0, st, a);
+            else hipLaunchKernelGGL((k_learned_bwd<1, false>), grid, dim3(kThreads), 0, st, a);
+            break;
+        default:
+            if (a.cubic) hipLaunchKernelGGL((k_learned_bwd<2, true>), grid, dim3(kThreads), 0, st, a);
+            else hipLaunchKernelGGL((k_learned_bwd<2, false>), grid, dim3(kThreads), 0, st, a);
+            break;
     }
     hipLaunchKernelGGL(k_grad_sum, dim3((kLearnedParams + 255) / 256), dim3(256), 0, st, a.partials,
                        (int)grid.x, a.grad);

@@ -112,26 +112,20 @@ def test_c2_sampled_slices_with_knobs():
 
 
 def test_learned_and_batch_reject_knobs():
-    """Batches keep to the paper's knobs.  The learned filter refuses the
-    cubic shift (it reads the linearly cropped rows) and takes the windowed
-    sinc as its base decimation: with zero weights it returns that
-    decimation exactly."""
+    """Batches keep to the paper's knobs.  The learned filter takes the
+    windowed sinc and the cubic shift: with zero weights it returns the
+    plan's plain decomposition exactly."""
     n, p, r = 64, 90, 256.0
     w = torch.zeros(pkg.LEARNED_PARAMS, dtype=torch.bfloat16, device=DEV)
     for knobs in (dict(decim="sinc", taps=4), dict(interp="cubic")):
         with pkg.Plan(n, p, r, s=2, **knobs) as plan:
-            if "interp" in knobs:
-                with pytest.raises(pkg.FdkodError) as ei:
-                    plan.learned_decompose(plan.empty_filtered(), plan.empty_workspace(), w)
-                assert ei.value.code == "E_UNSUPPORTED"
-            else:
-                filt = plan.empty_filtered().normal_(generator=torch.Generator(device=DEV).manual_seed(3))
-                ws_l, ws_t = plan.empty_workspace(), plan.empty_workspace()
-                plan.learned_decompose(filt, ws_l, w)
-                plan.decompose(filt, ws_t)
-                torch.cuda.synchronize()
-                e = plan.workspace_elems
-                assert torch.equal(ws_l.view(torch.float32)[:e], ws_t.view(torch.float32)[:e])
+            filt = plan.empty_filtered().normal_(generator=torch.Generator(device=DEV).manual_seed(3))
+            ws_l, ws_t = plan.empty_workspace(), plan.empty_workspace()
+            plan.learned_decompose(filt, ws_l, w)
+            plan.decompose(filt, ws_t)
+            torch.cuda.synchronize()
+            e = plan.workspace_elems
+            assert torch.equal(ws_l.view(torch.float32)[:e], ws_t.view(torch.float32)[:e])
         with pytest.raises(pkg.FdkodError) as ei:
             pkg.Batch([dict(n=n, p=p, r=r, s=2), dict(n=n, p=p, r=r, s=2, **knobs)])
         assert ei.value.code == "E_UNSUPPORTED"

@@ -67,14 +67,14 @@ def square_views(plan, buf):
     return out
 
 
-def oracle_subsinograms(proj, n, p, r, s, k, store=None):
+def oracle_subsinograms(proj, n, p, r, s, k, store=None, interp="linear"):
     """S_q[v, p, j] for every square (all rows), with the oracle's plan; the
     filtered rows are rounded to the storage type first when one is given."""
     sqs, betas, betas_dec = ofdkod.plan(n, p, r, s, k)
     frows = ofdk.filter_rows(proj.numpy().astype(np.float64), r, np.arange(n))
     if store is not None:
         frows.data = storage.ROUNDERS[store](frows.data)
-    subs = [np.moveaxis(ofdkod.crop_shift(frows, sq, betas, r, n), 0, 1) for sq in sqs]
+    subs = [np.moveaxis(ofdkod.crop_shift(frows, sq, betas, r, n, interp=interp), 0, 1) for sq in sqs]
     return sqs, betas_dec, frows, subs
 
 
@@ -128,24 +128,30 @@ def test_learned_forward_matches_oracle(case):
     plan.close()
 
 
+@pytest.mark.parametrize("knob", ["sinc", "cubic"])
 @pytest.mark.parametrize("case", [(40, 64, 160.0, 3, 0), (37, 50, 150.0, 3, 1)])
-def test_learned_forward_on_the_windowed_sinc(case):
+def test_learned_forward_on_the_knobs(case, knob):
     """With the windowed sinc (4 taps) as the plan's decimation the learned
-    filter adds the same correction R (it reads the linearly cropped S, not
-    the window): Y = Sinc + R against the oracle's sinc decimation and R."""
+    filter adds the same correction R (it reads the cropped S, which the
+    window does not change): Y = Sinc + R.  With the cubic shift S itself is
+    cropped by Keys' cubic convolution, in R as in the decimation:
+    Y = T(S_cubic) + R(S_cubic).  Both against the oracle."""
     n, p, r, s, k = case
     net = random_net(2)
     proj = scan(n, p, r, 6, 11 + n)
-    plan = pkg.Plan(n, p, r, s=s, skip=k, decim="sinc", taps=4)
+    knobs = dict(decim="sinc", taps=4) if knob == "sinc" else dict(interp="cubic")
+    plan = pkg.Plan(n, p, r, s=s, skip=k, **knobs)
     filt = plan.empty_filtered()
     plan.filter(proj.to(DEV), filt)
     ws_plain, ws_l = plan.empty_workspace(), plan.empty_workspace()
     plan.decompose(filt, ws_plain)
     plan.learned_decompose(filt, ws_l, device_weights(net))
     torch.cuda.synchronize()
-    sqs, betas_dec, _, subs = oracle_subsinograms(proj, n, p, r, s, k)
+    sqs, betas_dec, _, subs = oracle_subsinograms(proj, n, p, r, s, k,
+                                                  interp="cubic" if knob == "cubic" else "linear")
     d_factor = ofdkod.decimation_factor(s, k)
-    win = ofdkod.decimation_weights(p, len(betas_dec), "sinc", 4)
+    win = ofdkod.decimation_weights(p, len(betas_dec), "sinc", 4) if knob == "sinc" else \
+        ofdkod.triangle_weights(p, len(betas_dec))
     got_y = square_views(plan, _as(plan, ws_l))
     got_t = square_views(plan, _as(plan, ws_plain))
     errs_r, errs_y = [], []
@@ -156,7 +162,7 @@ def test_learned_forward_on_the_windowed_sinc(case):
         gt = got_t[q].numpy().transpose(1, 0, 2)
         errs_r.append(metrics.rel_rmse(gy - gt, r_or))
         errs_y.append(metrics.rel_rmse(gy, t_or + r_or))
-    log(f"learned on sinc {case}: R rel-RMSE max {max(errs_r):.2e}, Y rel-RMSE max {max(errs_y):.2e}")
+    log(f"learned on {knob} {case}: R rel-RMSE max {max(errs_r):.2e}, Y rel-RMSE max {max(errs_y):.2e}")
     assert max(errs_r) <= 1e-3 and max(errs_y) <= 1e-3
     plan.close()
 
@@ -429,6 +435,50 @@ def test_learned_gradient_matches_oracle(case):
     plan.close()
 
 
+def test_learned_gradient_with_the_cubic_shift():
+    """The weight gradient on a cubic-shift plan (S cropped by Keys' cubic
+    convolution) against the oracle's, with the bar set as for the linear
+    crop: 1e-3 or three times the change a 1e-6 relative perturbation of the
+    filtered rows makes in the oracle's gradient."""
+    n, p, r, s, k = 40, 64, 160.0, 3, 0
+    net = random_net(4)
+    proj = scan(n, p, r, 6, 11 + n)
+    plan = pkg.Plan(n, p, r, s=s, skip=k, interp="cubic")
+    filt = plan.empty_filtered()
+    plan.filter(proj.to(DEV), filt)
+    sqs, betas_dec, frows, subs = oracle_subsinograms(proj, n, p, r, s, k, interp="cubic")
+    _, betas, _ = ofdkod.plan(n, p, r, s, k)
+    rng = np.random.default_rng(12)
+    frows.data = frows.data * (1.0 + 1e-6 * rng.standard_normal(frows.data.shape))
+    subs_p = [np.moveaxis(ofdkod.crop_shift(frows, sq, betas, r, n, interp="cubic"), 0, 1) for sq in sqs]
+    d_factor = ofdkod.decimation_factor(s, k)
+    gen = torch.Generator().manual_seed(5)
+    dws = torch.zeros(plan.workspace_elems, dtype=torch.float32)
+    views = square_views(plan, dws)
+    for v in views:
+        v.copy_(torch.randn(v.shape, generator=gen))
+    grad = torch.zeros(pkg.LEARNED_PARAMS, dtype=torch.float32, device=DEV)
+    plan.learned_backward(filt, dws.to(DEV), device_weights(net), grad)
+    torch.cuda.synchronize()
+    got = unflat(grad.double().cpu().numpy())
+    ref = {key: np.zeros_like(val) for key, val in net.items()}
+    ref2 = {key: np.zeros_like(val) for key, val in net.items()}
+    for q in range(len(subs)):
+        d_r = views[q].double().numpy().transpose(1, 0, 2)
+        for out, sub in ((ref, subs[q]), (ref2, subs_p[q])):
+            _, cache = learned.forward(sub, net, d_factor, len(betas_dec), bf16=True)
+            g = learned.backward(sub, net, d_factor, len(betas_dec), d_r, cache, bf16=True)
+            for key in out:
+                out[key] += g[key]
+    for key in ("w1", "b1", "w2", "b2"):
+        err = metrics.rel_rmse(got[key], ref[key])
+        sens = metrics.rel_rmse(ref2[key], ref[key])
+        bar = max(1e-3, 3.0 * sens)
+        log(f"cubic gradient {key}: rel-RMSE {err:.2e} (perturbation {sens:.2e}, bar {bar:.2e})")
+        assert err <= bar, key
+    plan.close()
+
+
 # a close source (R = 100 for N = 64): a 16 x 16 x 32 block's detector footprint
 # is about 50 columns by 60 rows, wider than the adjoint's LDS tile, so its
 # direct path is exercised as well
@@ -593,9 +643,9 @@ def test_learned_rejects_unsupported_plans():
             plan.learned_decompose(filt, torch.empty(256, dtype=torch.uint8, device=DEV),
                                    device_weights(random_net(0)))
         assert ei.value.code == "E_UNSUPPORTED"
-    # the correction reads the linearly cropped rows of the detector: plans
-    # with the cubic shift or cone-corrected rows are refused
-    for knobs in (dict(interp="cubic"), dict(rows="cone")):
+    # the correction reads the cropped rows of the detector: plans with
+    # cone-corrected rows are refused
+    for knobs in (dict(rows="cone"),):
         with pkg.Plan(32, 48, 128.0, s=2, **knobs) as plan:
             filt, ws = plan.empty_filtered(), plan.empty_workspace()
             with pytest.raises(pkg.FdkodError) as ei:
