@@ -157,3 +157,19 @@ def test_choose_s_minimises_the_predicted_time():
     s_small, _ = pkg.choose_s(256, 360, 1024.0, costs=(c1, c2))
     s_large, _ = pkg.choose_s(2000, 720, 8000.0, costs=(c1, c2))
     assert s_large > s_small
+
+
+def test_batch_workloads_are_valid_plans():
+    """The benchmark's batched workloads (32 volumes of N = 128..512, 256 of
+    N = 32..64): every volume, with s from the cost model, passes the
+    library's validation, and the sizes follow the workload's seed."""
+    import bench
+    from synth import configs
+    for bw in (configs.C4, configs.C4S):
+        vols = bench.batch_volumes(bw, pkg)
+        assert len(vols) == bw.count
+        assert {v["n"] for v in vols} <= set(bw.sizes)
+        for v in vols:
+            assert v["p"] == round(bw.p_per_n * v["n"]) and v["r"] == bw.r_per_n * v["n"]
+            pkg.validate(**v)
+        assert vols == bench.batch_volumes(bw, pkg)
